@@ -1,0 +1,183 @@
+"""Seeded synthetic workloads for the FDTD path (stand-ins for the paper's
+DFT-derived Cu(111) and Au(111)-C6SAM systems of section 2.3).
+
+This module only *describes* inputs: grid shapes, units, atom lists drawn
+from seeded generators, packet parameters, CAP settings and run lengths.  It
+holds none of the method's arithmetic (no potential values, no packet values,
+no coefficients), so both the HIP library and the CPU oracle can consume the
+same inputs while sharing no computation.
+
+Units: ``ATOMIC`` uses hbar = m = 1 (bohr, hartree); ``EV_ANGSTROM`` uses eV,
+Angstrom and fs with hbar = 0.6582119569 eV fs and the electron mass
+m = hbar^2 / (7.619964 eV A^2).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import Optional, Tuple
+
+import numpy as np
+
+HBAR_EV_FS = 0.6582119569
+HBAR2_OVER_ME = 7.619964
+ME_EV_FS2_A2 = HBAR_EV_FS ** 2 / HBAR2_OVER_ME
+
+PERIODIC = 0
+ZERO = 1
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    hbar: float
+    mass: float
+    atoms: Optional[np.ndarray]          # [n][5] = x, y, z, Z, amplitude
+    soft: float = 0.1                    # softening length s
+    cutoff: float = 6.0
+    screened: bool = True
+    cap: Optional[Tuple[int, int, float]] = None   # (planes at bottom, planes at top, W_max)
+    r0: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    sigma: float = 1.0
+    energy: Optional[float] = None       # kinetic energy; wave vector along k_dir
+    k_dir: Tuple[float, float, float] = (0.0, 0.0, -1.0)
+    k0: Optional[Tuple[float, float, float]] = None  # explicit wave vector (overrides energy)
+    dt_frac: float = 0.9
+    steps: int = 100
+    k_det: int = 0
+    record_every: int = 0
+    bc: Tuple[int, int, int] = (PERIODIC, PERIODIC, PERIODIC)
+    precision: str = "f32"
+    kappa: float = 14.3996454784
+    a0: float = 0.529177210903
+    notes: str = ""
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def n_records(self, steps: Optional[int] = None) -> int:
+        s = self.steps if steps is None else steps
+        return (s // self.record_every + 1) if self.record_every > 0 else 0
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+def slab_atoms(seed: int, nsite_x: int, nsite_y: int, lx: float, ly: float, z_top: float,
+               n_layers: int = 3, layer_gap: float = 2.5, species=(6, 8, 14),
+               jitter: float = 0.05) -> np.ndarray:
+    """Square slab of ``n_layers`` layers of nsite_x x nsite_y sites, the
+    lattice stretched to lx/nsite_x so it stays periodic in the box; each site
+    gets a species drawn uniformly from ``species`` and an isotropic Gaussian
+    jitter of standard deviation ``jitter`` per coordinate."""
+    rng = np.random.default_rng(seed)
+    ax, ay = lx / nsite_x, ly / nsite_y
+    out = []
+    for layer in range(n_layers):
+        z = z_top - layer * layer_gap
+        for j in range(nsite_y):
+            for i in range(nsite_x):
+                out.append([(i + 0.5) * ax, (j + 0.5) * ay, z, 0.0, 1.0])
+    atoms = np.array(out, dtype=np.float64)
+    atoms[:, 3] = rng.choice(np.array(species, dtype=np.float64), size=atoms.shape[0])
+    atoms[:, 0:3] += rng.normal(0.0, jitter, size=(atoms.shape[0], 3))
+    return atoms
+
+
+def tile_atoms(atoms: np.ndarray, lx: float, ly: float, rx: int, ry: int) -> np.ndarray:
+    """Replicate an atom list rx x ry times in the xy plane."""
+    parts = []
+    for b in range(ry):
+        for a in range(rx):
+            t = atoms.copy()
+            t[:, 0] += a * lx
+            t[:, 1] += b * ly
+            parts.append(t)
+    return np.concatenate(parts, axis=0)
+
+
+def c1_free_gaussian() -> Workload:
+    """Free 3D Gaussian packet, atomic units, 64^3, dx = 0.2 bohr, periodic,
+    V = 0, sigma = 2 bohr, k0 = (0, 0, 1.5), dt = 0.5 x bound, 200 steps."""
+    return Workload(name="free-gaussian-64^3-fp64", nx=64, ny=64, nz=64, dx=0.2, dy=0.2,
+                    dz=0.2, hbar=1.0, mass=1.0, atoms=None, r0=(6.4, 6.4, 6.4), sigma=2.0,
+                    k0=(0.0, 0.0, 1.5), dt_frac=0.5, steps=200, k_det=48, record_every=10,
+                    precision="f64")
+
+
+def c2_surface(seed: int = 2401) -> Workload:
+    """Electron diffraction from a synthetic 3-layer slab: 256x256x512 grid,
+    dx = 0.2 A, Z in {6, 8, 14}, softening 0.1 A, 20x20 sites per layer
+    (2.56 A), jitter 0.05 A, 24-plane CAP at both z ends (W_max = 50 eV),
+    10 eV packet with sigma = 8 A at normal incidence, 20000 steps at
+    0.9 x bound, detection plane every 50 steps."""
+    L = 51.2
+    atoms = slab_atoms(seed, 20, 20, L, L, z_top=36.0)
+    return Workload(name="surface-256x256x512", nx=256, ny=256, nz=512, dx=0.2, dy=0.2,
+                    dz=0.2, hbar=HBAR_EV_FS, mass=ME_EV_FS2_A2, atoms=atoms,
+                    cap=(24, 24, 50.0), r0=(25.6, 25.6, 70.0), sigma=8.0, energy=10.0,
+                    dt_frac=0.9, steps=20000, k_det=250, record_every=50)
+
+
+def c2_reduced(seed: int = 2401) -> Workload:
+    """The surface-diffraction physics on a 64x64x128 box (12.8 x 12.8 x 25.6 A):
+    5x5 sites per layer, sigma = 2 A, 12-plane CAP, 2000 steps."""
+    L = 12.8
+    atoms = slab_atoms(seed, 5, 5, L, L, z_top=10.0)
+    return Workload(name="surface-64x64x128", nx=64, ny=64, nz=128, dx=0.2, dy=0.2, dz=0.2,
+                    hbar=HBAR_EV_FS, mass=ME_EV_FS2_A2, atoms=atoms, cap=(12, 12, 50.0),
+                    r0=(6.4, 6.4, 18.0), sigma=2.0, energy=10.0, dt_frac=0.9, steps=2000,
+                    k_det=70, record_every=20)
+
+
+def c3_headline(seed: int = 2401) -> Workload:
+    """Headline throughput run: 512x512x1024, FP32 state with FP64 reductions,
+    the surface slab tiled 2x2 in xy, 32-plane CAP, 10 eV packet, 10000 steps."""
+    base = slab_atoms(seed, 20, 20, 51.2, 51.2, z_top=36.0)
+    atoms = tile_atoms(base, 51.2, 51.2, 2, 2)
+    return Workload(name="surface-512x512x1024", nx=512, ny=512, nz=1024, dx=0.2, dy=0.2,
+                    dz=0.2, hbar=HBAR_EV_FS, mass=ME_EV_FS2_A2, atoms=atoms,
+                    cap=(32, 32, 50.0), r0=(51.2, 51.2, 70.0), sigma=8.0, energy=10.0,
+                    dt_frac=0.9, steps=10000, k_det=250, record_every=50)
+
+
+def ragged(precision: str = "f64", seed: int = 11) -> Workload:
+    """Odd, non-power-of-two box (37 x 29 x 53) that leaves ragged tiles in
+    every direction; a few atoms, a CAP and a packet."""
+    rng = np.random.default_rng(seed)
+    L = (37 * 0.2, 29 * 0.23, 53 * 0.21)
+    atoms = np.zeros((6, 5))
+    atoms[:, 0] = rng.uniform(0, L[0], 6)
+    atoms[:, 1] = rng.uniform(0, L[1], 6)
+    atoms[:, 2] = rng.uniform(3.0, 4.0, 6)
+    atoms[:, 3] = rng.choice([6.0, 8.0, 14.0], 6)
+    atoms[:, 4] = 1.0
+    return Workload(name="ragged-37x29x53", nx=37, ny=29, nz=53, dx=0.2, dy=0.23, dz=0.21,
+                    hbar=HBAR_EV_FS, mass=ME_EV_FS2_A2, atoms=atoms, cap=(6, 5, 40.0),
+                    r0=(3.7, 3.3, 7.5), sigma=1.2, energy=12.0, dt_frac=0.9, steps=300,
+                    k_det=20, record_every=7, precision=precision)
+
+
+def random_state(shape, seed: int):
+    """Seeded smooth-ish random initial arrays (for pins that need generic data)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape), rng.standard_normal(shape)
+
+
+ALL = {
+    "free-gaussian": c1_free_gaussian,
+    "surface": c2_surface,
+    "surface-reduced": c2_reduced,
+    "headline": c3_headline,
+    "ragged": ragged,
+}

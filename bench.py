@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Throughput of the FDTD leapfrog (arXiv 2401.07416, section 2.1) on one
+MI355X: Gcell-steps/s of the whole step (both half-steps with the fused
+detection records, FP64 flux and norm sums) on the 512x512x1024 synthetic
+surface-diffraction grid, FP32 state.  Prints one JSON line.
+
+A step is one pass of the hot path over the grid: the eq. (9) half-step, the
+eq. (8) half-step with the flux partials (and, every 50 steps, the record
+plane with Q, naive norm and plane sums), and the fixed-order FP64
+finalisation.  Inputs are resident in HBM before the timed region starts.
+
+roofline: the dominant kernel is the half-step kernel; its algorithmic bytes
+per launch are 16 B per cell in FP32 (read the stencil array, the updated
+array and V once, write the updated array once), divided by its average
+launch time measured with HIP events around each launch inside the timed
+region.  cpu_baseline: the FP64 oracle timed on this host's cores on a
+bounded slab of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FDTD Gcell-steps/s & %HBM roofline (FP32/FP64); batched & adjoint vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2000)
+    p.add_argument("--warmup", type=int, default=100)
+    p.add_argument("--workload", default="headline")
+    p.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    p.add_argument("--tile", default=None, help="rows,waves,zc (default: tuned table)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="target CPU time of the timed oracle sample")
+    p.add_argument("--cpu-planes", type=int, default=48)
+    p.add_argument("--no-timing", action="store_true",
+                   help="do not bracket launches with events (value only)")
+    return p.parse_args()
+
+
+def kernel_src_sha():
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "dispatch.hpp"):
+        with open(os.path.join(ROOT, "paper_2401_07416_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload_name, precision, cells):
+    """HBM bytes per launch of the half-step kernel from the committed PMC
+    summary, scaled by the copy-kernel calibration; null if the kernel
+    source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"half_step_{workload_name}_{precision}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_src_sha") != kernel_src_sha():
+        return None
+    return float(t["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(w, seconds, planes):
+    """Time the FP64 oracle on a slab of `planes` z-planes of the workload
+    (the windowed potential and packet of the full grid, zero outside the
+    slab) for about `seconds` of wall time, on the host threads the oracle
+    is given (at most 16, the CPU share of one GPU)."""
+    import numpy as np
+
+    import oracle
+    threads = min(16, len(os.sched_getaffinity(0)))
+    oracle.set_threads(threads)
+    g = oracle.Grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, bc=w.bc)
+    k0c = int(round(w.r0[2] / w.dz)) - planes // 2
+    size = (w.nx, w.ny, planes)
+    V = oracle.potential_window(g, w.atoms, (0, 0, k0c), size, soft=w.soft, cutoff=w.cutoff,
+                                kappa=w.kappa, a0=w.a0, screened=w.screened)
+    # time step of the full grid: the slab holds the deepest wells
+    Vs = oracle.potential_window(g, w.atoms, (0, 0, int(30.5 / w.dz) - 8), (w.nx, w.ny, 40),
+                                 soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
+                                 screened=w.screened)
+    gs = oracle.Grid(w.nx, w.ny, 40, w.dx, w.dy, w.dz, w.hbar, w.mass)
+    dt = w.dt_frac * w.hbar / oracle.emax(gs, Vs)
+    k0 = oracle.wavevector(w.energy, w.hbar, w.mass) * np.array(w.k_dir)
+    R, I = oracle.init_gaussian_window(g, w.r0, k0, w.sigma, dt, (0, 0, k0c), size)
+    gw = oracle.Grid(w.nx, w.ny, planes, w.dx, w.dy, w.dz, w.hbar, w.mass, bc=(0, 0, 1))
+    s = oracle.Sim(gw, V, R, I, dt, k_det=planes // 2)
+    t0 = time.perf_counter()
+    s.step(2)
+    per = (time.perf_counter() - t0) / 2
+    steps = max(2, int(seconds / per))
+    t0 = time.perf_counter()
+    s.step(steps)
+    el = time.perf_counter() - t0
+    threads = oracle.get_threads()
+    cells = w.nx * w.ny * planes
+    return {"value": cells * steps / el / 1e9, "unit": "Gcell-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"FP64 oracle, {w.nx}x{w.ny}x{planes}-plane slab of the {w.name} grid "
+                      f"around the packet, {steps} steps, {el:.1f} s",
+            "ns_per_cell_step": el / (cells * steps) * 1e9}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                                   "described in DESIGN.md but not implemented",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2401_07416_amd import tdse, tuning, workloads
+    w = workloads.ALL[a.workload]()
+    prec = a.precision
+    total = a.warmup + a.steps
+    sim = tdse.sim_from_workload(w, precision=prec, steps=total)
+    tile = tuple(int(x) for x in a.tile.split(",")) if a.tile else tuning.tile_for(w, prec)
+    if tile is not None:
+        sim.set_tile(*tile)
+    t = sim.get_tile()
+    torch.cuda.synchronize()
+    sim.step(a.warmup)
+    torch.cuda.synchronize()
+    sim.timing_read()
+    sim.set_timing(not a.no_timing)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record()
+    sim.step(a.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = e0.elapsed_time(e1)
+    sim.set_timing(False)
+    mi, ni, mr, nr = sim.timing_read()
+    det = sim.detect()
+    cells = w.cells
+    value = cells * a.steps / (ms * 1e-3) / 1e9
+    es = 8 if prec == "f64" else 4
+    alg_bytes = 4 * es * cells  # per half-step launch
+    roof = None
+    if ni and nr:
+        avg_i, avg_r = mi / ni, mr / nr
+        dom, avg = ("half_step eq.(8) real", avg_r) if mr >= mi else ("half_step eq.(9) imag", avg_i)
+        achieved = alg_bytes / (avg * 1e-3) / 1e9
+        traffic = traffic_from_profiles(w.name, prec, cells)
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg, 5),
+                "avg_launch_ms_imag": round(avg_i, 5), "avg_launch_ms_real": round(avg_r, 5),
+                "alg_bytes_per_launch": alg_bytes}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gcell-steps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms / a.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": f"{w.name} (FP32 state, FP64 sums)" if prec == "f32" else w.name,
+                   "grid": [w.nx, w.ny, w.nz], "cells": cells, "record_every": w.record_every,
+                   "k_det": w.k_det, "cap_planes": list(w.cap[:2]) if w.cap else None,
+                   "atoms": int(len(w.atoms)) if w.atoms is not None else 0,
+                   "tile": {"rows": t.rows, "waves": t.waves, "zc": t.zc, "vec": t.vec_elems,
+                            "groups": t.vec_groups, "lanes": t.lanes},
+                   "dt": det.dt, "records": det.n_records},
+        "roofline": roof,
+        "wall_s": round(wall, 3),
+        "hbm_bytes_per_cell_step_alg": 2 * 4 * es,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, a.cpu_planes)
+        out["cpu_baseline"]["speedup_gpu_over_cpu"] = round(value / out["cpu_baseline"]["value"], 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,267 @@
+/*
+ * libtdse: FDTD integration of the 3D time-dependent Schrodinger equation on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the staggered leapfrog of Nagaya, Omatsu and Packwood,
+ * arXiv 2401.07416, section 2.1:
+ *   eq. (2)   i hbar dpsi/dt = -(hbar^2/2m) lap psi + V psi
+ *   eq. (5)   psi = psiR + i psiI, psiR at integer and psiI at half-integer
+ *             time levels
+ *   eq. (9)   psiI^{n+1/2} = psiI^{n-1/2} + sum_d c_d delta_d^2 psiR^n
+ *                            - c_v V psiR^n
+ *   eq. (8)   psiR^{n+1}   = psiR^n - sum_d c_d delta_d^2 psiI^{n+1/2}
+ *                            + c_v V psiI^{n+1/2}
+ *             c_d = hbar dt / (2 m d^2), c_v = dt / hbar
+ *   eq. (10)  a complex absorbing potential near the z ends, here a
+ *             per-plane rate W_k >= 0 applied time-centred:
+ *             gamma = W_k dt / hbar, ca = (1 - gamma/2)/(1 + gamma/2),
+ *             cb = 1/(1 + gamma/2), U_new = ca U_old + cb (update term)
+ *   eqs. (13)-(14)  periodic wrap (i +- 1) mod N; a zero (Dirichlet)
+ *             boundary per axis is also offered
+ *   eq. (15)  detection-plane density rho = psiR^2 + psiI^2 on plane k_det,
+ *             stored every h steps starting at n = 0; the density at level n
+ *             is psiR^n^2 + psiI^{n-1/2}^2 (section 2.1)
+ *   eqs. (3)-(4)  Gaussian initial packet.
+ * Added to the paper's outputs, always accumulated in FP64:
+ *   Q   = dV sum[psiI^{n-1/2}^2 + psiR^{n-1} psiR^n]  (record 0:
+ *         dV sum[psiR^0^2 + psiI^{-1/2} psiI^{+1/2}]), the quadratic form the
+ *         leapfrog conserves exactly when W = 0;
+ *   naive norm = dV sum[psiR^n^2 + psiI^{n-1/2}^2];
+ *   flux through the face between planes k_det and k_det+1, accumulated
+ *         over steps: Phi^{n+1/2} = dV c_z sum_ij[I_{k+1}(R^n_k + R^{n+1}_k)
+ *         - I_k(R^n_{k+1} + R^{n+1}_{k+1})], I = psiI^{n+1/2}, k = k_det
+ *         (positive towards +z), the scheme's exact discrete current.
+ *
+ * Conventions for every call
+ *  - Status: every call returns tdse_status (0 = TDSE_OK); nothing aborts or
+ *    throws across this boundary.  tdse_last_error(h) keeps the message of
+ *    the last failure on a handle.
+ *  - Layout: every 3D array is [nz][ny][nx], x fastest, contiguous, in the
+ *    handle's precision (float for TDSE_F32, double for TDSE_F64), with a
+ *    base address aligned to 256 bytes.  Grid point (i, j, k) sits at
+ *    r = (i dx, j dy, k dz).
+ *  - Ownership: all large device memory belongs to the caller.  A handle
+ *    borrows the pointers passed to tdse_bind and never frees them.  Its
+ *    internal scratch lives in the caller's workspace (tdse_workspace_size).
+ *    Setup calls (tdse_build_potential) may allocate and free temporary
+ *    device memory before they return; the stepping calls allocate nothing.
+ *  - Streams: each handle launches on one HIP stream given at creation (NULL
+ *    = the null stream).  Launching calls are asynchronous.  Calls that
+ *    return host data synchronise that stream first.
+ *  - Threads: a handle is not thread-safe; distinct handles are independent.
+ *  - Units: the caller chooses them through hbar and mass (atomic units:
+ *    hbar = m = 1; eV-Angstrom-fs: hbar = 0.6582119569, m = hbar^2/7.619964).
+ *  - Supported x extents: nx = W * G * L with W in {1, 2, 4} (FP32) or
+ *    {1, 2} (FP64), G in {1, 2, 4, 8}, L <= 64 lanes; other nx return
+ *    TDSE_ERR_UNSUPPORTED from tdse_create.
+ */
+#ifndef TDSE_H
+#define TDSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tdse_status;
+
+enum {
+    TDSE_OK = 0,
+    TDSE_ERR_ARG = 1,         /* bad argument: null, size, alignment, range */
+    TDSE_ERR_STATE = 2,       /* call made out of order */
+    TDSE_ERR_UNSTABLE = 3,    /* dt above hbar / E_max without the override flag */
+    TDSE_ERR_NONFINITE = 4,   /* a NaN or Inf reached the FP64 sums */
+    TDSE_ERR_DEVICE = 5,      /* HIP runtime error; message kept */
+    TDSE_ERR_OOM = 6,         /* device allocation failed (setup temporaries) */
+    TDSE_ERR_UNSUPPORTED = 7, /* shape or option this build does not handle */
+    TDSE_ERR_CAPACITY = 8     /* the record buffer would overflow */
+};
+
+enum { TDSE_BC_PERIODIC = 0, TDSE_BC_ZERO = 1 };
+enum { TDSE_F32 = 0, TDSE_F64 = 1 };
+enum { TDSE_INIT_HALFSTEP = 0, TDSE_INIT_NAIVE = 1 };
+enum {
+    TDSE_FLAG_ALLOW_UNSTABLE = 1u, /* accept dt above the bound */
+    TDSE_FLAG_PIXEL_INTEGRAL = 2u  /* accumulate P_ij += h dt rho_ij (FP64) */
+};
+
+/* Problem description (section 2.1 grid, eq. (11) time step, eq. (15)
+ * detection).  dt > 0 is used as given; otherwise dt = dt_frac * hbar /
+ * E_max with E_max the Gershgorin bound of tdse_time_step_bound. */
+typedef struct tdse_desc {
+    int64_t nx, ny, nz;
+    double dx, dy, dz;
+    double hbar, mass;
+    double dt;
+    double dt_frac;
+    int32_t bc[3];          /* TDSE_BC_* per axis x, y, z */
+    int32_t precision;      /* TDSE_F32 or TDSE_F64 (state, V and records) */
+    int64_t k_det;          /* detection plane index, 0 <= k_det < nz */
+    int64_t record_every;   /* h >= 0; 0 = no records */
+    int64_t max_records;    /* capacity of the record buffers */
+    uint32_t flags;         /* TDSE_FLAG_* */
+    uint32_t reserved;
+} tdse_desc;
+
+/* One atom of the synthetic potential: position, nuclear charge, amplitude. */
+typedef struct tdse_atom {
+    double x, y, z, Z, amp;
+} tdse_atom;
+
+/* V(r) = sum_a amp_a v_Z(|r - X_a|) over atoms closer than cutoff, minimum
+ * image along periodic axes, with
+ *   v_Z(d) = -Z kappa exp(-d / lam_Z) / sqrt(d^2 + soft^2),
+ *   lam_Z = 0.8853 a0 Z^(-1/3) if screened, else no exponential. */
+typedef struct tdse_pot_params {
+    double soft, cutoff, kappa, a0;
+    int32_t screened;
+    int32_t reserved;
+} tdse_pot_params;
+
+/* Result of tdse_detect.  Pointers are the caller's own bound buffers. */
+typedef struct tdse_detect_out {
+    int64_t step;            /* global step counter n */
+    int64_t n_records;       /* records written so far (record 0 included) */
+    double flux_acc;         /* accumulated flux through face k_det + 1/2 */
+    double dt, e_max;
+    const void* records;     /* device [max_records][ny][nx], state precision */
+    const double* scalars;   /* device [max_records][4]: plane_sum, naive_norm, Q, flux_acc */
+    const double* pixel;     /* device [ny][nx] or NULL */
+} tdse_detect_out;
+
+typedef struct tdse_ctx* tdse_handle;
+
+/* Version of this interface. */
+int32_t tdse_abi_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char* tdse_status_string(tdse_status s);
+
+/* Last error message recorded on h ("" if none; static "" for NULL). */
+const char* tdse_last_error(tdse_handle h);
+
+/* Host-only check of a description: sizes > 0, spacings, hbar, mass > 0,
+ * boundary and precision codes, 0 <= k_det < nz, record settings, and
+ * dt or dt_frac > 0.  Touches no device. */
+tdse_status tdse_validate_desc(const tdse_desc* d);
+
+/* Host-only Gershgorin bound on max |E| of the discrete Hamiltonian of the
+ * section 2.1 scheme for a potential with range [vmin, vmax]:
+ *   E_max = max(|vmin|, |vmax + (hbar^2/2m) sum_d 4/d^2|)
+ * (a periodic axis of length 1 adds nothing), and dt_bound = hbar / E_max.
+ * The leapfrog is stable for dt < 2 hbar / max|E|, so dt_bound leaves at
+ * least a factor 2 of margin.  Either output pointer may be NULL. */
+tdse_status tdse_time_step_bound(const tdse_desc* d, double vmin, double vmax, double* e_max,
+                                 double* dt_bound);
+
+/* Bytes of device workspace a handle for d needs (host only). */
+tdse_status tdse_workspace_size(const tdse_desc* d, size_t* bytes);
+
+/* Create a handle on the current HIP device, launching on `stream` (a
+ * hipStream_t, NULL for the null stream).  Host memory only. */
+tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out);
+
+/* Destroy a handle (NULL is accepted).  Does not free bound memory. */
+tdse_status tdse_destroy(tdse_handle h);
+
+/* Attach caller device memory:
+ *   psi_r, psi_i, v : [nz][ny][nx] in the handle's precision;
+ *   workspace       : >= tdse_workspace_size bytes;
+ *   records         : [max_records][ny][nx] in the handle's precision, or
+ *                     NULL when record_every == 0;
+ *   scalars         : double [max_records][4], or NULL when
+ *                     record_every == 0;
+ *   pixel           : double [ny][nx] when TDSE_FLAG_PIXEL_INTEGRAL is set,
+ *                     else ignored.
+ * All pointers 256-byte aligned.  Rebinding resets the handle to the
+ * "potential not set" state. */
+tdse_status tdse_bind(tdse_handle h, void* psi_r, void* psi_i, void* v, void* workspace,
+                      size_t workspace_bytes, void* records, double* scalars, double* pixel);
+
+/* Fill the bound V with the atom-sum potential (setup; asynchronous on the
+ * handle's stream except for a short host sort).  atoms is host memory
+ * [n].  Alternatively the caller writes V itself and skips this call. */
+tdse_status tdse_build_potential(tdse_handle h, const tdse_atom* atoms, int64_t n,
+                                 const tdse_pot_params* p);
+
+/* CAP rates W[nz] >= 0 (host memory, energy units); NULL clears the CAP. */
+tdse_status tdse_set_cap(tdse_handle h, const double* w, int64_t nz);
+
+/* Quadratic CAP ramp (the shape of eq. (10)) over n_bottom planes at the
+ * bottom and n_top planes at the top of z:
+ *   W_k = w_max ((n_bottom - k)/n_bottom)^2 for k < n_bottom,
+ *   W_k = w_max ((k - (nz-1-n_top))/n_top)^2 for k >= nz - n_top. */
+tdse_status tdse_set_cap_quadratic(tdse_handle h, int64_t n_bottom, int64_t n_top, double w_max);
+
+/* Reduce min/max of V on the device, form E_max and dt, and build the
+ * per-plane coefficient tables.  Synchronises.  Returns TDSE_ERR_UNSTABLE
+ * if an absolute dt exceeds hbar / E_max and TDSE_FLAG_ALLOW_UNSTABLE is
+ * not set, TDSE_ERR_NONFINITE if V holds NaN or Inf.  Outputs may be NULL. */
+tdse_status tdse_finalize_setup(tdse_handle h, double* dt_out, double* e_max_out);
+
+/* Write the packet of eqs. (3)-(4) into the bound state, with k0 the wave
+ * vector (eq. (3) has k0 = -2 pi / lambda along z, eq. (4) for lambda) and
+ * sigma the amplitude width.  The periodic images |m| <= 2 are summed
+ * along periodic axes, and the state is scaled so dV sum |psi(r,0)|^2 = 1.
+ * TDSE_INIT_HALFSTEP: psiI^{-1/2} = Im psi(r, -dt/2) of the free-particle
+ * closed form; TDSE_INIT_NAIVE: psiI^{-1/2} = Im psi(r, 0).  Resets the
+ * step counter, the flux and the records, and writes record 0.  Requires
+ * tdse_finalize_setup. */
+tdse_status tdse_init_gaussian(tdse_handle h, const double r0[3], const double k0[3],
+                               double sigma, int32_t mode);
+
+/* Load a state (device pointers in the handle's precision, copied into the
+ * bound arrays unless they are the same) at global step `step`.  step == 0
+ * resets the flux and records and writes record 0.  step > 0 resumes: the
+ * records of earlier levels are taken to be in the bound buffers already
+ * and the flux accumulator is set to flux_acc. */
+tdse_status tdse_set_state(tdse_handle h, const void* psi_r, const void* psi_i, int64_t step,
+                           double flux_acc);
+
+/* Copy the state into caller device buffers (either may be NULL) and return
+ * the step counter and flux accumulator (either may be NULL).  Synchronises. */
+tdse_status tdse_get_state(tdse_handle h, void* psi_r, void* psi_i, int64_t* step,
+                           double* flux_acc);
+
+/* Advance n >= 0 steps (eq. (9) then eq. (8) per step) with the records,
+ * sums and flux fused in.  Asynchronous.  Returns TDSE_ERR_CAPACITY before
+ * launching anything if the records would overflow. */
+tdse_status tdse_step(tdse_handle h, int64_t n);
+
+/* Synchronise and report the counters and the caller's record buffers.
+ * Returns TDSE_ERR_NONFINITE if the flux or any record scalar is not
+ * finite. */
+tdse_status tdse_detect(tdse_handle h, tdse_detect_out* out);
+
+/* Copy the first n rows of the record scalars [n][4] to host memory.
+ * Synchronises. */
+tdse_status tdse_copy_scalars(tdse_handle h, double* host, int64_t n);
+
+/* Kernel timing for measurement: when enabled, each half-step launch is
+ * bracketed by HIP events on the handle's stream.  tdse_timing_read
+ * synchronises, returns the summed kernel milliseconds and launch counts of
+ * the imaginary (eq. (9)) and real (eq. (8)) half-steps since the last
+ * read, and clears them. */
+tdse_status tdse_set_timing(tdse_handle h, int32_t enable);
+tdse_status tdse_timing_read(tdse_handle h, double* ms_half_i, int64_t* n_half_i,
+                             double* ms_half_r, int64_t* n_half_r);
+
+/* Tile shape of the half-step kernels.  rows: y rows per wavefront (1, 2, 4
+ * or 8); waves: wavefronts per workgroup (1..4); zc: z planes per
+ * workgroup (>= 1).  tdse_create picks a default; tdse_set_tile checks and
+ * replaces it. */
+typedef struct tdse_tile {
+    int32_t rows, waves, zc;
+    int32_t vec_elems, vec_groups, lanes; /* read-only: x layout chosen by tdse_create */
+} tdse_tile;
+
+tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out);
+tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDSE_H */

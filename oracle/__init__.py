@@ -98,6 +98,12 @@ def lib():
         L.og_dvatom.restype = ctypes.c_double
         L.og_potential.argtypes = [gp, _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp]
+        L.og_potential_window.argtypes = [gp, _dp, ctypes.c_int64, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int] + [ctypes.c_int64] * 6 + [_dp]
+        L.og_init_gaussian_window.argtypes = [gp, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_int, ctypes.c_int] + \
+            [ctypes.c_int64] * 6 + [_dp, _dp]
         L.og_potential_points.argtypes = [gp, _dp, ctypes.c_int64, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_int, _dp, ctypes.c_int64, _dp]
@@ -202,6 +208,32 @@ def potential_points(grid: Grid, atoms: np.ndarray, pts: np.ndarray, soft=0.1, c
                               float(cutoff), float(kappa), float(a0), int(screened), _ptr(pts),
                               pts.shape[0], _ptr(out))
     return out
+
+
+def potential_window(grid: Grid, atoms: np.ndarray, origin, size, soft=0.1, cutoff=6.0,
+                     kappa=KAPPA_EV_A, a0=BOHR_A, screened=True) -> np.ndarray:
+    """V on the window of grid points ((i0+ii) mod nx, ...), shape [wnz][wny][wnx];
+    origin = (i0, j0, k0), size = (wnx, wny, wnz)."""
+    atoms = np.ascontiguousarray(atoms, dtype=np.float64).reshape(-1, 5)
+    out = np.zeros((int(size[2]), int(size[1]), int(size[0])))
+    lib().og_potential_window(grid.ref(), _ptr(atoms), atoms.shape[0], float(soft),
+                              float(cutoff), float(kappa), float(a0), int(screened),
+                              *[int(x) for x in origin], *[int(x) for x in size], _ptr(out))
+    return out
+
+
+def init_gaussian_window(grid: Grid, r0, k0, sigma, dt, origin, size, mode=INIT_HALFSTEP,
+                         nimg=2):
+    """init_gaussian restricted to a window (normalised over the whole grid)."""
+    shape = (int(size[2]), int(size[1]), int(size[0]))
+    R = np.zeros(shape)
+    I = np.zeros(shape)
+    r0 = np.ascontiguousarray(r0, dtype=np.float64)
+    k0 = np.ascontiguousarray(k0, dtype=np.float64)
+    lib().og_init_gaussian_window(grid.ref(), _ptr(r0), _ptr(k0), float(sigma), float(dt),
+                                  int(mode), int(nimg), *[int(x) for x in origin],
+                                  *[int(x) for x in size], _ptr(R), _ptr(I))
+    return R, I
 
 
 def gaussian_closed(grid: Grid, r0, k0, sigma, t, nimg=2):

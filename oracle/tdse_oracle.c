@@ -224,19 +224,45 @@ static double og_min_image(double u, double L) {
 }
 
 /* V(r) = sum_a amp_a v_{Z_a}(|r - X_a|) over atoms within the cutoff, in
- * atom order.  atoms is [n][5] = {x, y, z, Z, amp}.  Minimum image along
- * periodic axes. */
-void og_potential(const og_grid* g, const double* atoms, int64_t n, double soft, double cutoff,
-                  double kappa, double a0, int screened, double* V) {
+ * atom order, evaluated on a window of the grid: window cell (ii, jj, kk)
+ * is grid point ((i0+ii) mod nx, (j0+jj) mod ny, (k0+kk) mod nz) and out is
+ * [wnz][wny][wnx].  atoms is [n][5] = {x, y, z, Z, amp}.  Minimum image
+ * along periodic axes.  Per plane, atoms whose z distance alone reaches the
+ * cutoff are dropped, and per row those whose y distance does; they could
+ * not contribute, so the sum and its order are those of the plain
+ * definition. */
+void og_potential_window(const og_grid* g, const double* atoms, int64_t n, double soft,
+                         double cutoff, double kappa, double a0, int screened, int64_t i0,
+                         int64_t j0, int64_t k0, int64_t wnx, int64_t wny, int64_t wnz,
+                         double* out) {
     const double L[3] = {g->nx * g->dx, g->ny * g->dy, g->nz * g->dz};
-#pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < g->nz; ++k) {
-        for (int64_t j = 0; j < g->ny; ++j) {
-            for (int64_t i = 0; i < g->nx; ++i) {
-                const double r[3] = {i * g->dx, j * g->dy, k * g->dz};
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t kk = 0; kk < wnz; ++kk) {
+        const int64_t k = ((k0 + kk) % g->nz + g->nz) % g->nz;
+        const double rz = k * g->dz;
+        int64_t* cand = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+        int64_t* rowc = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+        int64_t nc = 0;
+        for (int64_t a = 0; a < n; ++a) {
+            double uz = rz - atoms[5 * a + 2];
+            if (g->bc[2] == OG_PERIODIC) uz = og_min_image(uz, L[2]);
+            if (fabs(uz) < cutoff) cand[nc++] = a;
+        }
+        for (int64_t jj = 0; jj < wny; ++jj) {
+            const int64_t j = ((j0 + jj) % g->ny + g->ny) % g->ny;
+            const double ry = j * g->dy;
+            int64_t nr = 0;
+            for (int64_t c = 0; c < nc; ++c) {
+                double uy = ry - atoms[5 * cand[c] + 1];
+                if (g->bc[1] == OG_PERIODIC) uy = og_min_image(uy, L[1]);
+                if (fabs(uy) < cutoff) rowc[nr++] = cand[c];
+            }
+            for (int64_t ii = 0; ii < wnx; ++ii) {
+                const int64_t i = ((i0 + ii) % g->nx + g->nx) % g->nx;
+                const double r[3] = {i * g->dx, ry, rz};
                 double v = 0.0;
-                for (int64_t a = 0; a < n; ++a) {
-                    const double* at = atoms + 5 * a;
+                for (int64_t c = 0; c < nr; ++c) {
+                    const double* at = atoms + 5 * rowc[c];
                     double u[3];
                     for (int d = 0; d < 3; ++d) {
                         u[d] = r[d] - at[d];
@@ -246,14 +272,22 @@ void og_potential(const og_grid* g, const double* atoms, int64_t n, double soft,
                     if (dist >= cutoff) continue;
                     v += at[4] * og_vatom(dist, at[3], soft, kappa, a0, screened);
                 }
-                V[og_idx(g, i, j, k)] = v;
+                out[(kk * wny + jj) * wnx + ii] = v;
             }
         }
+        free(cand);
+        free(rowc);
     }
 }
 
-/* Same potential at an explicit list of points pts[m][3] (for sampled checks
- * at sizes where the full grid is too large). */
+void og_potential(const og_grid* g, const double* atoms, int64_t n, double soft, double cutoff,
+                  double kappa, double a0, int screened, double* V) {
+    og_potential_window(g, atoms, n, soft, cutoff, kappa, a0, screened, 0, 0, 0, g->nx, g->ny,
+                        g->nz, V);
+}
+
+/* Same potential at an explicit list of points pts[m][3] (positions, not
+ * necessarily grid points), looping over every atom. */
 void og_potential_points(const og_grid* g, const double* atoms, int64_t n, double soft,
                          double cutoff, double kappa, double a0, int screened,
                          const double* pts, int64_t m, double* out) {
@@ -359,6 +393,56 @@ void og_init_gaussian(const og_grid* g, const double* r0, const double* k0, doub
         I[c] *= s;
     }
     free(tmp);
+}
+
+/* The initial state of og_init_gaussian evaluated only on a window of the
+ * grid (window cell (ii, jj, kk) is grid point ((i0+ii) mod nx, ...)), with
+ * the normalisation s summed over the whole grid exactly as there.  Used to
+ * check large grids on a few windows. */
+void og_init_gaussian_window(const og_grid* g, const double* r0, const double* k0, double sigma,
+                             double dt, int mode, int nimg, int64_t i0, int64_t j0, int64_t k0w,
+                             int64_t wnx, int64_t wny, int64_t wnz, double* psiR0,
+                             double* psiIh) {
+    double complex* f0[3];
+    double complex* fh[3];
+    const int64_t nd[3] = {g->nx, g->ny, g->nz};
+    const double dd[3] = {g->dx, g->dy, g->dz};
+    const double th = mode == OG_INIT_HALFSTEP ? -0.5 * dt : 0.0;
+    for (int d = 0; d < 3; ++d) {
+        f0[d] = malloc(sizeof(double complex) * nd[d]);
+        fh[d] = malloc(sizeof(double complex) * nd[d]);
+        for (int64_t i = 0; i < nd[d]; ++i) {
+            f0[d][i] = og_phi_axis(g, d, i * dd[d], r0[d], k0[d], sigma, 0.0, nimg);
+            fh[d][i] = og_phi_axis(g, d, i * dd[d], r0[d], k0[d], sigma, th, nimg);
+        }
+    }
+    double tot = 0.0;
+    for (int64_t k = 0; k < g->nz; ++k) {
+        double ps = 0.0;
+        for (int64_t j = 0; j < g->ny; ++j)
+            for (int64_t i = 0; i < g->nx; ++i) {
+                double complex p = f0[0][i] * f0[1][j] * f0[2][k];
+                ps += creal(p) * creal(p) + cimag(p) * cimag(p);
+            }
+        tot += ps;
+    }
+    const double s = 1.0 / sqrt(g->dx * g->dy * g->dz * tot);
+    for (int64_t kk = 0; kk < wnz; ++kk) {
+        const int64_t k = ((k0w + kk) % g->nz + g->nz) % g->nz;
+        for (int64_t jj = 0; jj < wny; ++jj) {
+            const int64_t j = ((j0 + jj) % g->ny + g->ny) % g->ny;
+            for (int64_t ii = 0; ii < wnx; ++ii) {
+                const int64_t i = ((i0 + ii) % g->nx + g->nx) % g->nx;
+                const int64_t c = (kk * wny + jj) * wnx + ii;
+                psiR0[c] = creal(f0[0][i] * f0[1][j] * f0[2][k]) * s;
+                psiIh[c] = cimag(fh[0][i] * fh[1][j] * fh[2][k]) * s;
+            }
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        free(f0[d]);
+        free(fh[d]);
+    }
 }
 
 /* ---------------------------------------------------------------------- */

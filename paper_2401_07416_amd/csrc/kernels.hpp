@@ -1,0 +1,280 @@
+// Device code of libtdse for gfx950 (CDNA4, wave64).
+//
+// Half-step kernels of the staggered leapfrog, arXiv 2401.07416 section 2.1:
+//   eq. (9): I <- ca_k I + cb_k ( L(R) - c_v V R )   (imaginary half-step)
+//   eq. (8): R <- ca_k R - cb_k ( L(I) - c_v V I )   (real half-step)
+// with L(X) = c_x dxx X + c_y dyy X + c_z dzz X (3-point second differences,
+// periodic wrap as in eqs. (13)-(14) or zero outside), and ca_k, cb_k the
+// time-centred damping of the per-plane absorbing rate (eq. (10)).
+//
+// Mapping.  Arrays are [nz][ny][nx], x fastest.  One wavefront owns a tile of
+// RY consecutive full x-rows and marches through a chunk of zc planes.  A row
+// of nx values is spread over the wave as G groups of W-element vectors:
+// lane l, group g, element e holds x = (g * nl + l) * W + e, so every vector
+// load instruction of a wave covers one contiguous run of nl * W * sizeof(T)
+// bytes.  z neighbours live in registers (planes k-1, k, k+1 of the stencil
+// array), y neighbours are the tile's own rows plus two halo rows, and the x
+// neighbours at vector edges come from the adjacent lane through a lane
+// permute, with the wrap across groups and across the row handled by which
+// value the edge lanes hand out.  Each of R, I and V is read from HBM about
+// once per half-step; the halo rows are re-read by the neighbouring tile and
+// the workgroup order keeps neighbouring tiles on one XCD so those re-reads
+// hit its L2.
+//
+// The real half-step also produces the FP64 partial sums of the detection
+// face flux (every step) and, on record steps, the detection-plane density,
+// the pixel integral and the partial sums of Q, the naive norm and the plane
+// density.  Every partial goes to its own slot (no atomics) and is reduced in
+// a fixed order by finalize_kernel, so results are bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tdse {
+
+enum Mode : int {
+    MODE_I = 0,       // eq. (9), store I
+    MODE_R = 1,       // eq. (8), store R, flux partials
+    MODE_R_REC = 2,   // eq. (8) + record: rho plane, Q, naive norm, pixel
+    MODE_I_PEEK = 3   // eq. (9) evaluated, not stored: record 0 (Q^0, rho^0)
+};
+
+template <typename T, int W>
+struct alignas(sizeof(T) * W) vec_t {
+    T v[W];
+};
+
+template <typename T>
+struct HalfArgs {
+    T* U;              // array updated in place (I for eq. (9), R for eq. (8))
+    const T* S;        // stencil array (R for eq. (9), I for eq. (8))
+    const T* V;
+    const T* ca;       // [nz]
+    const T* cb;       // [nz]
+    T cx, cy, cz, cv;
+    int nx, ny, nz, nl;
+    int ytiles, wpg, ywg, zc, nzc, nwg;
+    int bcx, bcy, bcz;  // 1 = zero boundary on that axis
+    int k_det, k_up;    // detection plane and the plane above it (-1: none)
+    double* flux_slots; // [2][ytiles] for this step
+    T* rec_plane;       // [ny][nx] record slot
+    double* part_q;     // [nzc][ytiles]
+    double* part_naive; // [nzc][ytiles]
+    double* part_plane; // [ytiles]
+    double* pixel;      // [ny][nx] or null
+    double pixel_w;     // h * dt
+};
+
+// Workgroup id -> logical tile index such that the workgroups the hardware
+// places on one XCD (ids congruent mod 8) get a contiguous range of logical
+// tiles, i.e. neighbouring y-tiles of the same z-chunk.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int q = n >> 3, rem = n & 7;
+    const int x = b & 7, r = b >> 3;
+    return (x < rem) ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T, int W>
+__device__ __forceinline__ vec_t<T, W> ldv(const T* p) {
+    return *reinterpret_cast<const vec_t<T, W>*>(p);
+}
+
+template <typename T, int W>
+__device__ __forceinline__ void stv(T* p, const vec_t<T, W>& x) {
+    *reinterpret_cast<vec_t<T, W>*>(p) = x;
+}
+
+template <typename T, int W, int G, int RY, int MODE>
+__global__ __launch_bounds__(256) void half_step_kernel(HalfArgs<T> a) {
+    using VT = vec_t<T, W>;
+    constexpr bool IS_R = (MODE == MODE_R || MODE == MODE_R_REC);
+    constexpr bool REC = (MODE == MODE_R_REC || MODE == MODE_I_PEEK);
+    const int lane = threadIdx.x;
+    const int L = xcd_remap(blockIdx.x, a.nwg);
+    const int zchunk = L / a.ywg;
+    const int ytile = (L - zchunk * a.ywg) * a.wpg + threadIdx.y;
+    if (ytile >= a.ytiles) return;  // whole wave leaves: no barriers below
+
+    const bool act = lane < a.nl;
+    const int lc = act ? lane : 0;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const long plane = (long)nx * ny;
+    const int j0 = ytile * RY;
+    const int k0 = zchunk * a.zc;
+    const int k1 = min(k0 + a.zc, nz);
+
+    // tile rows: real rows are stored; rows past ny are wrapped copies (or
+    // zero rows) that only serve as y neighbours
+    int jrow[RY];
+    bool real[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int jj = j0 + r;
+        real[r] = jj < ny;
+        jrow[r] = real[r] ? jj : (a.bcy ? -1 : jj % ny);
+    }
+    const int jlo = (j0 > 0) ? j0 - 1 : (a.bcy ? -1 : ny - 1);
+    const int jhi = (j0 + RY < ny) ? j0 + RY : (a.bcy ? -1 : (j0 + RY) % ny);
+
+    auto kwrap = [&](int kk) -> int {
+        if (kk < 0) return a.bcz ? -1 : kk + nz;
+        if (kk >= nz) return a.bcz ? -1 : kk - nz;
+        return kk;
+    };
+    auto load_row = [&](const T* base, int jj, int kk, VT(&out)[G]) {
+        if (jj < 0 || kk < 0) {
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int e = 0; e < W; ++e) out[g].v[e] = T(0);
+            return;
+        }
+        const T* p = base + (long)kk * plane + (long)jj * nx + (long)lc * W;
+#pragma unroll
+        for (int g = 0; g < G; ++g) out[g] = ldv<T, W>(p + (long)g * a.nl * W);
+    };
+
+    VT sp[RY][G], sc[RY][G], sn[RY][G];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        load_row(a.S, jrow[r], kwrap(k0 - 1), sp[r]);
+        load_row(a.S, jrow[r], k0, sc[r]);
+    }
+
+    double f0 = 0.0, f1 = 0.0, q = 0.0, nv = 0.0, pl = 0.0;
+    const int nl = a.nl;
+    const int src_l = (lane == 0) ? nl - 1 : lane - 1;
+    const int src_r = (lane == nl - 1) ? 0 : lane + 1;
+
+    for (int k = k0; k < k1; ++k) {
+        const int kn = kwrap(k + 1);
+        VT hl[G], hh[G], u[RY][G], vv[RY][G];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) load_row(a.S, jrow[r], kn, sn[r]);
+        load_row(a.S, jlo, k, hl);
+        load_row(a.S, jhi, k, hh);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            if (real[r]) {
+                load_row(a.U, jrow[r], k, u[r]);
+                load_row(a.V, jrow[r], k, vv[r]);
+            }
+        }
+        const T cak = a.ca[k];
+        const T cbk = a.cb[k];
+        const bool at_det = (k == a.k_det);
+        const bool at_up = (k == a.k_up);
+
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            if (!real[r]) continue;
+            VT un[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                // x neighbours across vector edges
+                const T give_l = (lane == nl - 1) ? sc[r][(g + G - 1) % G].v[W - 1] : sc[r][g].v[W - 1];
+                const T give_r = (lane == 0) ? sc[r][(g + 1) % G].v[0] : sc[r][g].v[0];
+                T xl_edge = __shfl(give_l, src_l, 64);
+                T xr_edge = __shfl(give_r, src_r, 64);
+                if (a.bcx) {
+                    if (lane == 0 && g == 0) xl_edge = T(0);
+                    if (lane == nl - 1 && g == G - 1) xr_edge = T(0);
+                }
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    const T c = sc[r][g].v[e];
+                    const T xl = (e > 0) ? sc[r][g].v[e - 1] : xl_edge;
+                    const T xr = (e < W - 1) ? sc[r][g].v[e + 1] : xr_edge;
+                    const T yl = (r > 0) ? sc[r - 1][g].v[e] : hl[g].v[e];
+                    const T yr = (r < RY - 1) ? sc[r + 1][g].v[e] : hh[g].v[e];
+                    const T zl = sp[r][g].v[e];
+                    const T zr = sn[r][g].v[e];
+                    const T lap = a.cx * ((xr - T(2) * c) + xl) + a.cy * ((yr - T(2) * c) + yl) +
+                                  a.cz * ((zr - T(2) * c) + zl);
+                    const T gt = lap - a.cv * vv[r][g].v[e] * c;
+                    const T uo = u[r][g].v[e];
+                    const T unew = IS_R ? (cak * uo - cbk * gt) : (cak * uo + cbk * gt);
+                    un[g].v[e] = unew;
+                    if (act) {
+                        if (IS_R) {
+                            if (at_det) f0 += (double)zr * ((double)uo + (double)unew);
+                            if (at_up) f1 += (double)zl * ((double)uo + (double)unew);
+                        }
+                        if (REC) {
+                            const double dc = (double)c, du = (double)uo, dn = (double)unew;
+                            q += dc * dc + du * dn;
+                            nv += IS_R ? (dn * dn + dc * dc) : (dc * dc + du * du);
+                        }
+                    }
+                }
+            }
+            if (act) {
+                const long off = (long)k * plane + (long)jrow[r] * nx + (long)lc * W;
+                if (MODE != MODE_I_PEEK) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) stv<T, W>(a.U + off + (long)g * nl * W, un[g]);
+                }
+                if (REC && at_det) {
+                    const long poff = (long)jrow[r] * nx + (long)lc * W;
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        VT rv;
+#pragma unroll
+                        for (int e = 0; e < W; ++e) {
+                            const double dc = (double)sc[r][g].v[e];
+                            const double dr = IS_R ? (double)un[g].v[e] : (double)u[r][g].v[e];
+                            const double rho = dr * dr + dc * dc;
+                            rv.v[e] = (T)rho;
+                            pl += rho;
+                            if (a.pixel) a.pixel[poff + (long)g * nl * W + e] += a.pixel_w * rho;
+                        }
+                        stv<T, W>(a.rec_plane + poff + (long)g * nl * W, rv);
+                    }
+                }
+            }
+        }
+        // rotate the z window
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                sp[r][g] = sc[r][g];
+                sc[r][g] = sn[r][g];
+            }
+    }
+
+    const bool has_det = (a.k_det >= k0 && a.k_det < k1);
+    const bool has_up = (a.k_up >= k0 && a.k_up < k1);
+    if (IS_R) {
+        if (has_det) {
+            const double s = wave_sum(f0);
+            if (lane == 0) a.flux_slots[ytile] = s;
+        }
+        if (has_up) {
+            const double s = wave_sum(f1);
+            if (lane == 0) a.flux_slots[a.ytiles + ytile] = s;
+        }
+    }
+    if (REC) {
+        const double sq = wave_sum(q);
+        const double sn_ = wave_sum(nv);
+        const long slot = (long)zchunk * a.ytiles + ytile;
+        if (lane == 0) {
+            a.part_q[slot] = sq;
+            a.part_naive[slot] = sn_;
+        }
+        if (has_det) {
+            const double sp_ = wave_sum(pl);
+            if (lane == 0) a.part_plane[ytile] = sp_;
+        }
+    }
+}
+
+}  // namespace tdse

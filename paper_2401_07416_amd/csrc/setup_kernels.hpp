@@ -1,0 +1,256 @@
+// Device code of libtdse outside the half-step kernels: the fixed-order
+// finalisation of the FP64 partial sums and the setup passes (potential,
+// Gaussian packet, min/max of V).  Included by the runtime only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace tdse {
+
+// Fixed-order FP64 sum over a workgroup of 256 threads.
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+struct FinArgs {
+    const double* flux_ring;  // [n_pending][2][ytiles]
+    int n_pending, ytiles, has_up, record;
+    long rec_idx;
+    double dv_cz, dV;
+    double* acc;              // acc[0] = accumulated flux
+    const double* part_q;
+    const double* part_naive;
+    long n_part;
+    const double* part_plane;
+    double* scalars;          // [max_records][4]
+};
+
+// Folds the pending per-step flux partials into the accumulator in step
+// order and, on record steps, writes {plane_sum, naive_norm, Q, flux_acc}.
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+    __shared__ double red[256];
+    const int t = threadIdx.x;
+    double acc = a.acc[0];
+    for (int s = 0; s < a.n_pending; ++s) {
+        const double* f = a.flux_ring + (long)s * 2 * a.ytiles;
+        double v = 0.0;
+        for (int i = t; i < a.ytiles; i += 256) v += f[i] - f[a.ytiles + i];
+        v = block_sum256(v, red);
+        if (a.has_up) acc += a.dv_cz * v;
+    }
+    if (a.record) {
+        double vq = 0.0, vn = 0.0, vp = 0.0;
+        for (long i = t; i < a.n_part; i += 256) {
+            vq += a.part_q[i];
+            vn += a.part_naive[i];
+        }
+        for (int i = t; i < a.ytiles; i += 256) vp += a.part_plane[i];
+        vq = block_sum256(vq, red);
+        vn = block_sum256(vn, red);
+        vp = block_sum256(vp, red);
+        if (t == 0) {
+            double* o = a.scalars + 4 * a.rec_idx;
+            o[0] = a.dV * vp;
+            o[1] = a.dV * vn;
+            o[2] = a.dV * vq;
+            o[3] = acc;
+        }
+    }
+    if (t == 0) a.acc[0] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Setup kernels
+// ---------------------------------------------------------------------------
+
+// Per-block min, max and non-finite count of V (FP64), for E_max.
+template <typename T>
+__global__ __launch_bounds__(256) void minmax_kernel(const T* V, long n, double* out) {
+    __shared__ double smin[256], smax[256], sbad[256];
+    const int t = threadIdx.x;
+    double mn = 1e308, mx = -1e308, bad = 0.0;
+    for (long i = (long)blockIdx.x * 256 + t; i < n; i += (long)gridDim.x * 256) {
+        const double v = (double)V[i];
+        if (!isfinite(v)) {
+            bad += 1.0;
+            continue;
+        }
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+    }
+    smin[t] = mn;
+    smax[t] = mx;
+    sbad[t] = bad;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            smin[t] = fmin(smin[t], smin[t + o]);
+            smax[t] = fmax(smax[t], smax[t + o]);
+            sbad[t] += sbad[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[3 * blockIdx.x + 0] = smin[0];
+        out[3 * blockIdx.x + 1] = smax[0];
+        out[3 * blockIdx.x + 2] = sbad[0];
+    }
+}
+
+struct PotArgs {
+    int nx, ny, nz;
+    double dx, dy, dz, Lx, Ly, Lz;
+    int bcx, bcy, bcz, screened;
+    const double* atoms;    // [n][5] in caller order
+    const int* plane_ptr;   // [nz + 1]
+    const int* plane_idx;   // candidate atoms per plane, ascending atom index
+    double soft, cutoff, kappa, a0;
+};
+
+__device__ __forceinline__ double min_image(double u, double L) { return u - L * rint(u / L); }
+
+// V(r) = sum_a amp_a v_Z(d_a) over the plane's candidate atoms in atom order,
+// v_Z(d) = -Z kappa exp(-d/lam_Z) / sqrt(d^2 + s^2), lam_Z = 0.8853 a0 Z^(-1/3).
+template <typename T>
+__global__ __launch_bounds__(256) void potential_kernel(PotArgs p, T* V) {
+    const int k = blockIdx.y;
+    const long c = (long)blockIdx.x * 256 + threadIdx.x;
+    const long nxy = (long)p.nx * p.ny;
+    if (c >= nxy) return;
+    const int i = (int)(c % p.nx), j = (int)(c / p.nx);
+    const double r0 = i * p.dx, r1 = j * p.dy, r2 = k * p.dz;
+    double v = 0.0;
+    for (int q = p.plane_ptr[k]; q < p.plane_ptr[k + 1]; ++q) {
+        const double* at = p.atoms + 5 * (long)p.plane_idx[q];
+        double u0 = r0 - at[0], u1 = r1 - at[1], u2 = r2 - at[2];
+        if (!p.bcx) u0 = min_image(u0, p.Lx);
+        if (!p.bcy) u1 = min_image(u1, p.Ly);
+        if (!p.bcz) u2 = min_image(u2, p.Lz);
+        const double d = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+        if (d >= p.cutoff) continue;
+        const double Z = at[3];
+        const double e = p.screened ? exp(-d / (0.8853 * p.a0 * pow(Z, -1.0 / 3.0))) : 1.0;
+        v += at[4] * (-Z * p.kappa * e / sqrt(d * d + p.soft * p.soft));
+    }
+    V[(long)k * nxy + c] = (T)v;
+}
+
+struct GaussAxisArgs {
+    int n[3];
+    double d[3], L[3], r0[3], k0[3];
+    int periodic[3];
+    double sigma, hbar, mass, t0, t1;
+    double* fac;  // [2 times][nx + ny + nz][2] complex
+};
+
+// One factor of eq. (3) evolved freely to time t (closed form), summed over
+// periodic images |m| <= 2:
+//   phi = (pi s^2)^(-1/4) (1 + i tau)^(-1/2)
+//         exp(-(x - x0 - v t)^2 / (2 s^2 (1 + i tau)) + i k (x - x0) - i hbar k^2 t / 2m)
+__device__ void gauss_phi(double x, double x0, double k, double s, double t, double hbar,
+                          double mass, double* re, double* im) {
+    const double tau = hbar * t / (mass * s * s);
+    const double v = hbar * k / mass;
+    const double u = x - x0 - v * t;
+    const double den = 2.0 * s * s * (1.0 + tau * tau);
+    const double are = -(u * u) / den;
+    const double aim = (u * u) * tau / den + k * (x - x0) - hbar * k * k * t / (2.0 * mass);
+    // (1 + i tau)^(-1/2) = (1 + tau^2)^(-1/4) exp(-i atan(tau) / 2)
+    const double mod = pow(1.0 + tau * tau, -0.25) * pow(M_PI * s * s, -0.25) * exp(are);
+    const double ph = aim - 0.5 * atan(tau);
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    *re = mod * cs;
+    *im = mod * sn;
+}
+
+__global__ __launch_bounds__(256) void gauss_axis_kernel(GaussAxisArgs a) {
+    const int tot = a.n[0] + a.n[1] + a.n[2];
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= 2 * tot) return;
+    const int which = idx / tot;
+    int m = idx % tot;
+    int ax = 0;
+    while (m >= a.n[ax]) {
+        m -= a.n[ax];
+        ++ax;
+    }
+    const double t = which ? a.t1 : a.t0;
+    const double x = m * a.d[ax];
+    double sre = 0.0, sim = 0.0;
+    const int ni = a.periodic[ax] ? 2 : 0;
+    for (int im = -ni; im <= ni; ++im) {
+        double re, imv;
+        gauss_phi(x + im * a.L[ax], a.r0[ax], a.k0[ax], a.sigma, t, a.hbar, a.mass, &re, &imv);
+        sre += re;
+        sim += imv;
+    }
+    a.fac[2 * idx] = sre;
+    a.fac[2 * idx + 1] = sim;
+}
+
+struct GaussCellArgs {
+    int nx, ny, nz;
+    const double* fac;  // as written by gauss_axis_kernel
+    double scale;
+    double* partial;    // [gridDim.x * gridDim.y] (norm pass)
+};
+
+__device__ __forceinline__ void cmul(double ar, double ai, double br, double bi, double* cr,
+                                     double* ci) {
+    *cr = ar * br - ai * bi;
+    *ci = ar * bi + ai * br;
+}
+
+__device__ __forceinline__ void psi_cell(const double* f, int nx, int ny, int i, int j, int k,
+                                         double* re, double* im) {
+    double r, m;
+    cmul(f[2 * i], f[2 * i + 1], f[2 * (nx + j)], f[2 * (nx + j) + 1], &r, &m);
+    cmul(r, m, f[2 * (nx + ny + k)], f[2 * (nx + ny + k) + 1], re, im);
+}
+
+// Per-block partial of sum |psi(r, 0)|^2.
+__global__ __launch_bounds__(256) void gauss_norm_kernel(GaussCellArgs a) {
+    __shared__ double red[256];
+    const int k = blockIdx.y;
+    const long c = (long)blockIdx.x * 256 + threadIdx.x;
+    const long nxy = (long)a.nx * a.ny;
+    double v = 0.0;
+    if (c < nxy) {
+        double re, im;
+        psi_cell(a.fac, a.nx, a.ny, (int)(c % a.nx), (int)(c / a.nx), k, &re, &im);
+        v = re * re + im * im;
+    }
+    v = block_sum256(v, red);
+    if (threadIdx.x == 0) a.partial[(long)k * gridDim.x + blockIdx.x] = v;
+}
+
+// R = s Re psi(r, t0), I = s Im psi(r, t1).
+template <typename T>
+__global__ __launch_bounds__(256) void gauss_write_kernel(GaussCellArgs a, T* R, T* I) {
+    const int k = blockIdx.y;
+    const long c = (long)blockIdx.x * 256 + threadIdx.x;
+    const long nxy = (long)a.nx * a.ny;
+    if (c >= nxy) return;
+    const int i = (int)(c % a.nx), j = (int)(c / a.nx);
+    double re0, im0, re1, im1;
+    psi_cell(a.fac, a.nx, a.ny, i, j, k, &re0, &im0);
+    const long off = (long)(a.nx + a.ny + a.nz);
+    psi_cell(a.fac + 2 * off, a.nx, a.ny, i, j, k, &re1, &im1);
+    R[(long)k * nxy + c] = (T)(a.scale * re0);
+    I[(long)k * nxy + c] = (T)(a.scale * im1);
+}
+
+}  // namespace tdse

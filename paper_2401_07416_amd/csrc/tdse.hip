@@ -1,0 +1,914 @@
+// libtdse runtime: the C ABI declared in include/tdse.h.
+//
+// The host side validates descriptions, carves the caller's workspace,
+// builds the coefficient tables, picks the x layout and tile shape of the
+// half-step kernels and drives the step loop on the handle's stream.  All
+// arithmetic of the method runs in the kernels of kernels.hpp.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/tdse.h"
+#include "kernels.hpp"
+#include "setup_kernels.hpp"
+
+using namespace tdse;
+
+struct tdse_ctx {
+    tdse_desc d;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // x layout and tile
+    int W = 1, G = 1, NL = 1;
+    int rows = 2, waves = 4, zc = 16;
+    // bound memory
+    void* R = nullptr;
+    void* I = nullptr;
+    void* V = nullptr;
+    void* ws = nullptr;
+    void* rec = nullptr;
+    double* scal = nullptr;
+    double* pix = nullptr;
+    size_t ws_bytes = 0;
+    // workspace carve
+    void* ca = nullptr;
+    void* cb = nullptr;
+    double* acc = nullptr;
+    double* flux_ring = nullptr;
+    double* part_q = nullptr;
+    double* part_naive = nullptr;
+    double* part_plane = nullptr;
+    double* red = nullptr;
+    double* gfac = nullptr;
+    int F = 1;
+    // state machine
+    bool bound = false, finalized = false, ready = false;
+    double dt = 0.0, emax = 0.0;
+    double c[4] = {0, 0, 0, 0};
+    std::vector<double> wcap;
+    std::vector<double> ca_h, cb_h;
+    std::vector<float> caf_h, cbf_h;
+    int64_t step = 0;
+    int pending = 0;
+    std::string err;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int RED_SLOTS = 3 * 4096;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t elem_size(const tdse_desc& d) { return d.precision == TDSE_F64 ? 8 : 4; }
+
+tdse_status fail(tdse_ctx* h, tdse_status s, const std::string& msg) {
+    if (h) h->err = msg;
+    return s;
+}
+
+tdse_status hip_check(tdse_ctx* h, hipError_t e, const char* what) {
+    if (e == hipSuccess) return TDSE_OK;
+    return fail(h, TDSE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, call)                                          \
+    do {                                                          \
+        tdse_status s_ = hip_check((h), (call), #call);           \
+        if (s_ != TDSE_OK) return s_;                             \
+    } while (0)
+
+struct Layout {
+    size_t ca, cb, acc, flux, part_q, part_n, part_p, red, gfac, total;
+    int F;
+};
+
+int flux_ring_steps(const tdse_desc& d) {
+    if (d.record_every > 0) return (int)std::min<int64_t>(d.record_every, 256);
+    return 256;
+}
+
+Layout layout_of(const tdse_desc& d) {
+    Layout L{};
+    const size_t es = elem_size(d);
+    const size_t nz = (size_t)d.nz, ny = (size_t)d.ny;
+    L.F = flux_ring_steps(d);
+    size_t o = 0;
+    L.ca = o; o = align_up(o + nz * es);
+    L.cb = o; o = align_up(o + nz * es);
+    L.acc = o; o = align_up(o + 8 * sizeof(double));
+    L.flux = o; o = align_up(o + (size_t)L.F * 2 * ny * sizeof(double));
+    // partial-sum slots: one per (z chunk, y tile) of any tile shape, and
+    // one per (256-cell block, plane) for the packet normalisation
+    const size_t nparts = std::max(ny * nz, ((size_t)d.nx * ny + 255) / 256 * nz);
+    L.part_q = o; o = align_up(o + nparts * sizeof(double));
+    L.part_n = o; o = align_up(o + nparts * sizeof(double));
+    L.part_p = o; o = align_up(o + ny * sizeof(double));
+    L.red = o; o = align_up(o + (size_t)RED_SLOTS * sizeof(double));
+    L.gfac = o; o = align_up(o + 2 * 2 * ((size_t)d.nx + ny + nz) * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+// nx = W * G * NL with NL <= 64 lanes; widest vectors first, fewest groups.
+bool choose_x_layout(const tdse_desc& d, int* W, int* G, int* NL) {
+    const int ws32[3] = {4, 2, 1};
+    const int ws64[2] = {2, 1};
+    const int* wl = d.precision == TDSE_F64 ? ws64 : ws32;
+    const int nw = d.precision == TDSE_F64 ? 2 : 3;
+    for (int a = 0; a < nw; ++a) {
+        const int w = wl[a];
+        if (d.nx % w) continue;
+        const int64_t m = d.nx / w;
+        for (int g : {1, 2, 4, 8}) {
+            if (m % g) continue;
+            if (m / g <= 64) {
+                *W = w;
+                *G = g;
+                *NL = (int)(m / g);
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
+void default_tile(tdse_ctx* h) {
+    const tdse_desc& d = h->d;
+    const int per_row = h->G * h->W * (d.precision == TDSE_F64 ? 2 : 1);  // VGPRs per row-plane
+    h->rows = per_row >= 8 ? 2 : 4;
+    if (h->rows > d.ny) h->rows = (d.ny >= 2) ? 2 : 1;
+    h->waves = 4;
+    const int ytiles = (int)((d.ny + h->rows - 1) / h->rows);
+    const int target_waves = 256 * 16;
+    int nzc = std::max(1, target_waves / std::max(1, ytiles));
+    int zc = (int)std::max<int64_t>(4, (d.nz + nzc - 1) / nzc);
+    h->zc = (int)std::min<int64_t>(zc, d.nz);
+}
+
+struct TileDims {
+    int ytiles, ywg, nzc, nwg;
+};
+
+TileDims tile_dims(const tdse_ctx* h, int rows, int waves, int zc) {
+    TileDims t;
+    t.ytiles = (int)((h->d.ny + rows - 1) / rows);
+    t.ywg = (t.ytiles + waves - 1) / waves;
+    t.nzc = (int)((h->d.nz + zc - 1) / zc);
+    t.nwg = t.ywg * t.nzc;
+    return t;
+}
+
+}  // namespace
+
+namespace tdse {
+// Half-step launchers, one translation unit per (precision, vector width)
+// so the many template instances compile in parallel (half_*.hip).
+hipError_t launch_half_f32_w4(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
+                              const HalfArgs<float>& a, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_half_f32_w2(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
+                              const HalfArgs<float>& a, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_half_f32_w1(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
+                              const HalfArgs<float>& a, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_half_f64_w2(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
+                              const HalfArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_half_f64_w1(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
+                              const HalfArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
+}  // namespace tdse
+
+namespace {
+
+hipError_t launch_half_f32(int w, int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
+                           const HalfArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
+    switch (w) {
+        case 4: return launch_half_f32_w4(g, rows, mode, grid, block, st, a, e0, e1);
+        case 2: return launch_half_f32_w2(g, rows, mode, grid, block, st, a, e0, e1);
+        default: return launch_half_f32_w1(g, rows, mode, grid, block, st, a, e0, e1);
+    }
+}
+
+hipError_t launch_half_f64(int w, int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
+                           const HalfArgs<double>& a, hipEvent_t e0, hipEvent_t e1) {
+    switch (w) {
+        case 2: return launch_half_f64_w2(g, rows, mode, grid, block, st, a, e0, e1);
+        default: return launch_half_f64_w1(g, rows, mode, grid, block, st, a, e0, e1);
+    }
+}
+
+// Fill a HalfArgs for one half-step.  mode selects the kernel; rec_idx is
+// the record slot for record modes; flux_slot the ring row for eq. (8).
+template <typename T>
+HalfArgs<T> make_args(tdse_ctx* h, int mode, int rows, int waves, int zc, long rec_idx,
+                      int flux_slot) {
+    const tdse_desc& d = h->d;
+    const TileDims td = tile_dims(h, rows, waves, zc);
+    HalfArgs<T> a;
+    const bool isR = (mode == MODE_R || mode == MODE_R_REC);
+    a.U = static_cast<T*>(isR ? h->R : h->I);
+    a.S = static_cast<const T*>(isR ? h->I : h->R);
+    a.V = static_cast<const T*>(h->V);
+    a.ca = static_cast<const T*>(h->ca);
+    a.cb = static_cast<const T*>(h->cb);
+    a.cx = (T)h->c[0];
+    a.cy = (T)h->c[1];
+    a.cz = (T)h->c[2];
+    a.cv = (T)h->c[3];
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    a.nl = h->NL;
+    a.ytiles = td.ytiles;
+    a.wpg = waves;
+    a.ywg = td.ywg;
+    a.zc = zc;
+    a.nzc = td.nzc;
+    a.nwg = td.nwg;
+    a.bcx = d.bc[0] == TDSE_BC_ZERO;
+    a.bcy = d.bc[1] == TDSE_BC_ZERO;
+    a.bcz = d.bc[2] == TDSE_BC_ZERO;
+    a.k_det = (int)d.k_det;
+    const bool has_up = !(a.bcz && d.k_det + 1 >= d.nz);
+    a.k_up = has_up ? (int)((d.k_det + 1) % d.nz) : -1;
+    a.flux_slots = h->flux_ring + (size_t)flux_slot * 2 * td.ytiles;
+    const size_t es = sizeof(T);
+    a.rec_plane = h->rec ? reinterpret_cast<T*>(static_cast<char*>(h->rec) +
+                                                (size_t)rec_idx * d.nx * d.ny * es)
+                         : nullptr;
+    a.part_q = h->part_q;
+    a.part_naive = h->part_naive;
+    a.part_plane = h->part_plane;
+    a.pixel = (d.flags & TDSE_FLAG_PIXEL_INTEGRAL) ? h->pix : nullptr;
+    a.pixel_w = (double)d.record_every * h->dt;
+    if (mode == MODE_I || mode == MODE_R) a.pixel = nullptr;
+    return a;
+}
+
+tdse_status launch_half(tdse_ctx* h, int mode, int rows, int waves, int zc, long rec_idx,
+                        int flux_slot) {
+    const TileDims td = tile_dims(h, rows, waves, zc);
+    dim3 grid(td.nwg), block(64, waves);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->timing && (mode == MODE_I || mode == MODE_R || mode == MODE_R_REC)) {
+        while (h->ev.size() < h->ev_used + 2) {
+            hipEvent_t e;
+            HIPCHK(h, hipEventCreate(&e));
+            h->ev.push_back(e);
+            h->ev_kind.push_back(0);
+        }
+        e0 = h->ev[h->ev_used];
+        e1 = h->ev[h->ev_used + 1];
+        h->ev_kind[h->ev_used] = (mode == MODE_I) ? 0 : 1;
+        h->ev_used += 2;
+    }
+    hipError_t e;
+    if (h->d.precision == TDSE_F64) {
+        HalfArgs<double> a = make_args<double>(h, mode, rows, waves, zc, rec_idx, flux_slot);
+        e = launch_half_f64(h->W, h->G, rows, mode, grid, block, h->stream, a, e0, e1);
+    } else {
+        HalfArgs<float> a = make_args<float>(h, mode, rows, waves, zc, rec_idx, flux_slot);
+        e = launch_half_f32(h->W, h->G, rows, mode, grid, block, h->stream, a, e0, e1);
+    }
+    return hip_check(h, e, "half-step launch");
+}
+
+tdse_status launch_finalize(tdse_ctx* h, int n_pending, bool record, long rec_idx, int rows,
+                            int waves, int zc) {
+    const tdse_desc& d = h->d;
+    const TileDims td = tile_dims(h, rows, waves, zc);
+    FinArgs a;
+    a.flux_ring = h->flux_ring;
+    a.n_pending = n_pending;
+    a.ytiles = td.ytiles;
+    a.has_up = !(d.bc[2] == TDSE_BC_ZERO && d.k_det + 1 >= d.nz);
+    a.record = record ? 1 : 0;
+    a.rec_idx = rec_idx;
+    a.dV = d.dx * d.dy * d.dz;
+    a.dv_cz = a.dV * h->c[2];
+    a.acc = h->acc;
+    a.part_q = h->part_q;
+    a.part_naive = h->part_naive;
+    a.n_part = (long)td.nzc * td.ytiles;
+    a.part_plane = h->part_plane;
+    a.scalars = h->scal;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, h->stream, a);
+    return hip_check(h, hipGetLastError(), "finalize launch");
+}
+
+// Record 0 of a freshly set state: rho^0, Q^0 with a non-storing peek of
+// eq. (9), the naive norm; flux and record count reset.
+tdse_status begin_records(tdse_ctx* h) {
+    HIPCHK(h, hipMemsetAsync(h->acc, 0, 8 * sizeof(double), h->stream));
+    h->pending = 0;
+    if (h->d.record_every <= 0) return TDSE_OK;
+    if (h->d.flags & TDSE_FLAG_PIXEL_INTEGRAL) {
+        HIPCHK(h, hipMemsetAsync(h->pix, 0, (size_t)h->d.nx * h->d.ny * sizeof(double), h->stream));
+    }
+    tdse_status s = launch_half(h, MODE_I_PEEK, h->rows, h->waves, h->zc, 0, 0);
+    if (s != TDSE_OK) return s;
+    return launch_finalize(h, 0, true, 0, h->rows, h->waves, h->zc);
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % ALIGN) == 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int32_t tdse_abi_version(void) { return 1; }
+
+const char* tdse_status_string(tdse_status s) {
+    switch (s) {
+        case TDSE_OK: return "ok";
+        case TDSE_ERR_ARG: return "invalid argument";
+        case TDSE_ERR_STATE: return "call out of order";
+        case TDSE_ERR_UNSTABLE: return "time step above the stability bound";
+        case TDSE_ERR_NONFINITE: return "non-finite value in the FP64 sums";
+        case TDSE_ERR_DEVICE: return "HIP device error";
+        case TDSE_ERR_OOM: return "device allocation failed";
+        case TDSE_ERR_UNSUPPORTED: return "unsupported shape or option";
+        case TDSE_ERR_CAPACITY: return "record buffer too small";
+        default: return "unknown status";
+    }
+}
+
+const char* tdse_last_error(tdse_handle h) { return h ? h->err.c_str() : ""; }
+
+tdse_status tdse_validate_desc(const tdse_desc* d) {
+    if (!d) return TDSE_ERR_ARG;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return TDSE_ERR_ARG;
+    if (d->nx > (1 << 20) || d->ny > (1 << 20) || d->nz > (1 << 20)) return TDSE_ERR_ARG;
+    if ((double)d->nx * d->ny * d->nz > 9.0e18) return TDSE_ERR_ARG;
+    if (!(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0)) return TDSE_ERR_ARG;
+    if (!std::isfinite(d->dx) || !std::isfinite(d->dy) || !std::isfinite(d->dz)) return TDSE_ERR_ARG;
+    if (!(d->hbar > 0) || !(d->mass > 0) || !std::isfinite(d->hbar) || !std::isfinite(d->mass))
+        return TDSE_ERR_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (d->bc[a] != TDSE_BC_PERIODIC && d->bc[a] != TDSE_BC_ZERO) return TDSE_ERR_ARG;
+    if (d->precision != TDSE_F32 && d->precision != TDSE_F64) return TDSE_ERR_ARG;
+    if (d->k_det < 0 || d->k_det >= d->nz) return TDSE_ERR_ARG;
+    if (d->record_every < 0) return TDSE_ERR_ARG;
+    if (d->record_every > 0 && d->max_records < 1) return TDSE_ERR_ARG;
+    if (!(d->dt > 0) && !(d->dt_frac > 0)) return TDSE_ERR_ARG;
+    if (!std::isfinite(d->dt) || !std::isfinite(d->dt_frac)) return TDSE_ERR_ARG;
+    if (d->flags & ~(uint32_t)(TDSE_FLAG_ALLOW_UNSTABLE | TDSE_FLAG_PIXEL_INTEGRAL))
+        return TDSE_ERR_ARG;
+    return TDSE_OK;
+}
+
+tdse_status tdse_time_step_bound(const tdse_desc* d, double vmin, double vmax, double* e_max,
+                                 double* dt_bound) {
+    tdse_status s = tdse_validate_desc(d);
+    if (s != TDSE_OK) return s;
+    if (!std::isfinite(vmin) || !std::isfinite(vmax) || vmin > vmax) return TDSE_ERR_ARG;
+    const int64_t n[3] = {d->nx, d->ny, d->nz};
+    const double sp[3] = {d->dx, d->dy, d->dz};
+    double kin = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] == 1 && d->bc[a] == TDSE_BC_PERIODIC) continue;
+        kin += 4.0 / (sp[a] * sp[a]);
+    }
+    kin *= d->hbar * d->hbar / (2.0 * d->mass);
+    const double em = std::max(std::fabs(vmin), std::fabs(vmax + kin));
+    if (!(em > 0)) return TDSE_ERR_ARG;
+    if (e_max) *e_max = em;
+    if (dt_bound) *dt_bound = d->hbar / em;
+    return TDSE_OK;
+}
+
+tdse_status tdse_workspace_size(const tdse_desc* d, size_t* bytes) {
+    tdse_status s = tdse_validate_desc(d);
+    if (s != TDSE_OK) return s;
+    if (!bytes) return TDSE_ERR_ARG;
+    *bytes = layout_of(*d).total;
+    return TDSE_OK;
+}
+
+tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out) {
+    if (!out) return TDSE_ERR_ARG;
+    *out = nullptr;
+    tdse_status s = tdse_validate_desc(d);
+    if (s != TDSE_OK) return s;
+    int W, G, NL;
+    if (!choose_x_layout(*d, &W, &G, &NL)) return TDSE_ERR_UNSUPPORTED;
+    if (d->ny > (int64_t)1 << 24 || d->nz > 65535) return TDSE_ERR_UNSUPPORTED;
+    tdse_ctx* h = new (std::nothrow) tdse_ctx();
+    if (!h) return TDSE_ERR_OOM;
+    h->d = *d;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->W = W;
+    h->G = G;
+    h->NL = NL;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return TDSE_ERR_DEVICE;
+    }
+    default_tile(h);
+    h->wcap.assign((size_t)d->nz, 0.0);
+    *out = h;
+    return TDSE_OK;
+}
+
+tdse_status tdse_destroy(tdse_handle h) {
+    if (!h) return TDSE_OK;
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return TDSE_OK;
+}
+
+tdse_status tdse_bind(tdse_handle h, void* psi_r, void* psi_i, void* v, void* workspace,
+                      size_t workspace_bytes, void* records, double* scalars, double* pixel) {
+    if (!h) return TDSE_ERR_ARG;
+    const tdse_desc& d = h->d;
+    if (!psi_r || !psi_i || !v || !workspace) return fail(h, TDSE_ERR_ARG, "null pointer");
+    if (psi_r == psi_i || psi_r == v || psi_i == v) return fail(h, TDSE_ERR_ARG, "aliased arrays");
+    const Layout L = layout_of(d);
+    if (workspace_bytes < L.total) return fail(h, TDSE_ERR_ARG, "workspace too small");
+    if (d.record_every > 0 && (!records || !scalars))
+        return fail(h, TDSE_ERR_ARG, "records and scalars are required when record_every > 0");
+    if ((d.flags & TDSE_FLAG_PIXEL_INTEGRAL) && !pixel)
+        return fail(h, TDSE_ERR_ARG, "pixel buffer required by TDSE_FLAG_PIXEL_INTEGRAL");
+    for (const void* p : {(const void*)psi_r, (const void*)psi_i, (const void*)v, (const void*)workspace})
+        if (!aligned(p)) return fail(h, TDSE_ERR_ARG, "pointer not 256-byte aligned");
+    if (records && !aligned(records)) return fail(h, TDSE_ERR_ARG, "records not 256-byte aligned");
+    if (scalars && !aligned(scalars)) return fail(h, TDSE_ERR_ARG, "scalars not 256-byte aligned");
+    if ((d.flags & TDSE_FLAG_PIXEL_INTEGRAL) && !aligned(pixel))
+        return fail(h, TDSE_ERR_ARG, "pixel not 256-byte aligned");
+    h->R = psi_r;
+    h->I = psi_i;
+    h->V = v;
+    h->ws = workspace;
+    h->ws_bytes = workspace_bytes;
+    h->rec = records;
+    h->scal = scalars;
+    h->pix = pixel;
+    char* w = static_cast<char*>(workspace);
+    h->ca = w + L.ca;
+    h->cb = w + L.cb;
+    h->acc = reinterpret_cast<double*>(w + L.acc);
+    h->flux_ring = reinterpret_cast<double*>(w + L.flux);
+    h->part_q = reinterpret_cast<double*>(w + L.part_q);
+    h->part_naive = reinterpret_cast<double*>(w + L.part_n);
+    h->part_plane = reinterpret_cast<double*>(w + L.part_p);
+    h->red = reinterpret_cast<double*>(w + L.red);
+    h->gfac = reinterpret_cast<double*>(w + L.gfac);
+    h->F = L.F;
+    h->bound = true;
+    h->finalized = false;
+    h->ready = false;
+    h->step = 0;
+    h->pending = 0;
+    return TDSE_OK;
+}
+
+tdse_status tdse_build_potential(tdse_handle h, const tdse_atom* atoms, int64_t n,
+                                 const tdse_pot_params* p) {
+    if (!h || !p || n < 0 || (n > 0 && !atoms)) return TDSE_ERR_ARG;
+    if (!h->bound) return fail(h, TDSE_ERR_STATE, "bind before building the potential");
+    if (!(p->cutoff > 0) || !(p->soft >= 0) || !(p->kappa > 0) || !(p->a0 > 0))
+        return fail(h, TDSE_ERR_ARG, "bad potential parameters");
+    if (n > (int64_t)1 << 26) return fail(h, TDSE_ERR_ARG, "too many atoms");
+    const tdse_desc& d = h->d;
+    for (int64_t a = 0; a < n; ++a) {
+        const tdse_atom& t = atoms[a];
+        if (!std::isfinite(t.x) || !std::isfinite(t.y) || !std::isfinite(t.z) || !(t.Z > 0) ||
+            !std::isfinite(t.amp))
+            return fail(h, TDSE_ERR_ARG, "bad atom");
+    }
+    // per-plane candidate lists: atoms whose z distance (minimum image on a
+    // periodic z axis) is below the cutoff, in ascending atom order
+    const double Lz = d.nz * d.dz;
+    std::vector<int> ptr((size_t)d.nz + 1, 0);
+    std::vector<int> idx;
+    for (int64_t k = 0; k < d.nz; ++k) {
+        const double z = k * d.dz;
+        for (int64_t a = 0; a < n; ++a) {
+            double u = z - atoms[a].z;
+            if (d.bc[2] == TDSE_BC_PERIODIC) u -= Lz * std::nearbyint(u / Lz);
+            if (std::fabs(u) < p->cutoff) idx.push_back((int)a);
+        }
+        ptr[(size_t)k + 1] = (int)idx.size();
+    }
+    if (idx.empty()) idx.push_back(0);
+    double* d_atoms = nullptr;
+    int* d_ptr = nullptr;
+    int* d_idx = nullptr;
+    auto cleanup = [&]() {
+        if (d_atoms) (void)hipFree(d_atoms);
+        if (d_ptr) (void)hipFree(d_ptr);
+        if (d_idx) (void)hipFree(d_idx);
+    };
+    const size_t na = std::max<int64_t>(n, 1);
+    if (hipMalloc(&d_atoms, na * 5 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_ptr, ptr.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc(&d_idx, idx.size() * sizeof(int)) != hipSuccess) {
+        cleanup();
+        return fail(h, TDSE_ERR_OOM, "potential temporaries");
+    }
+    std::vector<double> flat(na * 5, 0.0);
+    for (int64_t a = 0; a < n; ++a) {
+        flat[5 * a + 0] = atoms[a].x;
+        flat[5 * a + 1] = atoms[a].y;
+        flat[5 * a + 2] = atoms[a].z;
+        flat[5 * a + 3] = atoms[a].Z;
+        flat[5 * a + 4] = atoms[a].amp;
+    }
+    hipError_t e = hipMemcpyAsync(d_atoms, flat.data(), flat.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice,
+                           h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_idx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice,
+                           h->stream);
+    PotArgs a;
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    a.dx = d.dx;
+    a.dy = d.dy;
+    a.dz = d.dz;
+    a.Lx = d.nx * d.dx;
+    a.Ly = d.ny * d.dy;
+    a.Lz = Lz;
+    a.bcx = d.bc[0] == TDSE_BC_ZERO;
+    a.bcy = d.bc[1] == TDSE_BC_ZERO;
+    a.bcz = d.bc[2] == TDSE_BC_ZERO;
+    a.screened = p->screened;
+    a.atoms = d_atoms;
+    a.plane_ptr = d_ptr;
+    a.plane_idx = d_idx;
+    a.soft = p->soft;
+    a.cutoff = p->cutoff;
+    a.kappa = p->kappa;
+    a.a0 = p->a0;
+    const long nxy = (long)d.nx * d.ny;
+    dim3 grid((unsigned)((nxy + 255) / 256), (unsigned)d.nz);
+    if (e == hipSuccess) {
+        if (d.precision == TDSE_F64)
+            hipLaunchKernelGGL(potential_kernel<double>, grid, dim3(256), 0, h->stream, a,
+                               static_cast<double*>(h->V));
+        else
+            hipLaunchKernelGGL(potential_kernel<float>, grid, dim3(256), 0, h->stream, a,
+                               static_cast<float*>(h->V));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    cleanup();
+    h->finalized = false;
+    h->ready = false;
+    return hip_check(h, e, "build_potential");
+}
+
+static tdse_status upload_tables(tdse_ctx* h) {
+    const tdse_desc& d = h->d;
+    const size_t nz = (size_t)d.nz;
+    h->ca_h.assign(nz, 1.0);
+    h->cb_h.assign(nz, 1.0);
+    for (size_t k = 0; k < nz; ++k) {
+        const double gam = h->wcap[k] * h->dt / d.hbar;
+        h->ca_h[k] = (1.0 - 0.5 * gam) / (1.0 + 0.5 * gam);
+        h->cb_h[k] = 1.0 / (1.0 + 0.5 * gam);
+    }
+    if (d.precision == TDSE_F64) {
+        HIPCHK(h, hipMemcpyAsync(h->ca, h->ca_h.data(), nz * 8, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->cb, h->cb_h.data(), nz * 8, hipMemcpyHostToDevice, h->stream));
+    } else {
+        h->caf_h.assign(h->ca_h.begin(), h->ca_h.end());
+        h->cbf_h.assign(h->cb_h.begin(), h->cb_h.end());
+        HIPCHK(h, hipMemcpyAsync(h->ca, h->caf_h.data(), nz * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->cb, h->cbf_h.data(), nz * 4, hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TDSE_OK;
+}
+
+tdse_status tdse_set_cap(tdse_handle h, const double* w, int64_t nz) {
+    if (!h) return TDSE_ERR_ARG;
+    if (nz != h->d.nz) return fail(h, TDSE_ERR_ARG, "CAP length must equal nz");
+    if (w) {
+        for (int64_t k = 0; k < nz; ++k)
+            if (!(w[k] >= 0) || !std::isfinite(w[k])) return fail(h, TDSE_ERR_ARG, "CAP rates must be finite and >= 0");
+        h->wcap.assign(w, w + nz);
+    } else {
+        h->wcap.assign((size_t)nz, 0.0);
+    }
+    if (h->finalized) {
+        tdse_status s = upload_tables(h);
+        if (s != TDSE_OK) return s;
+        h->ready = false;
+    }
+    return TDSE_OK;
+}
+
+tdse_status tdse_set_cap_quadratic(tdse_handle h, int64_t n_bottom, int64_t n_top, double w_max) {
+    if (!h) return TDSE_ERR_ARG;
+    const int64_t nz = h->d.nz;
+    if (n_bottom < 0 || n_top < 0 || n_bottom + n_top > nz || !(w_max >= 0) || !std::isfinite(w_max))
+        return fail(h, TDSE_ERR_ARG, "bad CAP ramp");
+    std::vector<double> w((size_t)nz, 0.0);
+    for (int64_t k = 0; k < n_bottom; ++k) {
+        const double t = (double)(n_bottom - k) / (double)n_bottom;
+        w[(size_t)k] += w_max * t * t;
+    }
+    for (int64_t k = nz - n_top; k < nz; ++k) {
+        const double t = (double)(k - (nz - 1 - n_top)) / (double)n_top;
+        w[(size_t)k] += w_max * t * t;
+    }
+    return tdse_set_cap(h, w.data(), nz);
+}
+
+tdse_status tdse_finalize_setup(tdse_handle h, double* dt_out, double* e_max_out) {
+    if (!h) return TDSE_ERR_ARG;
+    if (!h->bound) return fail(h, TDSE_ERR_STATE, "bind before finalize");
+    const tdse_desc& d = h->d;
+    const long n = (long)d.nx * d.ny * d.nz;
+    const int blocks = (int)std::min<long>(4096, (n + 255) / 256);
+    if (d.precision == TDSE_F64)
+        hipLaunchKernelGGL(minmax_kernel<double>, dim3(blocks), dim3(256), 0, h->stream,
+                           static_cast<const double*>(h->V), n, h->red);
+    else
+        hipLaunchKernelGGL(minmax_kernel<float>, dim3(blocks), dim3(256), 0, h->stream,
+                           static_cast<const float*>(h->V), n, h->red);
+    HIPCHK(h, hipGetLastError());
+    std::vector<double> part((size_t)3 * blocks);
+    HIPCHK(h, hipMemcpyAsync(part.data(), h->red, part.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    double vmin = 1e308, vmax = -1e308, bad = 0.0;
+    for (int b = 0; b < blocks; ++b) {
+        vmin = std::min(vmin, part[3 * b]);
+        vmax = std::max(vmax, part[3 * b + 1]);
+        bad += part[3 * b + 2];
+    }
+    if (bad > 0) return fail(h, TDSE_ERR_NONFINITE, "V holds NaN or Inf");
+    double em, bound;
+    tdse_status s = tdse_time_step_bound(&d, vmin, vmax, &em, &bound);
+    if (s != TDSE_OK) return fail(h, s, "time step bound");
+    double dt = d.dt > 0 ? d.dt : d.dt_frac * bound;
+    if (dt > bound * (1.0 + 1e-12) && !(d.flags & TDSE_FLAG_ALLOW_UNSTABLE))
+        return fail(h, TDSE_ERR_UNSTABLE, "dt exceeds hbar / E_max");
+    h->dt = dt;
+    h->emax = em;
+    h->c[0] = d.hbar * dt / (2.0 * d.mass * d.dx * d.dx);
+    h->c[1] = d.hbar * dt / (2.0 * d.mass * d.dy * d.dy);
+    h->c[2] = d.hbar * dt / (2.0 * d.mass * d.dz * d.dz);
+    h->c[3] = dt / d.hbar;
+    s = upload_tables(h);
+    if (s != TDSE_OK) return s;
+    h->finalized = true;
+    h->ready = false;
+    if (dt_out) *dt_out = dt;
+    if (e_max_out) *e_max_out = em;
+    return TDSE_OK;
+}
+
+tdse_status tdse_init_gaussian(tdse_handle h, const double r0[3], const double k0[3], double sigma,
+                               int32_t mode) {
+    if (!h || !r0 || !k0) return TDSE_ERR_ARG;
+    if (!h->finalized) return fail(h, TDSE_ERR_STATE, "finalize_setup before init_gaussian");
+    if (!(sigma > 0) || !std::isfinite(sigma)) return fail(h, TDSE_ERR_ARG, "sigma must be > 0");
+    if (mode != TDSE_INIT_HALFSTEP && mode != TDSE_INIT_NAIVE) return fail(h, TDSE_ERR_ARG, "bad mode");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(r0[a]) || !std::isfinite(k0[a])) return fail(h, TDSE_ERR_ARG, "non-finite packet");
+    const tdse_desc& d = h->d;
+    GaussAxisArgs ga;
+    ga.n[0] = (int)d.nx;
+    ga.n[1] = (int)d.ny;
+    ga.n[2] = (int)d.nz;
+    ga.d[0] = d.dx;
+    ga.d[1] = d.dy;
+    ga.d[2] = d.dz;
+    for (int a = 0; a < 3; ++a) {
+        ga.L[a] = ga.n[a] * ga.d[a];
+        ga.r0[a] = r0[a];
+        ga.k0[a] = k0[a];
+        ga.periodic[a] = d.bc[a] == TDSE_BC_PERIODIC;
+    }
+    ga.sigma = sigma;
+    ga.hbar = d.hbar;
+    ga.mass = d.mass;
+    ga.t0 = 0.0;
+    ga.t1 = (mode == TDSE_INIT_HALFSTEP) ? -0.5 * h->dt : 0.0;
+    ga.fac = h->gfac;
+    const int tot = 2 * (ga.n[0] + ga.n[1] + ga.n[2]);
+    hipLaunchKernelGGL(gauss_axis_kernel, dim3((tot + 255) / 256), dim3(256), 0, h->stream, ga);
+    HIPCHK(h, hipGetLastError());
+    const long nxy = (long)d.nx * d.ny;
+    const unsigned gx = (unsigned)((nxy + 255) / 256);
+    GaussCellArgs gc;
+    gc.nx = (int)d.nx;
+    gc.ny = (int)d.ny;
+    gc.nz = (int)d.nz;
+    gc.fac = h->gfac;
+    gc.scale = 1.0;
+    // norm partials: one per (block, plane); reuse part_q (>= ny*nz slots)
+    gc.partial = h->part_q;
+    hipLaunchKernelGGL(gauss_norm_kernel, dim3(gx, (unsigned)d.nz), dim3(256), 0, h->stream, gc);
+    HIPCHK(h, hipGetLastError());
+    std::vector<double> part((size_t)gx * d.nz);
+    HIPCHK(h, hipMemcpyAsync(part.data(), h->part_q, part.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    double tot_norm = 0.0;
+    for (double v : part) tot_norm += v;
+    const double dV = d.dx * d.dy * d.dz;
+    if (!(tot_norm > 0) || !std::isfinite(tot_norm)) return fail(h, TDSE_ERR_NONFINITE, "packet norm");
+    gc.scale = 1.0 / std::sqrt(dV * tot_norm);
+    if (d.precision == TDSE_F64)
+        hipLaunchKernelGGL(gauss_write_kernel<double>, dim3(gx, (unsigned)d.nz), dim3(256), 0,
+                           h->stream, gc, static_cast<double*>(h->R), static_cast<double*>(h->I));
+    else
+        hipLaunchKernelGGL(gauss_write_kernel<float>, dim3(gx, (unsigned)d.nz), dim3(256), 0,
+                           h->stream, gc, static_cast<float*>(h->R), static_cast<float*>(h->I));
+    HIPCHK(h, hipGetLastError());
+    h->step = 0;
+    tdse_status s = begin_records(h);
+    if (s != TDSE_OK) return s;
+    h->ready = true;
+    return TDSE_OK;
+}
+
+tdse_status tdse_set_state(tdse_handle h, const void* psi_r, const void* psi_i, int64_t step,
+                           double flux_acc) {
+    if (!h || !psi_r || !psi_i || step < 0 || !std::isfinite(flux_acc)) return TDSE_ERR_ARG;
+    if (!h->finalized) return fail(h, TDSE_ERR_STATE, "finalize_setup before set_state");
+    const tdse_desc& d = h->d;
+    const size_t bytes = (size_t)d.nx * d.ny * d.nz * elem_size(d);
+    if (psi_r != h->R)
+        HIPCHK(h, hipMemcpyAsync(h->R, psi_r, bytes, hipMemcpyDeviceToDevice, h->stream));
+    if (psi_i != h->I)
+        HIPCHK(h, hipMemcpyAsync(h->I, psi_i, bytes, hipMemcpyDeviceToDevice, h->stream));
+    h->step = step;
+    h->pending = 0;
+    if (step == 0) {
+        tdse_status s = begin_records(h);
+        if (s != TDSE_OK) return s;
+    } else {
+        if (d.record_every > 0 && step / d.record_every + 1 > d.max_records)
+            return fail(h, TDSE_ERR_CAPACITY, "records of the resumed run exceed the buffer");
+        double acc[8] = {flux_acc, 0, 0, 0, 0, 0, 0, 0};
+        HIPCHK(h, hipMemcpyAsync(h->acc, acc, sizeof(acc), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    h->ready = true;
+    return TDSE_OK;
+}
+
+tdse_status tdse_get_state(tdse_handle h, void* psi_r, void* psi_i, int64_t* step,
+                           double* flux_acc) {
+    if (!h) return TDSE_ERR_ARG;
+    if (!h->ready) return fail(h, TDSE_ERR_STATE, "no state");
+    const tdse_desc& d = h->d;
+    const size_t bytes = (size_t)d.nx * d.ny * d.nz * elem_size(d);
+    if (psi_r && psi_r != h->R)
+        HIPCHK(h, hipMemcpyAsync(psi_r, h->R, bytes, hipMemcpyDeviceToDevice, h->stream));
+    if (psi_i && psi_i != h->I)
+        HIPCHK(h, hipMemcpyAsync(psi_i, h->I, bytes, hipMemcpyDeviceToDevice, h->stream));
+    double acc = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&acc, h->acc, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (step) *step = h->step;
+    if (flux_acc) *flux_acc = acc;
+    return TDSE_OK;
+}
+
+tdse_status tdse_step(tdse_handle h, int64_t n) {
+    if (!h || n < 0) return TDSE_ERR_ARG;
+    if (!h->ready) return fail(h, TDSE_ERR_STATE, "no state: init_gaussian or set_state first");
+    const tdse_desc& d = h->d;
+    const int64_t hrec = d.record_every;
+    if (hrec > 0 && (h->step + n) / hrec + 1 > d.max_records)
+        return fail(h, TDSE_ERR_CAPACITY, "record buffer would overflow");
+    for (int64_t it = 0; it < n; ++it) {
+        const int64_t s = h->step;
+        const bool record = hrec > 0 && ((s + 1) % hrec == 0);
+        const long rec_idx = record ? (long)((s + 1) / hrec) : 0;
+        tdse_status st = launch_half(h, MODE_I, h->rows, h->waves, h->zc, 0, 0);
+        if (st != TDSE_OK) return st;
+        st = launch_half(h, record ? MODE_R_REC : MODE_R, h->rows, h->waves, h->zc, rec_idx,
+                         h->pending);
+        if (st != TDSE_OK) return st;
+        h->pending += 1;
+        h->step += 1;
+        if (record || h->pending == h->F) {
+            st = launch_finalize(h, h->pending, record, rec_idx, h->rows, h->waves, h->zc);
+            if (st != TDSE_OK) return st;
+            h->pending = 0;
+        }
+    }
+    if (h->pending > 0) {
+        tdse_status st = launch_finalize(h, h->pending, false, 0, h->rows, h->waves, h->zc);
+        if (st != TDSE_OK) return st;
+        h->pending = 0;
+    }
+    return TDSE_OK;
+}
+
+tdse_status tdse_detect(tdse_handle h, tdse_detect_out* out) {
+    if (!h || !out) return TDSE_ERR_ARG;
+    if (!h->ready) return fail(h, TDSE_ERR_STATE, "no state");
+    const tdse_desc& d = h->d;
+    double acc = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&acc, h->acc, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    const int64_t nrec = d.record_every > 0 ? h->step / d.record_every + 1 : 0;
+    std::vector<double> sc((size_t)nrec * 4);
+    if (nrec > 0)
+        HIPCHK(h, hipMemcpyAsync(sc.data(), h->scal, sc.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    out->step = h->step;
+    out->n_records = nrec;
+    out->flux_acc = acc;
+    out->dt = h->dt;
+    out->e_max = h->emax;
+    out->records = h->rec;
+    out->scalars = h->scal;
+    out->pixel = (d.flags & TDSE_FLAG_PIXEL_INTEGRAL) ? h->pix : nullptr;
+    if (!std::isfinite(acc)) return fail(h, TDSE_ERR_NONFINITE, "flux accumulator not finite");
+    for (double v : sc)
+        if (!std::isfinite(v)) return fail(h, TDSE_ERR_NONFINITE, "record scalar not finite");
+    return TDSE_OK;
+}
+
+tdse_status tdse_copy_scalars(tdse_handle h, double* host, int64_t n) {
+    if (!h || !host || n < 0) return TDSE_ERR_ARG;
+    if (n > h->d.max_records) return fail(h, TDSE_ERR_ARG, "n exceeds max_records");
+    if (n == 0) return TDSE_OK;
+    if (!h->scal) return fail(h, TDSE_ERR_STATE, "no record scalars bound");
+    HIPCHK(h, hipMemcpyAsync(host, h->scal, (size_t)n * 4 * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TDSE_OK;
+}
+
+tdse_status tdse_set_timing(tdse_handle h, int32_t enable) {
+    if (!h) return TDSE_ERR_ARG;
+    h->timing = enable != 0;
+    return TDSE_OK;
+}
+
+tdse_status tdse_timing_read(tdse_handle h, double* ms_i, int64_t* n_i, double* ms_r, int64_t* n_r) {
+    if (!h) return TDSE_ERR_ARG;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    double ti = 0.0, tr = 0.0;
+    int64_t ci = 0, cr = 0;
+    for (size_t e = 0; e + 1 < h->ev_used; e += 2) {
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, h->ev[e], h->ev[e + 1]));
+        if (h->ev_kind[e] == 0) {
+            ti += ms;
+            ++ci;
+        } else {
+            tr += ms;
+            ++cr;
+        }
+    }
+    h->ev_used = 0;
+    if (ms_i) *ms_i = ti;
+    if (n_i) *n_i = ci;
+    if (ms_r) *ms_r = tr;
+    if (n_r) *n_r = cr;
+    return TDSE_OK;
+}
+
+tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
+    if (!h || !out) return TDSE_ERR_ARG;
+    out->rows = h->rows;
+    out->waves = h->waves;
+    out->zc = h->zc;
+    out->vec_elems = h->W;
+    out->vec_groups = h->G;
+    out->lanes = h->NL;
+    return TDSE_OK;
+}
+
+tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
+    if (!h || !t) return TDSE_ERR_ARG;
+    if (t->rows != 1 && t->rows != 2 && t->rows != 4 && t->rows != 8)
+        return fail(h, TDSE_ERR_ARG, "rows must be 1, 2, 4 or 8");
+    if (t->waves < 1 || t->waves > 4) return fail(h, TDSE_ERR_ARG, "waves must be 1..4");
+    if (t->zc < 1) return fail(h, TDSE_ERR_ARG, "zc must be >= 1");
+    if (h->pending != 0) return fail(h, TDSE_ERR_STATE, "pending flux partials");
+    h->rows = t->rows;
+    h->waves = t->waves;
+    h->zc = (int)std::min<int64_t>(t->zc, h->d.nz);
+    return TDSE_OK;
+}
+
+}  // extern "C"

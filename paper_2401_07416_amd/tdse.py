@@ -1,0 +1,346 @@
+"""Python binding of libtdse (include/tdse.h) through ctypes.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libtdse.so``.  PyTorch provides the device memory (caller-owned tensors
+bound to a handle) and the stream (torch's current stream).  There is no CPU
+fallback: if the library is missing, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtdse.so")
+
+OK, ERR_ARG, ERR_STATE, ERR_UNSTABLE, ERR_NONFINITE, ERR_DEVICE, ERR_OOM, ERR_UNSUPPORTED, \
+    ERR_CAPACITY = range(9)
+BC_PERIODIC, BC_ZERO = 0, 1
+F32, F64 = 0, 1
+INIT_HALFSTEP, INIT_NAIVE = 0, 1
+FLAG_ALLOW_UNSTABLE, FLAG_PIXEL_INTEGRAL = 1, 2
+
+# every symbol include/tdse.h declares
+EXPORTS = [
+    "tdse_abi_version", "tdse_status_string", "tdse_last_error", "tdse_validate_desc",
+    "tdse_time_step_bound", "tdse_workspace_size", "tdse_create", "tdse_destroy", "tdse_bind",
+    "tdse_build_potential", "tdse_set_cap", "tdse_set_cap_quadratic", "tdse_finalize_setup",
+    "tdse_init_gaussian", "tdse_set_state", "tdse_get_state", "tdse_step", "tdse_detect",
+    "tdse_copy_scalars", "tdse_set_timing", "tdse_timing_read", "tdse_get_tile", "tdse_set_tile",
+]
+
+
+class TdseError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("hbar", ctypes.c_double), ("mass", ctypes.c_double),
+                ("dt", ctypes.c_double), ("dt_frac", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
+                ("k_det", ctypes.c_int64), ("record_every", ctypes.c_int64),
+                ("max_records", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Atom(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double), ("y", ctypes.c_double), ("z", ctypes.c_double),
+                ("Z", ctypes.c_double), ("amp", ctypes.c_double)]
+
+
+class PotParams(ctypes.Structure):
+    _fields_ = [("soft", ctypes.c_double), ("cutoff", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("a0", ctypes.c_double),
+                ("screened", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class DetectOut(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("n_records", ctypes.c_int64),
+                ("flux_acc", ctypes.c_double), ("dt", ctypes.c_double),
+                ("e_max", ctypes.c_double), ("records", ctypes.c_void_p),
+                ("scalars", ctypes.c_void_p), ("pixel", ctypes.c_void_p)]
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("waves", ctypes.c_int32), ("zc", ctypes.c_int32),
+                ("vec_elems", ctypes.c_int32), ("vec_groups", ctypes.c_int32),
+                ("lanes", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libtdse.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2401_07416_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "tdse_abi_version": (i32, []),
+        "tdse_status_string": (ctypes.c_char_p, [i32]),
+        "tdse_last_error": (ctypes.c_char_p, [vp]),
+        "tdse_validate_desc": (i32, [ctypes.POINTER(Desc)]),
+        "tdse_time_step_bound": (i32, [ctypes.POINTER(Desc), dbl, dbl, dp, dp]),
+        "tdse_workspace_size": (i32, [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)]),
+        "tdse_create": (i32, [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]),
+        "tdse_destroy": (i32, [vp]),
+        "tdse_bind": (i32, [vp, vp, vp, vp, vp, ctypes.c_size_t, vp, vp, vp]),
+        "tdse_build_potential": (i32, [vp, ctypes.POINTER(Atom), i64, ctypes.POINTER(PotParams)]),
+        "tdse_set_cap": (i32, [vp, dp, i64]),
+        "tdse_set_cap_quadratic": (i32, [vp, i64, i64, dbl]),
+        "tdse_finalize_setup": (i32, [vp, dp, dp]),
+        "tdse_init_gaussian": (i32, [vp, dp, dp, dbl, i32]),
+        "tdse_set_state": (i32, [vp, vp, vp, i64, dbl]),
+        "tdse_get_state": (i32, [vp, vp, vp, ctypes.POINTER(i64), dp]),
+        "tdse_step": (i32, [vp, i64]),
+        "tdse_detect": (i32, [vp, ctypes.POINTER(DetectOut)]),
+        "tdse_copy_scalars": (i32, [vp, dp, i64]),
+        "tdse_set_timing": (i32, [vp, i32]),
+        "tdse_timing_read": (i32, [vp, dp, ctypes.POINTER(i64), dp, ctypes.POINTER(i64)]),
+        "tdse_get_tile": (i32, [vp, ctypes.POINTER(Tile)]),
+        "tdse_set_tile": (i32, [vp, ctypes.POINTER(Tile)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def make_desc(nx, ny, nz, dx, dy, dz, hbar=1.0, mass=1.0, dt=0.0, dt_frac=0.9,
+              bc=(BC_PERIODIC,) * 3, precision="f32", k_det=0, record_every=0, max_records=0,
+              flags=0) -> Desc:
+    d = Desc()
+    d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
+    d.dx, d.dy, d.dz = float(dx), float(dy), float(dz)
+    d.hbar, d.mass = float(hbar), float(mass)
+    d.dt, d.dt_frac = float(dt), float(dt_frac)
+    d.bc = (ctypes.c_int32 * 3)(*[int(b) for b in bc])
+    d.precision = F64 if precision in ("f64", F64) else F32
+    d.k_det, d.record_every, d.max_records = int(k_det), int(record_every), int(max_records)
+    d.flags = int(flags)
+    return d
+
+
+def validate_desc(d: Desc) -> int:
+    return int(load().tdse_validate_desc(ctypes.byref(d)))
+
+
+def time_step_bound(d: Desc, vmin: float, vmax: float):
+    em, dtb = ctypes.c_double(), ctypes.c_double()
+    st = load().tdse_time_step_bound(ctypes.byref(d), float(vmin), float(vmax), ctypes.byref(em),
+                                     ctypes.byref(dtb))
+    if st != OK:
+        raise TdseError(st, status_string(st))
+    return em.value, dtb.value
+
+
+def workspace_size(d: Desc) -> int:
+    n = ctypes.c_size_t()
+    st = load().tdse_workspace_size(ctypes.byref(d), ctypes.byref(n))
+    if st != OK:
+        raise TdseError(st, status_string(st))
+    return int(n.value)
+
+
+def status_string(st: int) -> str:
+    return load().tdse_status_string(int(st)).decode()
+
+
+def wavevector(energy: float, hbar: float, mass: float) -> float:
+    """|k| for kinetic energy E (eq. (4): lambda = sqrt(2 hbar^2 pi^2 / (m E)))."""
+    return float(np.sqrt(2.0 * mass * energy) / hbar)
+
+
+@dataclass
+class Detect:
+    step: int
+    n_records: int
+    flux: float
+    dt: float
+    e_max: float
+
+
+class Sim:
+    """One FDTD simulation on the current CUDA (HIP) device.
+
+    Owns the torch tensors it binds: psi_r, psi_i, v ([nz][ny][nx]), the
+    workspace, the records [max_records][ny][nx], the FP64 record scalars
+    [max_records][4] and optionally the FP64 pixel integral [ny][nx]."""
+
+    def __init__(self, desc: Desc, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libtdse needs a HIP device")
+        self.torch = torch
+        self.lib = load()
+        self.desc = desc
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        dt = torch.float64 if desc.precision == F64 else torch.float32
+        self.dtype = dt
+        shape = (desc.nz, desc.ny, desc.nx)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream()
+            self.psi_r = torch.zeros(shape, dtype=dt, device=self.device)
+            self.psi_i = torch.zeros(shape, dtype=dt, device=self.device)
+            self.v = torch.zeros(shape, dtype=dt, device=self.device)
+            self.workspace = torch.zeros(workspace_size(desc), dtype=torch.uint8,
+                                         device=self.device)
+            nrec = max(int(desc.max_records), 1)
+            self.records = torch.zeros((nrec, desc.ny, desc.nx), dtype=dt, device=self.device)
+            self.scalars = torch.zeros((nrec, 4), dtype=torch.float64, device=self.device)
+            self.pixel = (torch.zeros((desc.ny, desc.nx), dtype=torch.float64, device=self.device)
+                          if desc.flags & FLAG_PIXEL_INTEGRAL else None)
+            h = ctypes.c_void_p()
+            self._check(self.lib.tdse_create(ctypes.byref(desc),
+                                             ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(h)), None)
+            self.h = h
+            self._check(self.lib.tdse_bind(
+                self.h, self.psi_r.data_ptr(), self.psi_i.data_ptr(), self.v.data_ptr(),
+                self.workspace.data_ptr(), self.workspace.numel(), self.records.data_ptr(),
+                self.scalars.data_ptr(), self.pixel.data_ptr() if self.pixel is not None else None))
+        self.dt = None
+        self.e_max = None
+
+    # -- plumbing --------------------------------------------------------
+    def _check(self, st, h="self"):
+        if st != OK:
+            handle = self.h if h == "self" else h
+            msg = self.lib.tdse_last_error(handle).decode() if handle else ""
+            raise TdseError(st, f"{status_string(st)}: {msg}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tdse_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup -------------------------------------------------------------
+    def build_potential(self, atoms: np.ndarray, soft=0.1, cutoff=6.0, kappa=14.3996454784,
+                        a0=0.529177210903, screened=True):
+        atoms = np.ascontiguousarray(atoms, dtype=np.float64).reshape(-1, 5)
+        arr = (Atom * max(len(atoms), 1))()
+        for i, a in enumerate(atoms):
+            arr[i] = Atom(*[float(x) for x in a])
+        p = PotParams(float(soft), float(cutoff), float(kappa), float(a0), int(bool(screened)), 0)
+        self._check(self.lib.tdse_build_potential(self.h, arr, len(atoms), ctypes.byref(p)))
+
+    def set_cap(self, w: Optional[np.ndarray]):
+        if w is None:
+            self._check(self.lib.tdse_set_cap(self.h, None, self.desc.nz))
+            return
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        self._check(self.lib.tdse_set_cap(
+            self.h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(w)))
+
+    def set_cap_quadratic(self, n_bottom: int, n_top: int, w_max: float):
+        self._check(self.lib.tdse_set_cap_quadratic(self.h, int(n_bottom), int(n_top),
+                                                    float(w_max)))
+
+    def finalize(self):
+        dt, em = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.tdse_finalize_setup(self.h, ctypes.byref(dt), ctypes.byref(em)))
+        self.dt, self.e_max = dt.value, em.value
+        return self.dt, self.e_max
+
+    def init_gaussian(self, r0, k0, sigma, mode=INIT_HALFSTEP):
+        r = (ctypes.c_double * 3)(*[float(x) for x in r0])
+        k = (ctypes.c_double * 3)(*[float(x) for x in k0])
+        self._check(self.lib.tdse_init_gaussian(self.h, r, k, float(sigma), int(mode)))
+
+    def set_state(self, psi_r, psi_i, step=0, flux=0.0):
+        t = self.torch
+        pr = psi_r.to(self.device, self.dtype).contiguous()
+        pi = psi_i.to(self.device, self.dtype).contiguous()
+        self._keep = (pr, pi)  # alive until the asynchronous copy has run
+        self._check(self.lib.tdse_set_state(self.h, pr.data_ptr(), pi.data_ptr(), int(step),
+                                            float(flux)))
+        t.cuda.current_stream(self.device).synchronize()
+
+    def get_state(self):
+        step, flux = ctypes.c_int64(), ctypes.c_double()
+        self._check(self.lib.tdse_get_state(self.h, None, None, ctypes.byref(step),
+                                            ctypes.byref(flux)))
+        return self.psi_r.clone(), self.psi_i.clone(), step.value, flux.value
+
+    # -- run -----------------------------------------------------------
+    def step(self, n: int):
+        self._check(self.lib.tdse_step(self.h, int(n)))
+
+    def detect(self) -> Detect:
+        o = DetectOut()
+        self._check(self.lib.tdse_detect(self.h, ctypes.byref(o)))
+        return Detect(int(o.step), int(o.n_records), float(o.flux_acc), float(o.dt),
+                      float(o.e_max))
+
+    def records_host(self):
+        d = self.detect()
+        n = d.n_records
+        return (self.records[:n].double().cpu().numpy(), self.scalars[:n].cpu().numpy())
+
+    # -- measurement / tuning ------------------------------------------------
+    def set_timing(self, on: bool):
+        self._check(self.lib.tdse_set_timing(self.h, int(bool(on))))
+
+    def timing_read(self):
+        mi, mr = ctypes.c_double(), ctypes.c_double()
+        ni, nr = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.tdse_timing_read(self.h, ctypes.byref(mi), ctypes.byref(ni),
+                                              ctypes.byref(mr), ctypes.byref(nr)))
+        return mi.value, ni.value, mr.value, nr.value
+
+    def get_tile(self) -> Tile:
+        t = Tile()
+        self._check(self.lib.tdse_get_tile(self.h, ctypes.byref(t)))
+        return t
+
+    def set_tile(self, rows: int, waves: int, zc: int):
+        t = Tile(int(rows), int(waves), int(zc), 0, 0, 0)
+        self._check(self.lib.tdse_set_tile(self.h, ctypes.byref(t)))
+
+
+def sim_from_workload(w, precision: Optional[str] = None, steps: Optional[int] = None,
+                      pixel=False, device=None, max_records: Optional[int] = None) -> Sim:
+    """Set up a simulation from a seeded workload description (potential on
+    the device, CAP, dt, Gaussian packet)."""
+    prec = precision or w.precision
+    nsteps = w.steps if steps is None else steps
+    nrec = w.n_records(nsteps) if max_records is None else max_records
+    d = make_desc(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, dt_frac=w.dt_frac,
+                  bc=w.bc, precision=prec, k_det=w.k_det, record_every=w.record_every,
+                  max_records=nrec, flags=FLAG_PIXEL_INTEGRAL if pixel else 0)
+    s = Sim(d, device=device)
+    if w.atoms is not None and len(w.atoms):
+        s.build_potential(w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
+                          screened=w.screened)
+    if w.cap is not None:
+        s.set_cap_quadratic(*w.cap)
+    s.finalize()
+    if w.k0 is not None:
+        k0 = w.k0
+    else:
+        kk = wavevector(w.energy, w.hbar, w.mass)
+        k0 = tuple(kk * c for c in w.k_dir)
+    s.init_gaussian(w.r0, k0, w.sigma)
+    return s

@@ -1,0 +1,62 @@
+"""Tile shapes of the half-step kernels chosen by measurement.
+
+``tune_table.json`` maps "<nx>x<ny>x<nz>:<precision>" to the (rows, waves, zc)
+tile a sweep on the MI355X found fastest for that grid.  Grids absent from
+the table run the library's default tile.  ``autotune`` re-measures a grid
+in place.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tune_table.json")
+
+
+def _key(nx, ny, nz, precision):
+    return f"{nx}x{ny}x{nz}:{precision}"
+
+
+def load_table() -> dict:
+    if not os.path.exists(TABLE):
+        return {}
+    with open(TABLE) as f:
+        return json.load(f)
+
+
+def tile_for(w, precision: str) -> Optional[Tuple[int, int, int]]:
+    t = load_table().get(_key(w.nx, w.ny, w.nz, precision))
+    return tuple(t["tile"]) if t else None
+
+
+def candidates(nz: int):
+    for rows in (1, 2, 4):
+        for waves in (1, 2, 4):
+            for zc in (8, 16, 32, 64, 128, 256):
+                if zc <= nz:
+                    yield (rows, waves, zc)
+
+
+def autotune(sim, steps: int = 20, reps: int = 3, cands=None):
+    """Time each candidate tile on a live simulation (the state advances;
+    use a scratch simulation).  Returns [(ms_per_step, tile)] sorted."""
+    import torch
+    res = []
+    for tile in (cands or candidates(sim.desc.nz)):
+        sim.set_tile(*tile)
+        sim.step(2)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sim.step(steps)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / steps)
+        res.append((best, tile))
+    res.sort()
+    return res

@@ -1,0 +1,101 @@
+"""Shared helpers of the GPU tests: the oracle side and the HIP side are each
+set up from the same seeded workload description, independently (each builds
+its own potential, CAP, time step and packet), and then compared."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_2401_07416_amd import tdse
+
+
+def oracle_grid(w):
+    return oracle.Grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, bc=w.bc)
+
+
+def wave_vector(w, k_of_energy):
+    if w.k0 is not None:
+        return np.array(w.k0, dtype=np.float64)
+    return k_of_energy(w.energy, w.hbar, w.mass) * np.array(w.k_dir, dtype=np.float64)
+
+
+def oracle_setup(w):
+    g = oracle_grid(w)
+    if w.atoms is not None and len(w.atoms):
+        V = oracle.potential(g, w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
+                             screened=w.screened)
+    else:
+        V = np.zeros(g.shape)
+    dt = w.dt_frac * g.hbar / oracle.emax(g, V)
+    W = oracle.cap_quadratic(w.nz, *w.cap) if w.cap is not None else None
+    k0 = wave_vector(w, oracle.wavevector)
+    R, I = oracle.init_gaussian(g, w.r0, k0, w.sigma, dt)
+    return g, V, W, dt, R, I
+
+
+def oracle_run(w, steps, pixel=False):
+    g, V, W, dt, R, I = oracle_setup(w)
+    s = oracle.Sim(g, V, R, I, dt, W=W, k_det=w.k_det, record_every=w.record_every,
+                   max_records=max(w.n_records(steps), 1), pixel=pixel)
+    if w.record_every > 0:
+        s.record0()
+    s.step(steps)
+    return s
+
+
+def gpu_run(w, steps, precision=None, tile=None, pixel=False, chunks=None):
+    s = tdse.sim_from_workload(w, precision=precision, steps=steps, pixel=pixel)
+    if tile is not None:
+        s.set_tile(*tile)
+    if chunks:
+        done = 0
+        for c in chunks:
+            s.step(c)
+            done += c
+        s.step(steps - done)
+    else:
+        s.step(steps)
+    return s
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def state_rel(gpu, ref):
+    a = np.concatenate([gpu.psi_r.double().cpu().numpy().ravel(),
+                        gpu.psi_i.double().cpu().numpy().ravel()])
+    b = np.concatenate([ref.R.ravel(), ref.I.ravel()])
+    return rel_l2(a, b)
+
+
+def compare(gpu, ref, tol_state, tol_rec, tol_scal, tol_flux):
+    """Element-by-element comparison of a GPU run against the oracle."""
+    d = gpu.detect()
+    assert d.step == ref.step_count
+    assert d.n_records == ref.n_records
+    e_state = state_rel(gpu, ref)
+    assert e_state <= tol_state, f"state rel L2 {e_state:.3e} > {tol_state:.1e}"
+    out = {"state": e_state}
+    if ref.n_records:
+        rho, sc = gpu.records_host()
+        rr, rs = ref.records()
+        e_rec = rel_l2(rho, rr)
+        assert e_rec <= tol_rec, f"records rel L2 {e_rec:.3e} > {tol_rec:.1e}"
+        for col, name in ((0, "plane_sum"), (1, "naive"), (2, "Q")):
+            e = float(np.max(np.abs(sc[:, col] - rs[:, col]) / np.maximum(np.abs(rs[:, col]),
+                                                                         1e-300)))
+            if name == "plane_sum":
+                e = float(np.max(np.abs(sc[:, col] - rs[:, col])) /
+                          max(np.max(np.abs(rs[:, col])), 1e-300))
+            assert e <= tol_scal, f"{name} rel {e:.3e} > {tol_scal:.1e}"
+            out[name] = e
+        out["records"] = e_rec
+        fe = float(np.max(np.abs(sc[:, 3] - rs[:, 3])))
+        assert fe <= tol_flux, f"record flux abs {fe:.3e} > {tol_flux:.1e}"
+    fe = abs(d.flux - ref.flux)
+    assert fe <= tol_flux, f"flux abs {fe:.3e} > {tol_flux:.1e}"
+    out["flux"] = fe
+    return out

@@ -1,0 +1,99 @@
+"""Host-side tests of the C ABI (no GPU): the library loads, exports every
+symbol include/tdse.h declares, and its host-only calls (description
+checks, the Gershgorin time-step bound, workspace sizing) behave."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_07416_amd import tdse
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tdse.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdse_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tdse.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(tdse.EXPORTS) == names
+
+
+def test_abi_version_and_status_strings():
+    L = tdse.load()
+    assert L.tdse_abi_version() >= 1
+    for s in range(9):
+        assert tdse.status_string(s)
+    assert tdse.status_string(99) == "unknown status"
+    assert L.tdse_last_error(None) == b""
+
+
+def base_desc(**kw):
+    args = dict(nx=32, ny=24, nz=40, dx=0.2, dy=0.25, dz=0.3, hbar=1.0, mass=1.0, dt_frac=0.9,
+                k_det=10, record_every=5, max_records=10)
+    args.update(kw)
+    return tdse.make_desc(**args)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-1), dict(dz=0.0), dict(dx=float("nan")), dict(hbar=0.0), dict(mass=-1.0),
+    dict(bc=(0, 2, 0)), dict(k_det=40), dict(k_det=-1), dict(record_every=-1),
+    dict(record_every=5, max_records=0), dict(dt=0.0, dt_frac=0.0), dict(flags=8),
+    dict(dt=float("inf")),
+])
+def test_validate_rejects(bad):
+    assert tdse.validate_desc(base_desc(**bad)) == tdse.ERR_ARG
+
+
+def test_validate_accepts():
+    assert tdse.validate_desc(base_desc()) == tdse.OK
+    assert tdse.validate_desc(base_desc(precision="f64", bc=(1, 1, 1))) == tdse.OK
+
+
+def test_time_step_bound_matches_oracle_gershgorin():
+    rng = np.random.default_rng(0)
+    for shape, sp, bc in [((4, 5, 6), (0.3, 0.25, 0.2), (0, 0, 0)),
+                          ((1, 1, 12), (0.3, 0.3, 0.2), (0, 0, 0)),
+                          ((1, 7, 3), (0.3, 0.21, 0.2), (1, 1, 0))]:
+        for scale in (0.0, 5.0, 500.0):
+            V = scale * rng.standard_normal(shape[::-1]) - scale
+            g = oracle.Grid(*shape, *sp, hbar=0.658, mass=0.0568, bc=bc)
+            d = tdse.make_desc(*shape, *sp, hbar=0.658, mass=0.0568, bc=bc)
+            em, dtb = tdse.time_step_bound(d, V.min(), V.max())
+            assert em == pytest.approx(oracle.emax(g, V), rel=1e-14)
+            assert dtb == pytest.approx(0.658 / em, rel=1e-14)
+    with pytest.raises(tdse.TdseError):
+        tdse.time_step_bound(base_desc(), 1.0, -1.0)
+
+
+def test_workspace_size_scales_and_is_aligned():
+    a = tdse.workspace_size(base_desc())
+    b = tdse.workspace_size(base_desc(nz=400))
+    assert a % 256 == 0 and b > a
+
+
+def test_create_rejects_unsupported_x_extent():
+    L = tdse.load()
+    h = ctypes.c_void_p()
+    d = base_desc(nx=67)  # prime > 64: cannot be spread over 64 lanes
+    assert L.tdse_create(ctypes.byref(d), None, ctypes.byref(h)) == tdse.ERR_UNSUPPORTED
+    d = base_desc(nx=37)
+    assert L.tdse_create(ctypes.byref(d), None, ctypes.byref(h)) in (tdse.OK, tdse.ERR_DEVICE)
+    if h.value:
+        assert L.tdse_destroy(h) == tdse.OK
+
+
+def test_wavevector_agrees_with_oracle_reading_of_eq4():
+    for E in (10.0, 15.0, 60.0):
+        assert tdse.wavevector(E, 0.6582119569, 0.0568563) == pytest.approx(
+            oracle.wavevector(E, 0.6582119569, 0.0568563), rel=1e-14)

@@ -586,3 +586,19 @@ def test_cap_profile_shape():
     assert np.all(W[8:35] == 0.0)
     assert np.all(np.diff(W[:8]) < 0) and np.all(np.diff(W[35:]) > 0)
     assert W[7] == pytest.approx(50.0 / 64) and W[35] == pytest.approx(50.0 / 25)
+
+
+def test_window_evaluations_equal_slices_of_full_grid():
+    from paper_2401_07416_amd import workloads
+    w = workloads.ragged()
+    g = oracle.Grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass)
+    V = oracle.potential(g, w.atoms)
+    origin, size = (30, -4, 45), (12, 9, 15)
+    idx = [np.arange(o, o + s) % n for o, s, n in zip(origin, size, (w.nx, w.ny, w.nz))]
+    sl = np.ix_(idx[2], idx[1], idx[0])
+    np.testing.assert_array_equal(oracle.potential_window(g, w.atoms, origin, size), V[sl])
+    k = oracle.wavevector(w.energy, w.hbar, w.mass)
+    R, I = oracle.init_gaussian(g, w.r0, [0, 0, -k], w.sigma, 1e-4)
+    Rw, Iw = oracle.init_gaussian_window(g, w.r0, [0, 0, -k], w.sigma, 1e-4, origin, size)
+    np.testing.assert_array_equal(Rw, R[sl])
+    np.testing.assert_array_equal(Iw, I[sl])

@@ -4,16 +4,16 @@ MI355X: Gcell-steps/s of the whole step (both half-steps with the fused
 detection records, FP64 flux and norm sums) on the 512x512x1024 synthetic
 surface-diffraction grid, FP32 state.  Prints one JSON line.
 
-A step is one pass of the hot path over the grid: the eq. (9) half-step, the
-eq. (8) half-step with the flux partials (and, every 50 steps, the record
-plane with Q, naive norm and plane sums), and the fixed-order FP64
-finalisation.  Inputs are resident in HBM before the timed region starts.
+A step is one pass of the hot path over the grid: eq. (9) then eq. (8) (fused
+into one sweep over ping-pong buffers), with the flux partials, every 50
+steps the record plane with Q, naive norm and plane sums, and the
+fixed-order FP64 finalisation.  Inputs are resident in HBM before the timed region starts.
 
-roofline: the dominant kernel is the half-step kernel; its algorithmic bytes
-per launch are 16 B per cell in FP32 (read the stencil array, the updated
-array and V once, write the updated array once), divided by its average
-launch time measured with HIP events around each launch inside the timed
-region.  cpu_baseline: the FP64 oracle timed on this host's cores on a
+roofline: the dominant kernel is the one-pass step kernel (or the half-step
+kernel on the two-pass path); its algorithmic bytes per launch are 20 B per
+cell in FP32 (read R, I, V once, write R, I once; 16 B for a half-step),
+divided by its average launch time measured with HIP events around each
+launch inside the timed region.  cpu_baseline: the FP64 oracle timed on this host's cores on a
 bounded slab of the same workload.
 """
 from __future__ import annotations
@@ -39,29 +39,33 @@ def parse():
     p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--workload", default="headline")
     p.add_argument("--precision", default="f32", choices=["f32", "f64"])
-    p.add_argument("--tile", default=None, help="rows,waves,zc (default: tuned table)")
+    p.add_argument("--tile", default=None,
+                   help='JSON dict of Sim.set_tile keywords (default: tuned table)')
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU time of the timed oracle sample")
     p.add_argument("--cpu-planes", type=int, default=48)
     p.add_argument("--no-timing", action="store_true",
                    help="do not bracket launches with events (value only)")
+    p.add_argument("--copy-probe", action="store_true",
+                   help="run only a plain device copy of 1 GiB five times (calibrates the "
+                        "FETCH_SIZE / WRITE_SIZE counters against known bytes)")
     return p.parse_args()
 
 
 def kernel_src_sha():
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "dispatch.hpp"):
+    for f in ("kernels.hpp", "dispatch.hpp", "fused.hpp"):
         with open(os.path.join(ROOT, "paper_2401_07416_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload_name, precision, cells):
-    """HBM bytes per launch of the half-step kernel from the committed PMC
+def traffic_from_profiles(workload_name, precision, kind):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
     summary, scaled by the copy-kernel calibration; null if the kernel
     source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"half_step_{workload_name}_{precision}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload_name}_{precision}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -112,8 +116,24 @@ def cpu_baseline(w, seconds, planes):
             "ns_per_cell_step": el / (cells * steps) * 1e9}
 
 
+def copy_probe():
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "launches": 5}), flush=True)
+
+
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe()
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
                                    "described in DESIGN.md but not implemented",
@@ -126,9 +146,9 @@ def main():
     prec = a.precision
     total = a.warmup + a.steps
     sim = tdse.sim_from_workload(w, precision=prec, steps=total)
-    tile = tuple(int(x) for x in a.tile.split(",")) if a.tile else tuning.tile_for(w, prec)
+    tile = json.loads(a.tile) if a.tile else tuning.tile_for(w, prec)
     if tile is not None:
-        sim.set_tile(*tile)
+        sim.set_tile(**tile)
     t = sim.get_tile()
     torch.cuda.synchronize()
     sim.step(a.warmup)
@@ -146,23 +166,33 @@ def main():
     wall = time.perf_counter() - wall0
     ms = e0.elapsed_time(e1)
     sim.set_timing(False)
-    mi, ni, mr, nr = sim.timing_read()
+    kt = sim.timing_read()
     det = sim.detect()
     cells = w.cells
     value = cells * a.steps / (ms * 1e-3) / 1e9
     es = 8 if prec == "f64" else 4
-    alg_bytes = 4 * es * cells  # per half-step launch
+    # algorithmic bytes per launch: a half-step reads the stencil array, the
+    # updated array and V and writes the updated array (4 words per cell); the
+    # one-pass step reads R, I, V and writes R, I (5 words per cell)
+    words = {"half_i": 4, "half_r": 4, "fused": 5}
+    names = {"half_i": "half_step eq.(9) imaginary", "half_r": "half_step eq.(8) real",
+             "fused": "fused_step eqs.(9)+(8) one-pass"}
     roof = None
-    if ni and nr:
-        avg_i, avg_r = mi / ni, mr / nr
-        dom, avg = ("half_step eq.(8) real", avg_r) if mr >= mi else ("half_step eq.(9) imag", avg_i)
+    dom = max(kt, key=lambda k: kt[k][0])
+    tot_ms, launches = kt[dom]
+    if launches:
+        avg = tot_ms / launches
+        alg_bytes = words[dom] * es * cells
         achieved = alg_bytes / (avg * 1e-3) / 1e9
-        traffic = traffic_from_profiles(w.name, prec, cells)
+        traffic = traffic_from_profiles(w.name, prec, dom)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": dom, "avg_launch_ms": round(avg, 5),
-                "avg_launch_ms_imag": round(avg_i, 5), "avg_launch_ms_real": round(avg_r, 5),
-                "alg_bytes_per_launch": alg_bytes}
+                "traffic": traffic, "kernel": names[dom], "avg_launch_ms": round(avg, 5),
+                "alg_bytes_per_launch": alg_bytes,
+                "launches": {k: v[1] for k, v in kt.items()},
+                "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()}}
+    fused_share = kt["fused"][1] / max(1, a.steps)
+    bytes_per_cell_step = es * (5 * fused_share + 8 * (1 - fused_share))
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-steps/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms / a.steps, 5),
@@ -172,12 +202,12 @@ def main():
                    "grid": [w.nx, w.ny, w.nz], "cells": cells, "record_every": w.record_every,
                    "k_det": w.k_det, "cap_planes": list(w.cap[:2]) if w.cap else None,
                    "atoms": int(len(w.atoms)) if w.atoms is not None else 0,
-                   "tile": {"rows": t.rows, "waves": t.waves, "zc": t.zc, "vec": t.vec_elems,
-                            "groups": t.vec_groups, "lanes": t.lanes},
+                   "tile": t.as_dict(),
                    "dt": det.dt, "records": det.n_records},
         "roofline": roof,
         "wall_s": round(wall, 3),
-        "hbm_bytes_per_cell_step_alg": 2 * 4 * es,
+        "hbm_bytes_per_cell_step_alg": bytes_per_cell_step,
+        "hbm_gbs_whole_step": round(value * bytes_per_cell_step, 1),
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, a.cpu_planes)

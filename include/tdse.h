@@ -239,22 +239,35 @@ tdse_status tdse_detect(tdse_handle h, tdse_detect_out* out);
  * Synchronises. */
 tdse_status tdse_copy_scalars(tdse_handle h, double* host, int64_t n);
 
-/* Kernel timing for measurement: when enabled, each half-step launch is
- * bracketed by HIP events on the handle's stream.  tdse_timing_read
- * synchronises, returns the summed kernel milliseconds and launch counts of
- * the imaginary (eq. (9)) and real (eq. (8)) half-steps since the last
- * read, and clears them. */
-tdse_status tdse_set_timing(tdse_handle h, int32_t enable);
-tdse_status tdse_timing_read(tdse_handle h, double* ms_half_i, int64_t* n_half_i,
-                             double* ms_half_r, int64_t* n_half_r);
+/* Second state pair for the one-pass step: psi_r2, psi_i2 as psi_r, psi_i
+ * (caller-owned, 256-byte aligned, distinct from every other bound array).
+ * The one-pass step fuses eq. (9) and eq. (8) into one sweep that reads
+ * (psiR^n, psiI^{n-1/2}, V) and writes (psiR^{n+1}, psiI^{n+1/2}) into the
+ * other pair, 20 B per cell-step in FP32 instead of 32.  Steps run in pairs
+ * so that after every tdse_step call the state is back in the buffers bound
+ * by tdse_bind; an odd step runs as the two in-place half-steps.  Binding
+ * enables the one-pass step when the grid fits it (tdse_tile.fused). */
+tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2);
 
-/* Tile shape of the half-step kernels.  rows: y rows per wavefront (1, 2, 4
- * or 8); waves: wavefronts per workgroup (1..4); zc: z planes per
- * workgroup (>= 1).  tdse_create picks a default; tdse_set_tile checks and
- * replaces it. */
+/* Kernel timing for measurement: when enabled, each step kernel launch is
+ * bracketed by HIP events on the handle's stream.  tdse_timing_read
+ * synchronises and returns, per kernel kind (0: eq. (9) half-step, 1: eq. (8)
+ * half-step, 2: one-pass step), the summed kernel milliseconds ms[3] and
+ * launch counts count[3] since the last read, and clears them. */
+tdse_status tdse_set_timing(tdse_handle h, int32_t enable);
+tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count);
+
+/* Tile shapes.  Two-pass half-step kernels: rows = y rows per wavefront (1,
+ * 2, 4 or 8), waves = wavefronts per workgroup (1..4), zc = z planes per
+ * workgroup.  One-pass kernel: fused != 0 selects it (needs
+ * tdse_bind_pingpong), fused_rows = rows per thread (2, 3, 4 or 6; the band
+ * is band_rows = (256 / threads per row) * fused_rows - 2 rows), fused_zc =
+ * z planes per workgroup.  tdse_create picks defaults; tdse_set_tile checks
+ * and replaces them.  The last four fields are read-only. */
 typedef struct tdse_tile {
     int32_t rows, waves, zc;
-    int32_t vec_elems, vec_groups, lanes; /* read-only: x layout chosen by tdse_create */
+    int32_t fused, fused_rows, fused_zc;
+    int32_t vec_elems, vec_groups, lanes, band_rows;
 } tdse_tile;
 
 tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out);

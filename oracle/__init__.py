@@ -16,6 +16,8 @@ Parity status of each function (the pins live in ``tests/test_oracle_*.py``):
       normalisation, moments, group velocity)
   potential                           : pinned (on-node value, symmetries,
       periodic images, brute-force points)
+  adjoint / potential_vjp             : pinned (central finite differences of the
+      forward oracle, directional derivatives, checkpoint-interval invariance)
 """
 from __future__ import annotations
 
@@ -117,6 +119,11 @@ def lib():
         L.og_step.argtypes = [sp, ctypes.c_int64]
         L.og_step.restype = ctypes.c_int
         L.og_unstep.argtypes = [sp, ctypes.c_int64]
+        L.og_adjoint.argtypes = [sp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp, _dp]
+        L.og_adjoint.restype = ctypes.c_int
+        L.og_potential_vjp.argtypes = [gp, _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp,
+                                       _dp]
         _lib = L
     return _lib
 
@@ -236,6 +243,19 @@ def init_gaussian_window(grid: Grid, r0, k0, sigma, dt, origin, size, mode=INIT_
     return R, I
 
 
+def potential_vjp(grid: Grid, atoms: np.ndarray, gV: np.ndarray, soft=0.1, cutoff=6.0,
+                  kappa=KAPPA_EV_A, a0=BOHR_A, screened=True):
+    """(dL/dpositions [n][3], dL/damplitudes [n]) from dL/dV."""
+    atoms = np.ascontiguousarray(atoms, dtype=np.float64).reshape(-1, 5)
+    gV = np.ascontiguousarray(gV, dtype=np.float64)
+    dpos = np.zeros((atoms.shape[0], 3))
+    damp = np.zeros(atoms.shape[0])
+    lib().og_potential_vjp(grid.ref(), _ptr(atoms), atoms.shape[0], float(soft), float(cutoff),
+                           float(kappa), float(a0), int(screened), _ptr(gV), _ptr(dpos),
+                           _ptr(damp))
+    return dpos, damp
+
+
 def gaussian_closed(grid: Grid, r0, k0, sigma, t, nimg=2):
     re = np.zeros(grid.shape)
     im = np.zeros(grid.shape)
@@ -321,3 +341,15 @@ class Sim:
     def records(self):
         n = self.n_records
         return self.rec_rho[:n].copy(), self.rec_scalars[:n].copy()
+
+    def adjoint(self, nsteps: int, dL_drho: np.ndarray, ckpt_every: int = 100):
+        """Gradient of a loss of the records of an nsteps run started from the
+        current state: returns (dL/dV, dL/dR^0, dL/dI^{-1/2})."""
+        g = self.grid
+        nrec = (nsteps // self._s.h + 1) if self._s.h > 0 else 0
+        rb = np.ascontiguousarray(dL_drho, dtype=np.float64).reshape(max(nrec, 1), g.ny, g.nx)
+        gV, gR, gI = np.zeros(g.shape), np.zeros(g.shape), np.zeros(g.shape)
+        if lib().og_adjoint(ctypes.byref(self._s), int(nsteps), _ptr(rb), int(ckpt_every),
+                            _ptr(gV), _ptr(gR), _ptr(gI)) != 0:
+            raise MemoryError("oracle adjoint allocation")
+        return gV, gR, gI

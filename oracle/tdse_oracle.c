@@ -637,3 +637,175 @@ void og_unstep(og_sim* s, int64_t nsteps) {
         s->step -= 1;
     }
 }
+
+/* ---------------------------------------------------------------------- */
+/* Discrete adjoint of the leapfrog                                        */
+/* ---------------------------------------------------------------------- */
+
+/* G X = -(cx dxx + cy dyy + cz dzz) X + cv V X, the operator both half-steps
+ * apply (eq. (9): I' = A I - B G R; eq. (8): R' = A R + B G I', with
+ * A = diag(ca_k), B = diag(cb_k)).  G is symmetric. */
+static void og_apply_G(const og_sim* s, const double* X, double* out) {
+    const og_grid* g = &s->g;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < g->nz; ++k)
+        for (int64_t j = 0; j < g->ny; ++j)
+            for (int64_t i = 0; i < g->nx; ++i) {
+                int64_t c = og_idx(g, i, j, k);
+                out[c] = -og_laplace_terms(s, X, i, j, k) + s->cv * s->V[c] * X[c];
+            }
+}
+
+/* Gradient of a loss of the detection records through nsteps steps of the
+ * leapfrog started from the state in s (level 0), by reverse mode on the
+ * discrete scheme.  dL_drho is [n_rec][ny][nx] for the records at levels
+ * 0, h, 2h, ... <= nsteps (record m is rho at level m h on plane k_det).
+ * Forward states are recomputed from checkpoints stored every K steps.
+ * Backward step n (from r = dL/dR^{n+1}, i = dL/dI^{n+1/2}):
+ *   i_t = i + G (B r)
+ *   g_V += cv (B r) o I^{n+1/2} - cv (B i_t) o R^n
+ *   r  <- A r - G (B i_t),   i <- A i_t
+ * then the record injections at level n: r += 2 R^n rho_bar, i += 2 I^{n-1/2}
+ * rho_bar on plane k_det.  Outputs gV [nz][ny][nx] (dL/dV), gR0 = dL/dR^0,
+ * gI0 = dL/dI^{-1/2}.  s is left unchanged.  Returns 0 or -1 (allocation). */
+int og_adjoint(og_sim* s, int64_t nsteps, const double* dL_drho, int64_t K, double* gV,
+               double* gR0, double* gI0) {
+    const og_grid* g = &s->g;
+    const int64_t n = g->nx * g->ny * g->nz;
+    const int64_t nxy = g->nx * g->ny;
+    if (K < 1) K = 1;
+    const int64_t nck = nsteps / K + 1;
+    double* ckR = malloc(sizeof(double) * n * nck);
+    double* ckI = malloc(sizeof(double) * n * nck);
+    double* segR = malloc(sizeof(double) * n * (K + 1));
+    double* segI = malloc(sizeof(double) * n * (K + 1));
+    double* rb = calloc(n, sizeof(double));
+    double* ib = calloc(n, sizeof(double));
+    double* t1 = malloc(sizeof(double) * n);
+    double* t2 = malloc(sizeof(double) * n);
+    double* saveR = malloc(sizeof(double) * n);
+    double* saveI = malloc(sizeof(double) * n);
+    if (!ckR || !ckI || !segR || !segI || !rb || !ib || !t1 || !t2 || !saveR || !saveI) return -1;
+    memcpy(saveR, s->psiR, sizeof(double) * n);
+    memcpy(saveI, s->psiI, sizeof(double) * n);
+    const int64_t step0 = s->step;
+    const double flux0 = s->flux_acc;
+    const int64_t h_save = s->h;
+    s->h = 0; /* no records while replaying */
+
+    /* forward pass: checkpoints at 0, K, 2K, ... */
+    for (int64_t c = 0; c < nck; ++c) {
+        memcpy(ckR + c * n, s->psiR, sizeof(double) * n);
+        memcpy(ckI + c * n, s->psiI, sizeof(double) * n);
+        int64_t todo = (c + 1) * K <= nsteps ? K : nsteps - c * K;
+        if (c + 1 < nck) og_step(s, todo);
+    }
+    for (int64_t c = 0; c < n; ++c) gV[c] = 0.0;
+
+    /* record injection at level lev using state (R, I) = (R^lev, I^{lev-1/2}) */
+#define OG_INJECT(lev, Rl, Il)                                                        \
+    do {                                                                              \
+        if (h_save > 0 && (lev) % h_save == 0) {                                      \
+            const double* rbar = dL_drho + ((lev) / h_save) * nxy;                    \
+            for (int64_t p = 0; p < nxy; ++p) {                                       \
+                int64_t cc = s->k_det * nxy + p;                                      \
+                rb[cc] += 2.0 * (Rl)[cc] * rbar[p];                                   \
+                ib[cc] += 2.0 * (Il)[cc] * rbar[p];                                   \
+            }                                                                         \
+        }                                                                             \
+    } while (0)
+
+    for (int64_t c = nck - 1; c >= 0; --c) {
+        const int64_t s0 = c * K;
+        const int64_t s1 = (s0 + K < nsteps) ? s0 + K : nsteps;
+        /* recompute the states s0..s1 of this segment */
+        memcpy(s->psiR, ckR + c * n, sizeof(double) * n);
+        memcpy(s->psiI, ckI + c * n, sizeof(double) * n);
+        memcpy(segR, s->psiR, sizeof(double) * n);
+        memcpy(segI, s->psiI, sizeof(double) * n);
+        for (int64_t m = s0; m < s1; ++m) {
+            og_step(s, 1);
+            memcpy(segR + (m - s0 + 1) * n, s->psiR, sizeof(double) * n);
+            memcpy(segI + (m - s0 + 1) * n, s->psiI, sizeof(double) * n);
+        }
+        if (s1 == nsteps) OG_INJECT(nsteps, segR + (s1 - s0) * n, segI + (s1 - s0) * n);
+        for (int64_t m = s1 - 1; m >= s0; --m) {
+            const double* Rn = segR + (m - s0) * n;         /* R^m */
+            const double* Ih = segI + (m - s0 + 1) * n;     /* I^{m+1/2} */
+            /* t1 = B r, i_t = i + G t1 */
+            for (int64_t cc = 0; cc < n; ++cc) t1[cc] = s->cb[cc / nxy] * rb[cc];
+            og_apply_G(s, t1, t2);
+            for (int64_t cc = 0; cc < n; ++cc) {
+                gV[cc] += s->cv * t1[cc] * Ih[cc];
+                ib[cc] += t2[cc];
+            }
+            /* t1 = B i_t; r <- A r - G t1; i <- A i_t */
+            for (int64_t cc = 0; cc < n; ++cc) t1[cc] = s->cb[cc / nxy] * ib[cc];
+            og_apply_G(s, t1, t2);
+            for (int64_t cc = 0; cc < n; ++cc) {
+                gV[cc] -= s->cv * t1[cc] * Rn[cc];
+                const double a = s->ca[cc / nxy];
+                rb[cc] = a * rb[cc] - t2[cc];
+                ib[cc] = a * ib[cc];
+            }
+            OG_INJECT(m, Rn, segI + (m - s0) * n);
+        }
+    }
+#undef OG_INJECT
+    memcpy(gR0, rb, sizeof(double) * n);
+    memcpy(gI0, ib, sizeof(double) * n);
+    /* restore the simulation */
+    memcpy(s->psiR, saveR, sizeof(double) * n);
+    memcpy(s->psiI, saveI, sizeof(double) * n);
+    s->step = step0;
+    s->flux_acc = flux0;
+    s->h = h_save;
+    free(ckR); free(ckI); free(segR); free(segI); free(rb); free(ib);
+    free(t1); free(t2); free(saveR); free(saveI);
+    return 0;
+}
+
+/* Chain rule from dL/dV to the atoms of og_potential:
+ *   dL/dX_a = sum_r gV(r) dV(r)/dX_a,  dV/dX_a = -amp_a v'(d) u/d,
+ *   dL/damp_a = sum_r gV(r) v(d),
+ * u = r - X_a (minimum image), d = |u| < cutoff.  A grid point exactly on an
+ * atom (d = 0) adds nothing to dL/dX_a: the screened potential has a cusp
+ * there and the symmetric subgradient is zero. */
+void og_potential_vjp(const og_grid* g, const double* atoms, int64_t n, double soft,
+                      double cutoff, double kappa, double a0, int screened, const double* gV,
+                      double* dpos, double* damp) {
+    const double L[3] = {g->nx * g->dx, g->ny * g->dy, g->nz * g->dz};
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t a = 0; a < n; ++a) {
+        const double* at = atoms + 5 * a;
+        double sx = 0.0, sy = 0.0, sz = 0.0, sa = 0.0;
+        for (int64_t k = 0; k < g->nz; ++k) {
+            double uz = k * g->dz - at[2];
+            if (g->bc[2] == OG_PERIODIC) uz = og_min_image(uz, L[2]);
+            if (fabs(uz) >= cutoff) continue;
+            for (int64_t j = 0; j < g->ny; ++j) {
+                double uy = j * g->dy - at[1];
+                if (g->bc[1] == OG_PERIODIC) uy = og_min_image(uy, L[1]);
+                if (fabs(uy) >= cutoff) continue;
+                for (int64_t i = 0; i < g->nx; ++i) {
+                    double ux = i * g->dx - at[0];
+                    if (g->bc[0] == OG_PERIODIC) ux = og_min_image(ux, L[0]);
+                    const double d = sqrt(ux * ux + uy * uy + uz * uz);
+                    if (d >= cutoff) continue;
+                    const double w = gV[og_idx(g, i, j, k)];
+                    sa += w * og_vatom(d, at[3], soft, kappa, a0, screened);
+                    if (d > 0.0) {
+                        const double f = -at[4] * og_dvatom(d, at[3], soft, kappa, a0, screened) / d;
+                        sx += w * f * ux;
+                        sy += w * f * uy;
+                        sz += w * f * uz;
+                    }
+                }
+            }
+        }
+        dpos[3 * a + 0] = sx;
+        dpos[3 * a + 1] = sy;
+        dpos[3 * a + 2] = sz;
+        damp[a] = sa;
+    }
+}

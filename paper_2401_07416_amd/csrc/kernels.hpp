@@ -91,6 +91,26 @@ __device__ __forceinline__ void stv(T* p, const vec_t<T, W>& x) {
     *reinterpret_cast<vec_t<T, W>*>(p) = x;
 }
 
+// Cell arithmetic shared by the two-pass and the one-pass kernels, so both
+// produce the same bits.
+//   L(X) = cx (X(i+1) - 2X + X(i-1)) + cy (...) + cz (...)
+template <typename T>
+__device__ __forceinline__ T lap7(T c, T xl, T xr, T yl, T yr, T zl, T zr, T cx, T cy, T cz) {
+    return cx * ((xr - T(2) * c) + xl) + cy * ((yr - T(2) * c) + yl) + cz * ((zr - T(2) * c) + zl);
+}
+
+// eq. (9) with the time-centred CAP: I' = ca I + cb (L(R) - cv V R)
+template <typename T>
+__device__ __forceinline__ T update_I(T lap, T v, T c, T uo, T cv, T ca, T cb) {
+    return ca * uo + cb * (lap - cv * v * c);
+}
+
+// eq. (8) with the time-centred CAP: R' = ca R - cb (L(I) - cv V I)
+template <typename T>
+__device__ __forceinline__ T update_R(T lap, T v, T c, T uo, T cv, T ca, T cb) {
+    return ca * uo - cb * (lap - cv * v * c);
+}
+
 template <typename T, int W, int G, int RY, int MODE>
 __global__ __launch_bounds__(256) void half_step_kernel(HalfArgs<T> a) {
     using VT = vec_t<T, W>;
@@ -196,11 +216,10 @@ __global__ __launch_bounds__(256) void half_step_kernel(HalfArgs<T> a) {
                     const T yr = (r < RY - 1) ? sc[r + 1][g].v[e] : hh[g].v[e];
                     const T zl = sp[r][g].v[e];
                     const T zr = sn[r][g].v[e];
-                    const T lap = a.cx * ((xr - T(2) * c) + xl) + a.cy * ((yr - T(2) * c) + yl) +
-                                  a.cz * ((zr - T(2) * c) + zl);
-                    const T gt = lap - a.cv * vv[r][g].v[e] * c;
+                    const T lap = lap7(c, xl, xr, yl, yr, zl, zr, a.cx, a.cy, a.cz);
                     const T uo = u[r][g].v[e];
-                    const T unew = IS_R ? (cak * uo - cbk * gt) : (cak * uo + cbk * gt);
+                    const T unew = IS_R ? update_R(lap, vv[r][g].v[e], c, uo, a.cv, cak, cbk)
+                                        : update_I(lap, vv[r][g].v[e], c, uo, a.cv, cak, cbk);
                     un[g].v[e] = unew;
                     if (act) {
                         if (IS_R) {

@@ -18,6 +18,7 @@
 #include "../../include/tdse.h"
 #include "kernels.hpp"
 #include "setup_kernels.hpp"
+#include "fused.hpp"
 
 using namespace tdse;
 
@@ -28,10 +29,15 @@ struct tdse_ctx {
     // x layout and tile
     int W = 1, G = 1, NL = 1;
     int rows = 2, waves = 4, zc = 16;
+    // one-pass (fused) step: rows per thread M, z chunk, enabled flag
+    int fm = 4, fzc = 64;
+    bool fused = false;
     // bound memory
     void* R = nullptr;
     void* I = nullptr;
     void* V = nullptr;
+    void* R2 = nullptr;  // second state pair of the one-pass step
+    void* I2 = nullptr;
     void* ws = nullptr;
     void* rec = nullptr;
     double* scal = nullptr;
@@ -158,6 +164,10 @@ void default_tile(tdse_ctx* h) {
     h->zc = (int)std::min<int64_t>(zc, d.nz);
 }
 
+// Default one-pass tile: the largest band that fits the LDS limit, z chunks
+// sized for about 1500 workgroups.
+void default_fused_tile(tdse_ctx* h);
+
 struct TileDims {
     int ytiles, ywg, nzc, nwg;
 };
@@ -186,6 +196,10 @@ hipError_t launch_half_f64_w2(int g, int rows, int mode, dim3 grid, dim3 block, 
                               const HalfArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_half_f64_w1(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
                               const HalfArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_fused_f32(int w, int m, bool rec, dim3 grid, size_t lds, hipStream_t st,
+                            const FusedArgs<float>& a, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_fused_f64(int w, int m, bool rec, dim3 grid, size_t lds, hipStream_t st,
+                            const FusedArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
 }  // namespace tdse
 
 namespace {
@@ -255,22 +269,32 @@ HalfArgs<T> make_args(tdse_ctx* h, int mode, int rows, int waves, int zc, long r
     return a;
 }
 
+// Event pair around the next launch when timing is on.  kind: 0 = eq. (9)
+// half-step, 1 = eq. (8) half-step, 2 = one-pass step.
+tdse_status timing_events(tdse_ctx* h, int kind, hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
+    if (!h->timing) return TDSE_OK;
+    while (h->ev.size() < h->ev_used + 2) {
+        hipEvent_t e;
+        HIPCHK(h, hipEventCreate(&e));
+        h->ev.push_back(e);
+        h->ev_kind.push_back(0);
+    }
+    *e0 = h->ev[h->ev_used];
+    *e1 = h->ev[h->ev_used + 1];
+    h->ev_kind[h->ev_used] = kind;
+    h->ev_used += 2;
+    return TDSE_OK;
+}
+
 tdse_status launch_half(tdse_ctx* h, int mode, int rows, int waves, int zc, long rec_idx,
                         int flux_slot) {
     const TileDims td = tile_dims(h, rows, waves, zc);
     dim3 grid(td.nwg), block(64, waves);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (h->timing && (mode == MODE_I || mode == MODE_R || mode == MODE_R_REC)) {
-        while (h->ev.size() < h->ev_used + 2) {
-            hipEvent_t e;
-            HIPCHK(h, hipEventCreate(&e));
-            h->ev.push_back(e);
-            h->ev_kind.push_back(0);
-        }
-        e0 = h->ev[h->ev_used];
-        e1 = h->ev[h->ev_used + 1];
-        h->ev_kind[h->ev_used] = (mode == MODE_I) ? 0 : 1;
-        h->ev_used += 2;
+    if (mode != MODE_I_PEEK) {
+        tdse_status s = timing_events(h, mode == MODE_I ? 0 : 1, &e0, &e1);
+        if (s != TDSE_OK) return s;
     }
     hipError_t e;
     if (h->d.precision == TDSE_F64) {
@@ -283,14 +307,112 @@ tdse_status launch_half(tdse_ctx* h, int mode, int rows, int waves, int zc, long
     return hip_check(h, e, "half-step launch");
 }
 
-tdse_status launch_finalize(tdse_ctx* h, int n_pending, bool record, long rec_idx, int rows,
-                            int waves, int zc) {
+// Geometry of the one-pass kernel: W-element vectors, tpr threads per row,
+// rpp rows per pass of a 256-thread workgroup, band of ty = rpp*m - 2 rows.
+struct FusedDims {
+    int W, tpr, rpp, ty, nbands, nzc, nwg;
+    size_t lds;
+    bool ok;
+};
+
+FusedDims fused_dims(const tdse_ctx* h, int m, int zc) {
     const tdse_desc& d = h->d;
-    const TileDims td = tile_dims(h, rows, waves, zc);
+    FusedDims f{};
+    const int es = d.precision == TDSE_F64 ? 8 : 4;
+    const int wl32[3] = {4, 2, 1}, wl64[2] = {2, 1};
+    const int* wl = es == 8 ? wl64 : wl32;
+    const int nw = es == 8 ? 2 : 3;
+    f.ok = false;
+    for (int i = 0; i < nw; ++i) {
+        if (d.nx % wl[i] == 0 && d.nx / wl[i] <= 256) {
+            f.W = wl[i];
+            f.ok = true;
+            break;
+        }
+    }
+    if (!f.ok) return f;
+    f.tpr = (int)(d.nx / f.W);
+    f.rpp = 256 / f.tpr;
+    f.ty = f.rpp * m - 2;
+    f.nbands = f.ty > 0 ? (int)((d.ny + f.ty - 1) / f.ty) : 0;
+    f.nzc = (int)((d.nz + zc - 1) / zc);
+    f.nwg = f.nbands * f.nzc;
+    f.lds = (size_t)(3 * f.ty + 8) * d.nx * es;
+    // dynamic LDS plus the 2 KB static reduction buffer stay under 64 KB
+    f.ok = f.ty >= 1 && f.lds <= 65536 - 4096;
+    return f;
+}
+
+template <typename T>
+FusedArgs<T> make_fused_args(tdse_ctx* h, const FusedDims& f, bool rec, long rec_idx,
+                             int flux_slot) {
+    const tdse_desc& d = h->d;
+    FusedArgs<T> a;
+    a.R0 = static_cast<const T*>(h->R);
+    a.I0 = static_cast<const T*>(h->I);
+    a.R1 = static_cast<T*>(h->R2);
+    a.I1 = static_cast<T*>(h->I2);
+    a.V = static_cast<const T*>(h->V);
+    a.ca = static_cast<const T*>(h->ca);
+    a.cb = static_cast<const T*>(h->cb);
+    a.cx = (T)h->c[0];
+    a.cy = (T)h->c[1];
+    a.cz = (T)h->c[2];
+    a.cv = (T)h->c[3];
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    a.tpr = f.tpr;
+    a.rpp = f.rpp;
+    a.ty = f.ty;
+    a.nbands = f.nbands;
+    a.zc = h->fzc;
+    a.nzc = f.nzc;
+    a.nwg = f.nwg;
+    a.bcx = d.bc[0] == TDSE_BC_ZERO;
+    a.bcy = d.bc[1] == TDSE_BC_ZERO;
+    a.bcz = d.bc[2] == TDSE_BC_ZERO;
+    a.k_det = (int)d.k_det;
+    const bool has_up = !(a.bcz && d.k_det + 1 >= d.nz);
+    a.k_up = has_up ? (int)((d.k_det + 1) % d.nz) : -1;
+    a.flux_slots = h->flux_ring + (size_t)flux_slot * 2 * f.nbands;
+    a.rec_plane = (rec && h->rec) ? reinterpret_cast<T*>(static_cast<char*>(h->rec) +
+                                                         (size_t)rec_idx * d.nx * d.ny * sizeof(T))
+                                  : nullptr;
+    a.part_q = h->part_q;
+    a.part_naive = h->part_naive;
+    a.part_plane = h->part_plane;
+    a.pixel = (rec && (d.flags & TDSE_FLAG_PIXEL_INTEGRAL)) ? h->pix : nullptr;
+    a.pixel_w = (double)d.record_every * h->dt;
+    return a;
+}
+
+// One one-pass step from (R, I) into (R2, I2); the caller swaps the pairs.
+tdse_status launch_fused(tdse_ctx* h, const FusedDims& f, bool rec, long rec_idx, int flux_slot) {
+    hipEvent_t e0, e1;
+    tdse_status s = timing_events(h, 2, &e0, &e1);
+    if (s != TDSE_OK) return s;
+    hipError_t e;
+    if (h->d.precision == TDSE_F64) {
+        FusedArgs<double> a = make_fused_args<double>(h, f, rec, rec_idx, flux_slot);
+        e = launch_fused_f64(f.W, h->fm, rec, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+    } else {
+        FusedArgs<float> a = make_fused_args<float>(h, f, rec, rec_idx, flux_slot);
+        e = launch_fused_f32(f.W, h->fm, rec, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+    }
+    return hip_check(h, e, "one-pass step launch");
+}
+
+// Fold n_pending steps of flux partials (slots per step each) into the
+// accumulator; on record steps also write the record scalars from n_part
+// partial slots.
+tdse_status launch_finalize(tdse_ctx* h, int n_pending, bool record, long rec_idx, int slots,
+                            long n_part) {
+    const tdse_desc& d = h->d;
     FinArgs a;
     a.flux_ring = h->flux_ring;
     a.n_pending = n_pending;
-    a.ytiles = td.ytiles;
+    a.ytiles = slots;
     a.has_up = !(d.bc[2] == TDSE_BC_ZERO && d.k_det + 1 >= d.nz);
     a.record = record ? 1 : 0;
     a.rec_idx = rec_idx;
@@ -299,7 +421,7 @@ tdse_status launch_finalize(tdse_ctx* h, int n_pending, bool record, long rec_id
     a.acc = h->acc;
     a.part_q = h->part_q;
     a.part_naive = h->part_naive;
-    a.n_part = (long)td.nzc * td.ytiles;
+    a.n_part = n_part;
     a.part_plane = h->part_plane;
     a.scalars = h->scal;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, h->stream, a);
@@ -317,10 +439,27 @@ tdse_status begin_records(tdse_ctx* h) {
     }
     tdse_status s = launch_half(h, MODE_I_PEEK, h->rows, h->waves, h->zc, 0, 0);
     if (s != TDSE_OK) return s;
-    return launch_finalize(h, 0, true, 0, h->rows, h->waves, h->zc);
+    const TileDims td = tile_dims(h, h->rows, h->waves, h->zc);
+    return launch_finalize(h, 0, true, 0, td.ytiles, (long)td.nzc * td.ytiles);
 }
 
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % ALIGN) == 0; }
+
+void default_fused_tile(tdse_ctx* h) {
+    const tdse_desc& d = h->d;
+    h->fzc = (int)std::min<int64_t>(64, d.nz);
+    for (int m : {4, 3, 2}) {
+        const FusedDims f = fused_dims(h, m, h->fzc);
+        if (f.ok && f.ty <= d.ny + 2) {
+            h->fm = m;
+            const int target = 1536;
+            int nzc = std::max(1, target / std::max(1, f.nbands));
+            h->fzc = (int)std::min<int64_t>(d.nz, std::max<int64_t>(8, (d.nz + nzc - 1) / nzc));
+            return;
+        }
+    }
+    h->fm = 2;
+}
 
 }  // namespace
 
@@ -419,6 +558,7 @@ tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out) {
         return TDSE_ERR_DEVICE;
     }
     default_tile(h);
+    default_fused_tile(h);
     h->wcap.assign((size_t)d->nz, 0.0);
     *out = h;
     return TDSE_OK;
@@ -452,6 +592,9 @@ tdse_status tdse_bind(tdse_handle h, void* psi_r, void* psi_i, void* v, void* wo
     h->R = psi_r;
     h->I = psi_i;
     h->V = v;
+    h->R2 = nullptr;
+    h->I2 = nullptr;
+    h->fused = false;
     h->ws = workspace;
     h->ws_bytes = workspace_bytes;
     h->rec = records;
@@ -795,25 +938,49 @@ tdse_status tdse_step(tdse_handle h, int64_t n) {
     const int64_t hrec = d.record_every;
     if (hrec > 0 && (h->step + n) / hrec + 1 > d.max_records)
         return fail(h, TDSE_ERR_CAPACITY, "record buffer would overflow");
+    // one-pass steps come in pairs so the state ends in the bound buffers;
+    // an odd step runs as two in-place half-steps
+    const FusedDims fd = fused_dims(h, h->fm, h->fzc);
+    const bool use_fused = h->fused && h->R2 && fd.ok;
+    const int64_t n_fused = use_fused ? (n / 2) * 2 : 0;
+    const TileDims td = tile_dims(h, h->rows, h->waves, h->zc);
     for (int64_t it = 0; it < n; ++it) {
         const int64_t s = h->step;
         const bool record = hrec > 0 && ((s + 1) % hrec == 0);
         const long rec_idx = record ? (long)((s + 1) / hrec) : 0;
-        tdse_status st = launch_half(h, MODE_I, h->rows, h->waves, h->zc, 0, 0);
-        if (st != TDSE_OK) return st;
-        st = launch_half(h, record ? MODE_R_REC : MODE_R, h->rows, h->waves, h->zc, rec_idx,
-                         h->pending);
-        if (st != TDSE_OK) return st;
+        const bool fused = it < n_fused;
+        const int slots = fused ? fd.nbands : td.ytiles;
+        const long nparts = fused ? (long)fd.nzc * fd.nbands : (long)td.nzc * td.ytiles;
+        if (!fused && it == n_fused && h->pending > 0) {
+            // partial slots of one-pass steps use another layout: fold them first
+            tdse_status st = launch_finalize(h, h->pending, false, 0, fd.nbands, 0);
+            if (st != TDSE_OK) return st;
+            h->pending = 0;
+        }
+        tdse_status st;
+        if (fused) {
+            st = launch_fused(h, fd, record, rec_idx, h->pending);
+            if (st != TDSE_OK) return st;
+            std::swap(h->R, h->R2);
+            std::swap(h->I, h->I2);
+        } else {
+            st = launch_half(h, MODE_I, h->rows, h->waves, h->zc, 0, 0);
+            if (st != TDSE_OK) return st;
+            st = launch_half(h, record ? MODE_R_REC : MODE_R, h->rows, h->waves, h->zc, rec_idx,
+                             h->pending);
+            if (st != TDSE_OK) return st;
+        }
         h->pending += 1;
         h->step += 1;
         if (record || h->pending == h->F) {
-            st = launch_finalize(h, h->pending, record, rec_idx, h->rows, h->waves, h->zc);
+            st = launch_finalize(h, h->pending, record, rec_idx, slots, nparts);
             if (st != TDSE_OK) return st;
             h->pending = 0;
         }
     }
     if (h->pending > 0) {
-        tdse_status st = launch_finalize(h, h->pending, false, 0, h->rows, h->waves, h->zc);
+        const bool last_fused = n_fused == n;
+        tdse_status st = launch_finalize(h, h->pending, false, 0, last_fused ? fd.nbands : td.ytiles, 0);
         if (st != TDSE_OK) return st;
         h->pending = 0;
     }
@@ -863,27 +1030,21 @@ tdse_status tdse_set_timing(tdse_handle h, int32_t enable) {
     return TDSE_OK;
 }
 
-tdse_status tdse_timing_read(tdse_handle h, double* ms_i, int64_t* n_i, double* ms_r, int64_t* n_r) {
-    if (!h) return TDSE_ERR_ARG;
+tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count) {
+    if (!h || !ms || !count) return TDSE_ERR_ARG;
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    double ti = 0.0, tr = 0.0;
-    int64_t ci = 0, cr = 0;
+    for (int k = 0; k < 3; ++k) {
+        ms[k] = 0.0;
+        count[k] = 0;
+    }
     for (size_t e = 0; e + 1 < h->ev_used; e += 2) {
-        float ms = 0.f;
-        HIPCHK(h, hipEventElapsedTime(&ms, h->ev[e], h->ev[e + 1]));
-        if (h->ev_kind[e] == 0) {
-            ti += ms;
-            ++ci;
-        } else {
-            tr += ms;
-            ++cr;
-        }
+        float t = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&t, h->ev[e], h->ev[e + 1]));
+        const int k = h->ev_kind[e];
+        ms[k] += t;
+        count[k] += 1;
     }
     h->ev_used = 0;
-    if (ms_i) *ms_i = ti;
-    if (n_i) *n_i = ci;
-    if (ms_r) *ms_r = tr;
-    if (n_r) *n_r = cr;
     return TDSE_OK;
 }
 
@@ -892,9 +1053,14 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
     out->rows = h->rows;
     out->waves = h->waves;
     out->zc = h->zc;
+    out->fused = (h->fused && h->R2) ? 1 : 0;
+    out->fused_rows = h->fm;
+    out->fused_zc = h->fzc;
     out->vec_elems = h->W;
     out->vec_groups = h->G;
     out->lanes = h->NL;
+    const FusedDims f = fused_dims(h, h->fm, h->fzc);
+    out->band_rows = f.ok ? f.ty : 0;
     return TDSE_OK;
 }
 
@@ -903,11 +1069,37 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
     if (t->rows != 1 && t->rows != 2 && t->rows != 4 && t->rows != 8)
         return fail(h, TDSE_ERR_ARG, "rows must be 1, 2, 4 or 8");
     if (t->waves < 1 || t->waves > 4) return fail(h, TDSE_ERR_ARG, "waves must be 1..4");
-    if (t->zc < 1) return fail(h, TDSE_ERR_ARG, "zc must be >= 1");
+    if (t->zc < 1 || t->fused_zc < 1) return fail(h, TDSE_ERR_ARG, "z chunks must be >= 1");
+    if (t->fused_rows != 2 && t->fused_rows != 3 && t->fused_rows != 4 && t->fused_rows != 6)
+        return fail(h, TDSE_ERR_ARG, "fused_rows must be 2, 3, 4 or 6");
     if (h->pending != 0) return fail(h, TDSE_ERR_STATE, "pending flux partials");
+    const int fzc = (int)std::min<int64_t>(t->fused_zc, h->d.nz);
+    if (t->fused) {
+        if (!h->R2) return fail(h, TDSE_ERR_STATE, "one-pass step needs tdse_bind_pingpong");
+        if (!fused_dims(h, t->fused_rows, fzc).ok)
+            return fail(h, TDSE_ERR_UNSUPPORTED, "one-pass tile does not fit this grid");
+    }
     h->rows = t->rows;
     h->waves = t->waves;
     h->zc = (int)std::min<int64_t>(t->zc, h->d.nz);
+    h->fused = t->fused != 0;
+    h->fm = t->fused_rows;
+    h->fzc = fzc;
+    return TDSE_OK;
+}
+
+tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2) {
+    if (!h) return TDSE_ERR_ARG;
+    if (!h->bound) return fail(h, TDSE_ERR_STATE, "bind before bind_pingpong");
+    if (!psi_r2 || !psi_i2) return fail(h, TDSE_ERR_ARG, "null pointer");
+    if (!aligned(psi_r2) || !aligned(psi_i2)) return fail(h, TDSE_ERR_ARG, "pointer not 256-byte aligned");
+    void* used[5] = {h->R, h->I, h->V, psi_r2, psi_i2};
+    for (int i = 0; i < 5; ++i)
+        for (int j = i + 1; j < 5; ++j)
+            if (used[i] == used[j]) return fail(h, TDSE_ERR_ARG, "aliased arrays");
+    h->R2 = psi_r2;
+    h->I2 = psi_i2;
+    h->fused = fused_dims(h, h->fm, h->fzc).ok;
     return TDSE_OK;
 }
 

@@ -31,6 +31,7 @@ EXPORTS = [
     "tdse_build_potential", "tdse_set_cap", "tdse_set_cap_quadratic", "tdse_finalize_setup",
     "tdse_init_gaussian", "tdse_set_state", "tdse_get_state", "tdse_step", "tdse_detect",
     "tdse_copy_scalars", "tdse_set_timing", "tdse_timing_read", "tdse_get_tile", "tdse_set_tile",
+    "tdse_bind_pingpong",
 ]
 
 
@@ -71,8 +72,13 @@ class DetectOut(ctypes.Structure):
 
 class Tile(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("waves", ctypes.c_int32), ("zc", ctypes.c_int32),
-                ("vec_elems", ctypes.c_int32), ("vec_groups", ctypes.c_int32),
-                ("lanes", ctypes.c_int32)]
+                ("fused", ctypes.c_int32), ("fused_rows", ctypes.c_int32),
+                ("fused_zc", ctypes.c_int32), ("vec_elems", ctypes.c_int32),
+                ("vec_groups", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("band_rows", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 _lib = None
@@ -110,7 +116,8 @@ def load():
         "tdse_detect": (i32, [vp, ctypes.POINTER(DetectOut)]),
         "tdse_copy_scalars": (i32, [vp, dp, i64]),
         "tdse_set_timing": (i32, [vp, i32]),
-        "tdse_timing_read": (i32, [vp, dp, ctypes.POINTER(i64), dp, ctypes.POINTER(i64)]),
+        "tdse_timing_read": (i32, [vp, dp, ctypes.POINTER(i64)]),
+        "tdse_bind_pingpong": (i32, [vp, vp, vp]),
         "tdse_get_tile": (i32, [vp, ctypes.POINTER(Tile)]),
         "tdse_set_tile": (i32, [vp, ctypes.POINTER(Tile)]),
     }
@@ -183,7 +190,7 @@ class Sim:
     workspace, the records [max_records][ny][nx], the FP64 record scalars
     [max_records][4] and optionally the FP64 pixel integral [ny][nx]."""
 
-    def __init__(self, desc: Desc, device=None, stream=None):
+    def __init__(self, desc: Desc, device=None, stream=None, pingpong=True):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libtdse needs a HIP device")
@@ -215,6 +222,12 @@ class Sim:
                 self.h, self.psi_r.data_ptr(), self.psi_i.data_ptr(), self.v.data_ptr(),
                 self.workspace.data_ptr(), self.workspace.numel(), self.records.data_ptr(),
                 self.scalars.data_ptr(), self.pixel.data_ptr() if self.pixel is not None else None))
+            self.psi_r2 = self.psi_i2 = None
+            if pingpong:
+                self.psi_r2 = torch.empty(shape, dtype=dt, device=self.device)
+                self.psi_i2 = torch.empty(shape, dtype=dt, device=self.device)
+                self._check(self.lib.tdse_bind_pingpong(self.h, self.psi_r2.data_ptr(),
+                                                        self.psi_i2.data_ptr()))
         self.dt = None
         self.e_max = None
 
@@ -304,24 +317,30 @@ class Sim:
         self._check(self.lib.tdse_set_timing(self.h, int(bool(on))))
 
     def timing_read(self):
-        mi, mr = ctypes.c_double(), ctypes.c_double()
-        ni, nr = ctypes.c_int64(), ctypes.c_int64()
-        self._check(self.lib.tdse_timing_read(self.h, ctypes.byref(mi), ctypes.byref(ni),
-                                              ctypes.byref(mr), ctypes.byref(nr)))
-        return mi.value, ni.value, mr.value, nr.value
+        """{kind: (ms, launches)} for 'half_i', 'half_r', 'fused' since the last read."""
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 3)()
+        self._check(self.lib.tdse_timing_read(self.h, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(("half_i", "half_r", "fused"))}
 
     def get_tile(self) -> Tile:
         t = Tile()
         self._check(self.lib.tdse_get_tile(self.h, ctypes.byref(t)))
         return t
 
-    def set_tile(self, rows: int, waves: int, zc: int):
-        t = Tile(int(rows), int(waves), int(zc), 0, 0, 0)
+    def set_tile(self, rows=None, waves=None, zc=None, fused=None, fused_rows=None,
+                 fused_zc=None):
+        t = self.get_tile()
+        for name, v in (("rows", rows), ("waves", waves), ("zc", zc), ("fused", fused),
+                        ("fused_rows", fused_rows), ("fused_zc", fused_zc)):
+            if v is not None:
+                setattr(t, name, int(v))
         self._check(self.lib.tdse_set_tile(self.h, ctypes.byref(t)))
 
 
 def sim_from_workload(w, precision: Optional[str] = None, steps: Optional[int] = None,
-                      pixel=False, device=None, max_records: Optional[int] = None) -> Sim:
+                      pixel=False, device=None, max_records: Optional[int] = None,
+                      pingpong=True) -> Sim:
     """Set up a simulation from a seeded workload description (potential on
     the device, CAP, dt, Gaussian packet)."""
     prec = precision or w.precision
@@ -330,7 +349,7 @@ def sim_from_workload(w, precision: Optional[str] = None, steps: Optional[int] =
     d = make_desc(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, dt_frac=w.dt_frac,
                   bc=w.bc, precision=prec, k_det=w.k_det, record_every=w.record_every,
                   max_records=nrec, flags=FLAG_PIXEL_INTEGRAL if pixel else 0)
-    s = Sim(d, device=device)
+    s = Sim(d, device=device, pingpong=pingpong)
     if w.atoms is not None and len(w.atoms):
         s.build_potential(w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
                           screened=w.screened)

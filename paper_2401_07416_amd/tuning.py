@@ -1,9 +1,10 @@
 """Tile shapes of the half-step kernels chosen by measurement.
 
-``tune_table.json`` maps "<nx>x<ny>x<nz>:<precision>" to the (rows, waves, zc)
-tile a sweep on the MI355X found fastest for that grid.  Grids absent from
-the table run the library's default tile.  ``autotune`` re-measures a grid
-in place.
+``tune_table.json`` maps "<nx>x<ny>x<nz>:<precision>" to the tile (the
+keyword arguments of ``Sim.set_tile``: two-pass rows/waves/zc, one-pass
+fused/fused_rows/fused_zc) that a sweep on the MI355X found fastest for that
+grid.  Grids absent from the table run the library's defaults.  ``autotune``
+re-measures a grid in place.
 """
 from __future__ import annotations
 
@@ -26,26 +27,37 @@ def load_table() -> dict:
         return json.load(f)
 
 
-def tile_for(w, precision: str) -> Optional[Tuple[int, int, int]]:
+def tile_for(w, precision: str) -> Optional[dict]:
     t = load_table().get(_key(w.nx, w.ny, w.nz, precision))
-    return tuple(t["tile"]) if t else None
+    return dict(t["tile"]) if t else None
 
 
 def candidates(nz: int):
+    """Two-pass tiles then one-pass tiles, as set_tile keyword dicts."""
     for rows in (1, 2, 4):
         for waves in (1, 2, 4):
             for zc in (8, 16, 32, 64, 128, 256):
                 if zc <= nz:
-                    yield (rows, waves, zc)
+                    yield dict(fused=0, rows=rows, waves=waves, zc=zc)
+    for fr in (2, 3, 4, 6):
+        for zc in (16, 32, 64, 128, 256):
+            if zc <= nz:
+                yield dict(fused=1, fused_rows=fr, fused_zc=zc)
 
 
 def autotune(sim, steps: int = 20, reps: int = 3, cands=None):
     """Time each candidate tile on a live simulation (the state advances;
-    use a scratch simulation).  Returns [(ms_per_step, tile)] sorted."""
+    use a scratch simulation).  Tiles the grid cannot take are skipped.
+    Returns [(ms_per_step, tile)] sorted."""
     import torch
+
+    from .tdse import TdseError
     res = []
     for tile in (cands or candidates(sim.desc.nz)):
-        sim.set_tile(*tile)
+        try:
+            sim.set_tile(**tile)
+        except TdseError:
+            continue
         sim.step(2)
         torch.cuda.synchronize()
         best = float("inf")

@@ -16,6 +16,9 @@ pytestmark = pytest.mark.gpu
 
 FP64 = dict(tol_state=1e-11, tol_rec=1e-11, tol_scal=1e-12, tol_flux=1e-12)
 FP32 = dict(tol_state=1e-4, tol_rec=1e-3, tol_scal=1e-4, tol_flux=1e-5)
+# the one-pass step (ping-pong buffers) and the two in-place half-steps
+PATHS = [True, False]
+PATH_IDS = ["onepass", "twopass"]
 
 
 def say(*a):
@@ -23,11 +26,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def test_free_gaussian_64cubed_fp64():
+@pytest.mark.parametrize("pp", PATHS, ids=PATH_IDS)
+def test_free_gaussian_64cubed_fp64(pp):
     w = workloads.c1_free_gaussian()
-    say("free gaussian 64^3 fp64, 200 steps")
+    say("free gaussian 64^3 fp64, 200 steps, one-pass" if pp else "two-pass")
     ref = H.oracle_run(w, w.steps)
-    gpu = H.gpu_run(w, w.steps, precision="f64")
+    gpu = H.gpu_run(w, w.steps, precision="f64", pingpong=pp)
     say(H.compare(gpu, ref, **FP64))
 
 
@@ -47,30 +51,33 @@ def test_setup_potential_and_packet(name, prec):
     assert H.rel_l2(gpu.psi_i.double().cpu().numpy(), I) <= tol
 
 
+@pytest.mark.parametrize("pp", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_surface_reduced_2000_steps(prec):
+def test_surface_reduced_2000_steps(prec, pp):
     w = workloads.c2_reduced()
-    say("surface 64x64x128", prec, w.steps, "steps")
+    say("surface 64x64x128", prec, w.steps, "steps", "one-pass" if pp else "two-pass")
     ref = H.oracle_run(w, w.steps, pixel=True)
-    gpu = H.gpu_run(w, w.steps, precision=prec, pixel=True)
+    gpu = H.gpu_run(w, w.steps, precision=prec, pixel=True, pingpong=pp)
     say(H.compare(gpu, ref, **(FP64 if prec == "f64" else FP32)))
     pix = gpu.pixel.cpu().numpy()
     assert H.rel_l2(pix, ref.pixel) <= (1e-11 if prec == "f64" else 1e-3)
 
 
+@pytest.mark.parametrize("pp", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (1, 0, 1), (0, 1, 0)])
-def test_ragged_boundaries(prec, bc):
+def test_ragged_boundaries(prec, bc, pp):
     w = workloads.ragged(prec).with_(bc=bc)
-    say("ragged 37x29x53", prec, "bc", bc)
+    say("ragged 37x29x53", prec, "bc", bc, "one-pass" if pp else "two-pass")
     ref = H.oracle_run(w, w.steps)
-    gpu = H.gpu_run(w, w.steps, precision=prec)
+    gpu = H.gpu_run(w, w.steps, precision=prec, pingpong=pp)
     say(H.compare(gpu, ref, **(FP64 if prec == "f64" else FP32)))
 
 
+@pytest.mark.parametrize("pp", PATHS, ids=PATH_IDS)
 @pytest.mark.parametrize("shape,kdet", [((1, 1, 96), 60), ((4, 1, 64), 63), ((8, 3, 1), 0),
                                         ((2, 5, 40), 39)])
-def test_degenerate_extents(shape, kdet):
+def test_degenerate_extents(shape, kdet, pp):
     nx, ny, nz = shape
     w = workloads.ragged("f64").with_(nx=nx, ny=ny, nz=nz, k_det=kdet, cap=(3, 3, 20.0)
                                       if nz >= 8 else None,
@@ -79,16 +86,26 @@ def test_degenerate_extents(shape, kdet):
         ww = w.with_(bc=bc)
         say("degenerate", shape, "bc", bc)
         ref = H.oracle_run(ww, ww.steps)
-        gpu = H.gpu_run(ww, ww.steps, precision="f64")
+        gpu = H.gpu_run(ww, ww.steps, precision="f64", pingpong=pp)
         say(H.compare(gpu, ref, **FP64))
 
 
+TILES = [dict(fused=0, rows=1, waves=1, zc=4), dict(fused=0, rows=2, waves=4, zc=16),
+         dict(fused=0, rows=4, waves=2, zc=7), dict(fused=0, rows=8, waves=1, zc=128),
+         dict(fused=0, rows=2, waves=3, zc=33), dict(fused=1, fused_rows=2, fused_zc=8),
+         dict(fused=1, fused_rows=3, fused_zc=33), dict(fused=1, fused_rows=4, fused_zc=128),
+         dict(fused=1, fused_rows=2, fused_zc=5)]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_tile_shapes_give_identical_states(prec):
+def test_tile_shapes_and_paths_give_identical_states(prec):
+    """Every tile of both step paths produces the same bits: the cell
+    arithmetic is shared and the sums are reduced in a fixed order."""
     w = workloads.c2_reduced().with_(steps=120)
     say("tile shapes", prec)
     base = None
-    for tile in [(1, 1, 4), (2, 4, 16), (4, 2, 7), (8, 1, 128), (2, 3, 33)]:
+    for tile in TILES:
+        say(" tile", tile)
         gpu = H.gpu_run(w, w.steps, precision=prec, tile=tile)
         st = (gpu.psi_r.cpu().numpy(), gpu.psi_i.cpu().numpy())
         rho, sc = gpu.records_host()
@@ -155,7 +172,7 @@ def test_headline_grid_light_cone_windows():
     gpu = tdse.sim_from_workload(w, precision="f32", steps=steps)
     tile = tuning.tile_for(w, "f32")
     if tile is not None:
-        gpu.set_tile(*tile)
+        gpu.set_tile(**tile)
     gpu.step(steps)
     d = gpu.detect()
     g = H.oracle_grid(w)

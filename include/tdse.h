@@ -249,6 +249,50 @@ tdse_status tdse_copy_scalars(tdse_handle h, double* host, int64_t n);
  * enables the one-pass step when the grid fits it (tdse_tile.fused). */
 tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2);
 
+/* Reverse-mode gradient of a loss of the detection records (eq. (15))
+ * through the leapfrog of eqs. (8)-(9) with the CAP.
+ *
+ * tdse_adjoint_workspace_size: bytes of the adjoint workspace for a forward
+ * run of n_steps steps with checkpoints every ckpt_every steps: 2 ceil(N/K)
+ * checkpoint arrays, 2 (K + 1) segment arrays and 4 work arrays, each
+ * [nz][ny][nx] in the state precision (host only).
+ *
+ * tdse_bind_adjoint: attach that caller-owned device workspace (256-byte
+ * aligned; NULL detaches) to a handle whose state is at level 0.  The next
+ * n_steps steps store (psiR, psiI) of levels 0, K, 2K, ... as checkpoints.
+ *
+ * tdse_adjoint: after exactly n_steps steps, form
+ *   dL_dV  (device, double [nz][ny][nx])       dL/dV
+ *   dL_dR0 (device, state precision, nullable) dL/dpsiR^0
+ *   dL_dI0 (device, state precision, nullable) dL/dpsiI^{-1/2}
+ * from dL_drho (device, state precision, [n_rec][ny][nx], the derivative of
+ * the loss with respect to each record, n_rec = n_steps/h + 1).  Each
+ * segment between checkpoints is recomputed forward (bit-identical to the
+ * forward run) and then swept backwards:
+ *   i_t = i + G (B r);  dL/dV += cv (B r) o psiI^{n+1/2} - cv (B i_t) o psiR^n;
+ *   r <- A r - G (B i_t);  i <- A i_t;  then record injections of level n,
+ * G X = -(cx dxx + cy dyy + cz dzz) X + cv V X, A = diag(ca_k),
+ * B = diag(cb_k).  In FP32 dL/dV is summed per segment in FP32 and folded
+ * into FP64.  The handle's state is left at level n_steps.  Synchronises. */
+tdse_status tdse_adjoint_workspace_size(const tdse_desc* d, int64_t n_steps, int32_t ckpt_every,
+                                        size_t* bytes);
+tdse_status tdse_bind_adjoint(tdse_handle h, void* adj_ws, size_t bytes, int64_t n_steps,
+                              int32_t ckpt_every);
+tdse_status tdse_adjoint(tdse_handle h, const void* dL_drho, double* dL_dV, void* dL_dR0,
+                         void* dL_dI0);
+
+/* Chain rule from dL/dV (device, double [nz][ny][nx]) to the atoms of
+ * tdse_build_potential (host [n]):
+ *   dL_dpos[a][0..2] = sum_r dL/dV(r) (-amp_a v'(d) u/d),
+ *   dL_damp[a]       = sum_r dL/dV(r) v(d),
+ * u = r - X_a (minimum image), d = |u| < cutoff; a grid point exactly on an
+ * atom adds nothing to dL_dpos (the screened potential has a cusp there).
+ * Outputs are host memory.  Allocates and frees a small temporary;
+ * synchronises. */
+tdse_status tdse_potential_vjp(tdse_handle h, const tdse_atom* atoms, int64_t n,
+                               const tdse_pot_params* p, const double* dL_dV, double* dL_dpos,
+                               double* dL_damp);
+
 /* Kernel timing for measurement: when enabled, each step kernel launch is
  * bracketed by HIP events on the handle's stream.  tdse_timing_read
  * synchronises and returns, per kernel kind (0: eq. (9) half-step, 1: eq. (8)
@@ -262,11 +306,13 @@ tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count);
  * workgroup.  One-pass kernel: fused != 0 selects it (needs
  * tdse_bind_pingpong), fused_rows = rows per thread (2, 3, 4 or 6; the band
  * is band_rows = (256 / threads per row) * fused_rows - 2 rows), fused_zc =
- * z planes per workgroup.  tdse_create picks defaults; tdse_set_tile checks
- * and replaces them.  The last four fields are read-only. */
+ * z planes per workgroup, fused_prefetch != 0 issues the next plane's loads
+ * before the current plane's eq. (8) part.  tdse_create picks defaults;
+ * tdse_set_tile checks and replaces them.  The last four fields are
+ * read-only. */
 typedef struct tdse_tile {
     int32_t rows, waves, zc;
-    int32_t fused, fused_rows, fused_zc;
+    int32_t fused, fused_rows, fused_zc, fused_prefetch;
     int32_t vec_elems, vec_groups, lanes, band_rows;
 } tdse_tile;
 

@@ -21,6 +21,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 instructions: the compiler may not form them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every multiply and add rounded on its own, as written: the one-pass and
+    # two-pass kernels then give the same bits, and FP64 follows the
+    # oracle's rounding sequence
+    "-ffp-contract=off",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -47,7 +47,10 @@ struct FusedArgs {
     double pixel_w;
 };
 
-template <typename T, int W, int M, bool REC>
+// PF: issue the loads of the next plane (R three planes ahead, I^{n-1/2}
+// and V two ahead, the LDS halo rows) before the eq. (8) part of the
+// current plane, so their latency hides behind it.
+template <typename T, int W, int M, bool REC, bool PF>
 __global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
     using VT = vec_t<T, W>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -78,18 +81,19 @@ __global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
         return j;
     };
     auto gplane = [&](int p) -> int {
-        if (p < 0) return a.bcz ? -1 : ((p % nz) + nz) % nz;
-        if (p >= nz) return a.bcz ? -1 : p % nz;
+        if (p < 0) {
+            if (a.bcz) return -1;
+            do p += nz; while (p < 0);
+        } else if (p >= nz) {
+            if (a.bcz) return -1;
+            do p -= nz; while (p >= nz);
+        }
         return p;
     };
-    auto ld = [&](const T* base, int j, int p) -> VT {
-        VT r;
-        if (j < 0 || p < 0 || !live) {
-#pragma unroll
-            for (int e = 0; e < W; ++e) r.v[e] = T(0);
-            return r;
-        }
-        return ldv<T, W>(base + (long)p * plane + (long)j * nx + x0);
+    // plane resource of an array (size 0 for a zero plane)
+    const int pbytes = (int)(plane * (long)sizeof(T));
+    auto prs = [&](const T* base, int gp) {
+        return plane_rsrc(base + (long)(gp < 0 ? 0 : gp) * plane, gp < 0 ? 0 : pbytes);
     };
 
     int rowb[M];   // band row of owned row i
@@ -105,6 +109,16 @@ __global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
     const bool halo_lo = live && rs == 0;
     const bool halo_hi = live && rs == a.rpp - 1;
     const int jh_lo = grow(-1), jh_hi = grow(TY + 2);
+    // byte offsets within a plane: loads of owned rows, stores of band rows,
+    // halo rows; OOB reads zero / drops the store
+    int voff[M], voffB[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        voff[i] = (live && rowj[i] >= 0) ? (rowj[i] * nx + x0) * (int)sizeof(T) : OOB;
+        voffB[i] = isB[i] ? voff[i] : OOB;
+    }
+    const int voff_lo = (halo_lo && jh_lo >= 0) ? (jh_lo * nx + x0) * (int)sizeof(T) : OOB;
+    const int voff_hi = (halo_hi && jh_hi >= 0) ? (jh_hi * nx + x0) * (int)sizeof(T) : OOB;
 
     VT Rz[3][M], Iz[3][M], Vk[M];
 
@@ -123,25 +137,39 @@ __global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
         return row[x];
     };
 
-    // phase A for plane p: I^{n+1/2}(p) on the owned rows from the R window
-    // (planes p-1, p, p+1 in Rz[0..2]); result into Iz[slot] and LDS buffer.
-    auto phase_a = [&](int p, int slot, bool store) {
+    // load the plane-p inputs of phase A: I^{n-1/2}(p), V(p), and the two
+    // extra R(p) rows of the LDS band
+    auto load_a = [&](int p, VT(&io)[M], VT(&vv)[M], VT& hlo, VT& hhi) {
         const int gp = gplane(p);
-        // stage R(p) of the band (+ halo rows) in LDS
+        const auto rI = prs(a.I0, gp), rV = prs(a.V, gp), rR = prs(a.R0, gp);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            io[i] = bload<T, W>(rI, voff[i]);
+            vv[i] = bload<T, W>(rV, voff[i]);
+        }
+        hlo = bload<T, W>(rR, voff_lo);
+        hhi = bload<T, W>(rR, voff_hi);
+    };
+    auto load_r = [&](int p, VT(&out)[M]) {
+        const auto rR = prs(a.R0, gplane(p));
+#pragma unroll
+        for (int i = 0; i < M; ++i) out[i] = bload<T, W>(rR, voff[i]);
+    };
+    // stage R(p) = Rz[1] of the band and its halo rows in LDS
+    auto stage = [&](const VT& hlo, const VT& hhi) {
         if (live) {
 #pragma unroll
             for (int i = 0; i < M; ++i)
                 if (rowb[i] <= TY + 1) *reinterpret_cast<VT*>(lr_row(rowb[i]) + x0) = Rz[1][i];
-            if (halo_lo) *reinterpret_cast<VT*>(lr_row(-1) + x0) = ld(a.R0, jh_lo, gp);
-            if (halo_hi) *reinterpret_cast<VT*>(lr_row(TY + 2) + x0) = ld(a.R0, jh_hi, gp);
+            if (halo_lo) *reinterpret_cast<VT*>(lr_row(-1) + x0) = hlo;
+            if (halo_hi) *reinterpret_cast<VT*>(lr_row(TY + 2) + x0) = hhi;
         }
-        VT io[M], vv[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-            io[i] = ld(a.I0, rowj[i], gp);
-            vv[i] = ld(a.V, rowj[i], gp);
-        }
-        __syncthreads();
+    };
+    // phase A for plane p: I^{n+1/2}(p) on the owned rows from the R window
+    // (planes p-1, p, p+1 in Rz[0..2], centre plane staged in LDS); result
+    // into outI and the LDS buffer of plane p; stored if p is in the chunk.
+    auto compute_a = [&](int p, const VT(&io)[M], const VT(&vv)[M], VT(&outI)[M], bool store) {
+        const int gp = gplane(p);
         const T cap = gp >= 0 ? a.ca[gp] : T(1);
         const T cbp = gp >= 0 ? a.cb[gp] : T(1);
         const int buf = (p - k0 + 2) & 1;
@@ -152,10 +180,8 @@ __global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
             const bool zero = (gp < 0) || (rowj[i] < 0);
             if (live && b <= TY + 1) {
                 const T* rc = lr_row(b);
-                const T* ru = lr_row(b - 1);
-                const T* rd = lr_row(b + 1);
-                const VT yl = *reinterpret_cast<const VT*>(ru + x0);
-                const VT yr = *reinterpret_cast<const VT*>(rd + x0);
+                const VT yl = *reinterpret_cast<const VT*>(lr_row(b - 1) + x0);
+                const VT yr = *reinterpret_cast<const VT*>(lr_row(b + 1) + x0);
                 const T xle = xl_of(rc), xre = xr_of(rc);
 #pragma unroll
                 for (int e = 0; e < W; ++e) {
@@ -167,49 +193,68 @@ __global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
                     out.v[e] = zero ? T(0) : update_I(lap, vv[i].v[e], c, io[i].v[e], a.cv, cap, cbp);
                 }
                 *reinterpret_cast<VT*>(li_row(buf, b) + x0) = out;
-                if (store && isB[i])
-                    stv<T, W>(a.I1 + (long)gp * plane + (long)rowj[i] * nx + x0, out);
+                if (store) bstore<T, W>(prs(a.I1, gp), voffB[i], out);
             } else {
 #pragma unroll
                 for (int e = 0; e < W; ++e) out.v[e] = T(0);
             }
-            Iz[slot][i] = out;
-            Vk[i] = vv[i];
+            outI[i] = out;
         }
     };
 
-    // R window for the prologue: planes k0-2, k0-1, k0
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-        Rz[0][i] = ld(a.R0, rowj[i], gplane(k0 - 2));
-        Rz[1][i] = ld(a.R0, rowj[i], gplane(k0 - 1));
-        Rz[2][i] = ld(a.R0, rowj[i], gplane(k0));
-    }
-    phase_a(k0 - 1, 0, false);       // I^{n+1/2}(k0-1), neighbour only
+    VT io[M], vv[M], hlo, hhi, Rn[M];
+    // prologue: I^{n+1/2} at planes k0-1 (neighbour only) and k0
+    load_r(k0 - 2, Rz[0]);
+    load_r(k0 - 1, Rz[1]);
+    load_r(k0, Rz[2]);
+    load_a(k0 - 1, io, vv, hlo, hhi);
+    stage(hlo, hhi);
+    __syncthreads();
+    compute_a(k0 - 1, io, vv, Iz[0], false);
     __syncthreads();                  // LR is rewritten next
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         Rz[0][i] = Rz[1][i];
         Rz[1][i] = Rz[2][i];
-        Rz[2][i] = ld(a.R0, rowj[i], gplane(k0 + 1));
     }
-    phase_a(k0, 1, true);             // I^{n+1/2}(k0)
-    // Vk now holds V(k0)
+    load_r(k0 + 1, Rz[2]);
+    load_a(k0, io, vv, hlo, hhi);
+    stage(hlo, hhi);
+    __syncthreads();
+    compute_a(k0, io, vv, Iz[1], true);
+#pragma unroll
+    for (int i = 0; i < M; ++i) Vk[i] = vv[i];  // V(k0)
+    if (PF) {
+        load_r(k0 + 2, Rn);
+        load_a(k0 + 1, io, vv, hlo, hhi);
+    }
 
     double f0 = 0.0, f1 = 0.0, q = 0.0, nv = 0.0, pl = 0.0;
     for (int k = k0; k < k1; ++k) {
-        // R window to planes k, k+1, k+2
+        // R window to planes k, k+1, k+2 and the phase-A inputs of plane k+1
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             Rz[0][i] = Rz[1][i];
             Rz[1][i] = Rz[2][i];
-            Rz[2][i] = ld(a.R0, rowj[i], gplane(k + 2));
+            if (PF) Rz[2][i] = Rn[i];
+        }
+        if (!PF) {
+            load_r(k + 2, Rz[2]);
+            load_a(k + 1, io, vv, hlo, hhi);
         }
         VT vk[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) vk[i] = Vk[i];
-        __syncthreads();                 // all phase-B reads of the previous plane done
-        phase_a(k + 1, 2, k + 1 < k1);   // I^{n+1/2}(k+1); barrier inside
+        __syncthreads();                 // all reads of the previous plane's LDS done
+        stage(hlo, hhi);
+        __syncthreads();
+        compute_a(k + 1, io, vv, Iz[2], k + 1 < k1);   // I^{n+1/2}(k+1)
+#pragma unroll
+        for (int i = 0; i < M; ++i) Vk[i] = vv[i];      // V(k+1)
+        if (PF && k + 1 < k1) {
+            load_r(k + 3, Rn);
+            load_a(k + 2, io, vv, hlo, hhi);
+        }
         // phase B for plane k: R^{n+1}(k) = eq. (8) from I^{n+1/2}(k-1..k+1)
         const int buf = (k - k0 + 2) & 1;
         const T cak = a.ca[k];
@@ -242,8 +287,7 @@ __global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
                     nv += dn * dn + dc * dc;
                 }
             }
-            const long off = (long)k * plane + (long)rowj[i] * nx + x0;
-            stv<T, W>(a.R1 + off, out);
+            bstore<T, W>(prs(a.R1, k), voffB[i], out);
             if (REC && at_det) {
                 VT rv;
                 const long poff = (long)rowj[i] * nx + x0;

@@ -9,7 +9,7 @@ namespace tdse {
 namespace {
 
 template <int W, int M>
-hipError_t go(bool rec, dim3 grid, size_t lds, hipStream_t st, const FusedArgs<float>& a,
+hipError_t go(bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st, const FusedArgs<float>& a,
               hipEvent_t e0, hipEvent_t e1) {
     auto run = [&](auto kern) -> hipError_t {
         if (e0)
@@ -18,28 +18,32 @@ hipError_t go(bool rec, dim3 grid, size_t lds, hipStream_t st, const FusedArgs<f
             hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a);
         return hipGetLastError();
     };
-    return rec ? run(fused_step_kernel<float, W, M, true>) : run(fused_step_kernel<float, W, M, false>);
+    if (pf)
+        return rec ? run(fused_step_kernel<float, W, M, true, true>)
+                   : run(fused_step_kernel<float, W, M, false, true>);
+    return rec ? run(fused_step_kernel<float, W, M, true, false>)
+               : run(fused_step_kernel<float, W, M, false, false>);
 }
 
 template <int W>
-hipError_t go_m(int m, bool rec, dim3 grid, size_t lds, hipStream_t st,
+hipError_t go_m(int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
                 const FusedArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
     switch (m) {
-        case 2: return go<W, 2>(rec, grid, lds, st, a, e0, e1);
-        case 3: return go<W, 3>(rec, grid, lds, st, a, e0, e1);
-        case 4: return go<W, 4>(rec, grid, lds, st, a, e0, e1);
-        default: return go<W, 6>(rec, grid, lds, st, a, e0, e1);
+        case 2: return go<W, 2>(rec, pf, grid, lds, st, a, e0, e1);
+        case 3: return go<W, 3>(rec, pf, grid, lds, st, a, e0, e1);
+        case 4: return go<W, 4>(rec, pf, grid, lds, st, a, e0, e1);
+        default: return go<W, 6>(rec, pf, grid, lds, st, a, e0, e1);
     }
 }
 
 }  // namespace
 
-hipError_t launch_fused_f32(int w, int m, bool rec, dim3 grid, size_t lds, hipStream_t st,
+hipError_t launch_fused_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
                              const FusedArgs<float>& a, hipEvent_t e0, hipEvent_t e1) {
     switch (w) {
-        case 4: return go_m<4>(m, rec, grid, lds, st, a, e0, e1);
-        case 2: return go_m<2>(m, rec, grid, lds, st, a, e0, e1);
-        default: return go_m<1>(m, rec, grid, lds, st, a, e0, e1);
+        case 4: return go_m<4>(m, rec, pf, grid, lds, st, a, e0, e1);
+        case 2: return go_m<2>(m, rec, pf, grid, lds, st, a, e0, e1);
+        default: return go_m<1>(m, rec, pf, grid, lds, st, a, e0, e1);
     }
 }
 

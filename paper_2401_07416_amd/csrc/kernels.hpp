@@ -91,6 +91,44 @@ __device__ __forceinline__ void stv(T* p, const vec_t<T, W>& x) {
     *reinterpret_cast<vec_t<T, W>*>(p) = x;
 }
 
+// Buffer accesses through a resource spanning one z-plane of an array: the
+// 32-bit byte offset of a row is the same for every plane and every array
+// of the grid, and an offset past the plane (or a plane of size 0) reads
+// as zero and drops stores, so zero rows and planes cost no branches.
+// 0x00020000 is the gfx9 word-3 setting of a raw (stride 0) buffer.
+constexpr int OOB = 0x7ffffff0;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
+template <typename T, int W>
+__device__ __forceinline__ vec_t<T, W> bload(__amdgpu_buffer_rsrc_t r, int off) {
+    constexpr int B = (int)sizeof(T) * W;
+    static_assert(B == 4 || B == 8 || B == 16, "vector of 4, 8 or 16 bytes");
+    if constexpr (B == 16) {
+        return __builtin_bit_cast(vec_t<T, W>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    } else if constexpr (B == 8) {
+        return __builtin_bit_cast(vec_t<T, W>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    } else {
+        return __builtin_bit_cast(vec_t<T, W>, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+}
+
+template <typename T, int W>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, const vec_t<T, W>& v) {
+    constexpr int B = (int)sizeof(T) * W;
+    if constexpr (B == 16) {
+        using U = __attribute__((ext_vector_type(4))) unsigned int;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, off, 0, 0);
+    } else if constexpr (B == 8) {
+        using U = __attribute__((ext_vector_type(2))) unsigned int;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+    }
+}
+
 // Cell arithmetic shared by the two-pass and the one-pass kernels, so both
 // produce the same bits.
 //   L(X) = cx (X(i+1) - 2X + X(i-1)) + cy (...) + cz (...)

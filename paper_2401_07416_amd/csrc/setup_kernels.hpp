@@ -254,3 +254,93 @@ __global__ __launch_bounds__(256) void gauss_write_kernel(GaussCellArgs a, T* R,
 }
 
 }  // namespace tdse
+
+namespace tdse {
+
+struct VjpArgs {
+    int nx, ny, nz;
+    double dx, dy, dz, Lx, Ly, Lz;
+    int bcx, bcy, bcz, screened;
+    const double* atoms;  // [n][5]
+    const double* gV;     // dL/dV [nz][ny][nx]
+    double soft, cutoff, kappa, a0;
+    double* out;          // [n][4]: dL/dx, dL/dy, dL/dz, dL/damp
+};
+
+// Index range of one axis around coordinate x within the cutoff: the cells
+// i0 .. i0 + cnt - 1 (wrapped on a periodic axis, clipped on a zero one),
+// each cell of the axis at most once.
+__device__ __forceinline__ void axis_range(double x, double cut, double d, int n, int zero,
+                                           int* i0, int* cnt) {
+    int lo = (int)ceil((x - cut) / d), hi = (int)floor((x + cut) / d);
+    if (zero) {
+        lo = max(lo, 0);
+        hi = min(hi, n - 1);
+        *i0 = lo;
+        *cnt = max(0, hi - lo + 1);
+        return;
+    }
+    if (hi - lo + 1 >= n) {
+        *i0 = 0;
+        *cnt = n;
+        return;
+    }
+    *i0 = lo;
+    *cnt = hi - lo + 1;
+}
+
+// Chain rule from dL/dV to the atoms:
+//   dL/dX_a = sum_r gV(r) (-amp_a v'(d) u / d),  dL/damp_a = sum_r gV(r) v(d),
+// u = r - X_a (minimum image), d = |u| < cutoff; a cell exactly on the atom
+// adds nothing to dL/dX_a (cusp of the screened potential).  One workgroup
+// per atom, fixed-order reduction.
+__global__ __launch_bounds__(256) void potential_vjp_kernel(VjpArgs p) {
+    __shared__ double red[256];
+    const double* at = p.atoms + 5 * (long)blockIdx.x;
+    int i0, ci, j0, cj, k0, ck;
+    axis_range(at[0], p.cutoff, p.dx, p.nx, p.bcx, &i0, &ci);
+    axis_range(at[1], p.cutoff, p.dy, p.ny, p.bcy, &j0, &cj);
+    axis_range(at[2], p.cutoff, p.dz, p.nz, p.bcz, &k0, &ck);
+    const long tot = (long)ci * cj * ck;
+    double sx = 0.0, sy = 0.0, sz = 0.0, sa = 0.0;
+    const double Z = at[3], amp = at[4];
+    const double lam = 0.8853 * p.a0 * pow(Z, -1.0 / 3.0);
+    for (long c = threadIdx.x; c < tot; c += 256) {
+        const int ii = (int)(c % ci), jj = (int)((c / ci) % cj), kk = (int)(c / ((long)ci * cj));
+        int i = i0 + ii, j = j0 + jj, k = k0 + kk;
+        if (!p.bcx) i = ((i % p.nx) + p.nx) % p.nx;
+        if (!p.bcy) j = ((j % p.ny) + p.ny) % p.ny;
+        if (!p.bcz) k = ((k % p.nz) + p.nz) % p.nz;
+        double ux = i * p.dx - at[0], uy = j * p.dy - at[1], uz = k * p.dz - at[2];
+        if (!p.bcx) ux = min_image(ux, p.Lx);
+        if (!p.bcy) uy = min_image(uy, p.Ly);
+        if (!p.bcz) uz = min_image(uz, p.Lz);
+        const double d = sqrt(ux * ux + uy * uy + uz * uz);
+        if (d >= p.cutoff) continue;
+        const double w = p.gV[((long)k * p.ny + j) * p.nx + i];
+        const double e = p.screened ? exp(-d / lam) : 1.0;
+        const double v = -Z * p.kappa * e / sqrt(d * d + p.soft * p.soft);
+        sa += w * v;
+        if (d > 0.0) {
+            const double inv_lam = p.screened ? 1.0 / lam : 0.0;
+            const double dv = v * (-inv_lam - d / (d * d + p.soft * p.soft));
+            const double f = -amp * dv / d;
+            sx += w * f * ux;
+            sy += w * f * uy;
+            sz += w * f * uz;
+        }
+    }
+    sx = block_sum256(sx, red);
+    sy = block_sum256(sy, red);
+    sz = block_sum256(sz, red);
+    sa = block_sum256(sa, red);
+    if (threadIdx.x == 0) {
+        double* o = p.out + 4 * (long)blockIdx.x;
+        o[0] = sx;
+        o[1] = sy;
+        o[2] = sz;
+        o[3] = sa;
+    }
+}
+
+}  // namespace tdse

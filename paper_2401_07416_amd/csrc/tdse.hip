@@ -19,6 +19,7 @@
 #include "kernels.hpp"
 #include "setup_kernels.hpp"
 #include "fused.hpp"
+#include "adjoint.hpp"
 
 using namespace tdse;
 
@@ -31,7 +32,12 @@ struct tdse_ctx {
     int rows = 2, waves = 4, zc = 16;
     // one-pass (fused) step: rows per thread M, z chunk, enabled flag
     int fm = 4, fzc = 64;
+    bool fpf = true;
     bool fused = false;
+    // adjoint: checkpoints every adj_K steps of an adj_N-step forward run
+    void* adj_ws = nullptr;
+    int64_t adj_N = 0;
+    int adj_K = 0;
     // bound memory
     void* R = nullptr;
     void* I = nullptr;
@@ -196,9 +202,13 @@ hipError_t launch_half_f64_w2(int g, int rows, int mode, dim3 grid, dim3 block, 
                               const HalfArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_half_f64_w1(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
                               const HalfArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_fused_f32(int w, int m, bool rec, dim3 grid, size_t lds, hipStream_t st,
+hipError_t launch_fused_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
                             const FusedArgs<float>& a, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_fused_f64(int w, int m, bool rec, dim3 grid, size_t lds, hipStream_t st,
+hipError_t launch_adjoint_f32(int w, int g, int phase, dim3 grid, dim3 block, hipStream_t st,
+                              const AdjArgs<float>& a);
+hipError_t launch_adjoint_f64(int w, int g, int phase, dim3 grid, dim3 block, hipStream_t st,
+                              const AdjArgs<double>& a);
+hipError_t launch_fused_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
                             const FusedArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
 }  // namespace tdse
 
@@ -395,10 +405,10 @@ tdse_status launch_fused(tdse_ctx* h, const FusedDims& f, bool rec, long rec_idx
     hipError_t e;
     if (h->d.precision == TDSE_F64) {
         FusedArgs<double> a = make_fused_args<double>(h, f, rec, rec_idx, flux_slot);
-        e = launch_fused_f64(f.W, h->fm, rec, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+        e = launch_fused_f64(f.W, h->fm, rec, h->fpf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
     } else {
         FusedArgs<float> a = make_fused_args<float>(h, f, rec, rec_idx, flux_slot);
-        e = launch_fused_f32(f.W, h->fm, rec, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+        e = launch_fused_f32(f.W, h->fm, rec, h->fpf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
     }
     return hip_check(h, e, "one-pass step launch");
 }
@@ -444,6 +454,174 @@ tdse_status begin_records(tdse_ctx* h) {
 }
 
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % ALIGN) == 0; }
+
+// Adjoint workspace: checkpoints of levels 0, K, 2K, ... < N, the K + 1
+// states of one recomputed segment, and r, i, A i_t and (FP32) the segment
+// accumulator of dL/dV.  Each array is [nz][ny][nx] in the state precision.
+struct AdjLayout {
+    size_t arr, nck, ckpt, seg, rb, ia, ib, gv, total;
+};
+
+AdjLayout adj_layout(const tdse_desc& d, int64_t N, int K) {
+    AdjLayout L{};
+    L.arr = align_up((size_t)d.nx * d.ny * d.nz * elem_size(d));
+    L.nck = (size_t)((N + K - 1) / K);
+    size_t o = 0;
+    L.ckpt = o; o += 2 * L.nck * L.arr;
+    L.seg = o; o += 2 * ((size_t)K + 1) * L.arr;
+    L.rb = o; o += L.arr;
+    L.ia = o; o += L.arr;
+    L.ib = o; o += L.arr;
+    L.gv = o; o += L.arr;
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+AdjArgs<T> make_adj_args(tdse_ctx* h, const T* S, T* U, T* U2, const T* Rn, const T* Ih, T* gv) {
+    const tdse_desc& d = h->d;
+    const TileDims td = tile_dims(h, 1, h->waves, h->zc);
+    AdjArgs<T> a;
+    a.S = S;
+    a.U = U;
+    a.U2 = U2;
+    a.V = static_cast<const T*>(h->V);
+    a.Rn = Rn;
+    a.Ih = Ih;
+    a.gv = gv;
+    a.ca = static_cast<const T*>(h->ca);
+    a.cb = static_cast<const T*>(h->cb);
+    a.cx = (T)h->c[0];
+    a.cy = (T)h->c[1];
+    a.cz = (T)h->c[2];
+    a.cv = (T)h->c[3];
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    a.nl = h->NL;
+    a.ytiles = td.ytiles;
+    a.wpg = h->waves;
+    a.ywg = td.ywg;
+    a.zc = h->zc;
+    a.nzc = td.nzc;
+    a.nwg = td.nwg;
+    a.bcx = d.bc[0] == TDSE_BC_ZERO;
+    a.bcy = d.bc[1] == TDSE_BC_ZERO;
+    a.bcz = d.bc[2] == TDSE_BC_ZERO;
+    return a;
+}
+
+template <typename T>
+tdse_status launch_adj(tdse_ctx* h, int phase, const AdjArgs<T>& a) {
+    const TileDims td = tile_dims(h, 1, h->waves, h->zc);
+    hipError_t e;
+    if constexpr (sizeof(T) == 8)
+        e = launch_adjoint_f64(h->W, h->G, phase, dim3(td.nwg), dim3(64, h->waves), h->stream, a);
+    else
+        e = launch_adjoint_f32(h->W, h->G, phase, dim3(td.nwg), dim3(64, h->waves), h->stream, a);
+    return hip_check(h, e, "adjoint launch");
+}
+
+// One forward step from (Rs, Is) into (Rd, Id), no records, no flux
+// accumulation (the flux ring slot 0 is scratch here).
+tdse_status forward_step_explicit(tdse_ctx* h, void* Rs, void* Is, void* Rd, void* Id) {
+    const FusedDims fd = fused_dims(h, h->fm, h->fzc);
+    void* sR = h->R;
+    void* sI = h->I;
+    void* sR2 = h->R2;
+    void* sI2 = h->I2;
+    tdse_status st = TDSE_OK;
+    if (fd.ok) {
+        h->R = Rs;
+        h->I = Is;
+        h->R2 = Rd;
+        h->I2 = Id;
+        st = launch_fused(h, fd, false, 0, 0);
+    } else {
+        const size_t bytes = (size_t)h->d.nx * h->d.ny * h->d.nz * elem_size(h->d);
+        st = hip_check(h, hipMemcpyAsync(Rd, Rs, bytes, hipMemcpyDeviceToDevice, h->stream), "copy");
+        if (st == TDSE_OK)
+            st = hip_check(h, hipMemcpyAsync(Id, Is, bytes, hipMemcpyDeviceToDevice, h->stream), "copy");
+        h->R = Rd;
+        h->I = Id;
+        if (st == TDSE_OK) st = launch_half(h, MODE_I, h->rows, h->waves, h->zc, 0, 0);
+        if (st == TDSE_OK) st = launch_half(h, MODE_R, h->rows, h->waves, h->zc, 0, 0);
+    }
+    h->R = sR;
+    h->I = sI;
+    h->R2 = sR2;
+    h->I2 = sI2;
+    return st;
+}
+
+template <typename T>
+tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* gI0) {
+    const tdse_desc& d = h->d;
+    const int64_t N = h->adj_N;
+    const int K = h->adj_K;
+    const AdjLayout L = adj_layout(d, N, K);
+    char* w = static_cast<char*>(h->adj_ws);
+    const long n = (long)d.nx * d.ny * d.nz;
+    const long nxy = (long)d.nx * d.ny;
+    auto ck = [&](size_t c, int which) { return reinterpret_cast<T*>(w + L.ckpt + (2 * c + which) * L.arr); };
+    auto sg = [&](size_t m, int which) { return reinterpret_cast<T*>(w + L.seg + (2 * m + which) * L.arr); };
+    T* rb = reinterpret_cast<T*>(w + L.rb);
+    T* ia = reinterpret_cast<T*>(w + L.ia);
+    T* ib = reinterpret_cast<T*>(w + L.ib);
+    T* gv = sizeof(T) == 8 ? reinterpret_cast<T*>(gV64) : reinterpret_cast<T*>(w + L.gv);
+    const size_t bytes = (size_t)n * sizeof(T);
+    HIPCHK(h, hipMemsetAsync(rb, 0, bytes, h->stream));
+    HIPCHK(h, hipMemsetAsync(ia, 0, bytes, h->stream));
+    HIPCHK(h, hipMemsetAsync(gV64, 0, (size_t)n * sizeof(double), h->stream));
+    if (sizeof(T) != 8) HIPCHK(h, hipMemsetAsync(gv, 0, bytes, h->stream));
+    const int64_t hrec = d.record_every;
+    const long poff = (long)d.k_det * nxy;
+    const unsigned gi = (unsigned)((nxy + 255) / 256);
+    auto inject = [&](int64_t lev, const T* Rm, const T* Im) -> tdse_status {
+        if (hrec <= 0 || lev % hrec != 0) return TDSE_OK;
+        hipLaunchKernelGGL(adjoint_inject_kernel<T>, dim3(gi), dim3(256), 0, h->stream, rb, ia, Rm,
+                           Im, rho_bar + (lev / hrec) * nxy, poff, nxy);
+        return hip_check(h, hipGetLastError(), "inject launch");
+    };
+    bool first = true;
+    for (int64_t c = (int64_t)L.nck - 1; c >= 0; --c) {
+        const int64_t s0 = c * K;
+        const int64_t s1 = std::min<int64_t>(s0 + K, N);
+        HIPCHK(h, hipMemcpyAsync(sg(0, 0), ck(c, 0), bytes, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(sg(0, 1), ck(c, 1), bytes, hipMemcpyDeviceToDevice, h->stream));
+        for (int64_t m = s0; m < s1; ++m) {
+            tdse_status st = forward_step_explicit(h, sg(m - s0, 0), sg(m - s0, 1),
+                                                   sg(m - s0 + 1, 0), sg(m - s0 + 1, 1));
+            if (st != TDSE_OK) return st;
+        }
+        if (first) {
+            tdse_status st = inject(N, sg(s1 - s0, 0), sg(s1 - s0, 1));
+            if (st != TDSE_OK) return st;
+            first = false;
+        }
+        for (int64_t m = s1 - 1; m >= s0; --m) {
+            const T* Rn = sg(m - s0, 0);
+            const T* Ih = sg(m - s0 + 1, 1);
+            tdse_status st = launch_adj<T>(h, 0, make_adj_args<T>(h, rb, ia, nullptr, nullptr, nullptr, nullptr));
+            if (st != TDSE_OK) return st;
+            st = launch_adj<T>(h, 1, make_adj_args<T>(h, ia, rb, ib, Rn, Ih, gv));
+            if (st != TDSE_OK) return st;
+            std::swap(ia, ib);
+            st = inject(m, sg(m - s0, 0), sg(m - s0, 1));
+            if (st != TDSE_OK) return st;
+        }
+        if (sizeof(T) != 8) {
+            hipLaunchKernelGGL(adjoint_fold_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                               h->stream, gV64, gv, n);
+            HIPCHK(h, hipGetLastError());
+        }
+    }
+    if (gR0) HIPCHK(h, hipMemcpyAsync(gR0, rb, bytes, hipMemcpyDeviceToDevice, h->stream));
+    if (gI0) HIPCHK(h, hipMemcpyAsync(gI0, ia, bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return TDSE_OK;
+}
+
 
 void default_fused_tile(tdse_ctx* h) {
     const tdse_desc& d = h->d;
@@ -595,6 +773,7 @@ tdse_status tdse_bind(tdse_handle h, void* psi_r, void* psi_i, void* v, void* wo
     h->R2 = nullptr;
     h->I2 = nullptr;
     h->fused = false;
+    h->adj_ws = nullptr;
     h->ws = workspace;
     h->ws_bytes = workspace_bytes;
     h->rec = records;
@@ -946,6 +1125,14 @@ tdse_status tdse_step(tdse_handle h, int64_t n) {
     const TileDims td = tile_dims(h, h->rows, h->waves, h->zc);
     for (int64_t it = 0; it < n; ++it) {
         const int64_t s = h->step;
+        if (h->adj_ws && s < h->adj_N && s % h->adj_K == 0) {
+            // checkpoint of level s for the adjoint
+            const AdjLayout L = adj_layout(d, h->adj_N, h->adj_K);
+            char* w = static_cast<char*>(h->adj_ws) + L.ckpt + 2 * (size_t)(s / h->adj_K) * L.arr;
+            const size_t bytes = (size_t)d.nx * d.ny * d.nz * elem_size(d);
+            HIPCHK(h, hipMemcpyAsync(w, h->R, bytes, hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(h, hipMemcpyAsync(w + L.arr, h->I, bytes, hipMemcpyDeviceToDevice, h->stream));
+        }
         const bool record = hrec > 0 && ((s + 1) % hrec == 0);
         const long rec_idx = record ? (long)((s + 1) / hrec) : 0;
         const bool fused = it < n_fused;
@@ -1056,6 +1243,7 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
     out->fused = (h->fused && h->R2) ? 1 : 0;
     out->fused_rows = h->fm;
     out->fused_zc = h->fzc;
+    out->fused_prefetch = h->fpf ? 1 : 0;
     out->vec_elems = h->W;
     out->vec_groups = h->G;
     out->lanes = h->NL;
@@ -1085,6 +1273,7 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
     h->fused = t->fused != 0;
     h->fm = t->fused_rows;
     h->fzc = fzc;
+    h->fpf = t->fused_prefetch != 0;
     return TDSE_OK;
 }
 
@@ -1100,6 +1289,116 @@ tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2) {
     h->R2 = psi_r2;
     h->I2 = psi_i2;
     h->fused = fused_dims(h, h->fm, h->fzc).ok;
+    return TDSE_OK;
+}
+
+tdse_status tdse_adjoint_workspace_size(const tdse_desc* d, int64_t n_steps, int32_t ckpt_every,
+                                        size_t* bytes) {
+    tdse_status s = tdse_validate_desc(d);
+    if (s != TDSE_OK) return s;
+    if (!bytes || n_steps < 1 || ckpt_every < 1) return TDSE_ERR_ARG;
+    *bytes = adj_layout(*d, n_steps, ckpt_every).total;
+    return TDSE_OK;
+}
+
+tdse_status tdse_bind_adjoint(tdse_handle h, void* adj_ws, size_t bytes, int64_t n_steps,
+                              int32_t ckpt_every) {
+    if (!h) return TDSE_ERR_ARG;
+    if (!adj_ws) {
+        h->adj_ws = nullptr;
+        return TDSE_OK;
+    }
+    if (!h->bound) return fail(h, TDSE_ERR_STATE, "bind before bind_adjoint");
+    if (n_steps < 1 || ckpt_every < 1) return fail(h, TDSE_ERR_ARG, "n_steps and ckpt_every must be >= 1");
+    if (!aligned(adj_ws)) return fail(h, TDSE_ERR_ARG, "adjoint workspace not 256-byte aligned");
+    if (bytes < adj_layout(h->d, n_steps, ckpt_every).total)
+        return fail(h, TDSE_ERR_ARG, "adjoint workspace too small");
+    if (h->step != 0) return fail(h, TDSE_ERR_STATE, "bind the adjoint before stepping from level 0");
+    h->adj_ws = adj_ws;
+    h->adj_N = n_steps;
+    h->adj_K = ckpt_every;
+    return TDSE_OK;
+}
+
+tdse_status tdse_adjoint(tdse_handle h, const void* dL_drho, double* dL_dV, void* dL_dR0,
+                         void* dL_dI0) {
+    if (!h || !dL_dV) return TDSE_ERR_ARG;
+    if (!h->adj_ws) return fail(h, TDSE_ERR_STATE, "tdse_bind_adjoint first");
+    if (h->step != h->adj_N) return fail(h, TDSE_ERR_STATE, "run exactly n_steps forward before the adjoint");
+    if (h->d.record_every > 0 && !dL_drho) return fail(h, TDSE_ERR_ARG, "dL_drho required");
+    if (h->pending != 0) return fail(h, TDSE_ERR_STATE, "pending flux partials");
+    if (h->d.precision == TDSE_F64)
+        return run_adjoint<double>(h, static_cast<const double*>(dL_drho), dL_dV,
+                                   static_cast<double*>(dL_dR0), static_cast<double*>(dL_dI0));
+    return run_adjoint<float>(h, static_cast<const float*>(dL_drho), dL_dV,
+                              static_cast<float*>(dL_dR0), static_cast<float*>(dL_dI0));
+}
+
+tdse_status tdse_potential_vjp(tdse_handle h, const tdse_atom* atoms, int64_t n,
+                               const tdse_pot_params* p, const double* dL_dV, double* dL_dpos,
+                               double* dL_damp) {
+    if (!h || !p || !dL_dV || n < 0 || (n > 0 && (!atoms || !dL_dpos || !dL_damp))) return TDSE_ERR_ARG;
+    if (n == 0) return TDSE_OK;
+    const tdse_desc& d = h->d;
+    if (!(p->cutoff > 0) || !(p->soft >= 0) || !(p->kappa > 0) || !(p->a0 > 0))
+        return fail(h, TDSE_ERR_ARG, "bad potential parameters");
+    std::vector<double> flat((size_t)n * 5);
+    for (int64_t a = 0; a < n; ++a) {
+        flat[5 * a + 0] = atoms[a].x;
+        flat[5 * a + 1] = atoms[a].y;
+        flat[5 * a + 2] = atoms[a].z;
+        flat[5 * a + 3] = atoms[a].Z;
+        flat[5 * a + 4] = atoms[a].amp;
+        if (!(atoms[a].Z > 0)) return fail(h, TDSE_ERR_ARG, "bad atom");
+    }
+    double* d_atoms = nullptr;
+    double* d_out = nullptr;
+    if (hipMalloc(&d_atoms, flat.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_out, (size_t)n * 4 * sizeof(double)) != hipSuccess) {
+        if (d_atoms) (void)hipFree(d_atoms);
+        return fail(h, TDSE_ERR_OOM, "vjp temporaries");
+    }
+    hipError_t e = hipMemcpyAsync(d_atoms, flat.data(), flat.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, h->stream);
+    VjpArgs a;
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    a.dx = d.dx;
+    a.dy = d.dy;
+    a.dz = d.dz;
+    a.Lx = d.nx * d.dx;
+    a.Ly = d.ny * d.dy;
+    a.Lz = d.nz * d.dz;
+    a.bcx = d.bc[0] == TDSE_BC_ZERO;
+    a.bcy = d.bc[1] == TDSE_BC_ZERO;
+    a.bcz = d.bc[2] == TDSE_BC_ZERO;
+    a.screened = p->screened;
+    a.atoms = d_atoms;
+    a.gV = dL_dV;
+    a.soft = p->soft;
+    a.cutoff = p->cutoff;
+    a.kappa = p->kappa;
+    a.a0 = p->a0;
+    a.out = d_out;
+    std::vector<double> out((size_t)n * 4);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(potential_vjp_kernel, dim3((unsigned)n), dim3(256), 0, h->stream, a);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out.data(), d_out, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d_atoms);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_check(h, e, "potential_vjp");
+    for (int64_t a2 = 0; a2 < n; ++a2) {
+        dL_dpos[3 * a2 + 0] = out[4 * a2 + 0];
+        dL_dpos[3 * a2 + 1] = out[4 * a2 + 1];
+        dL_dpos[3 * a2 + 2] = out[4 * a2 + 2];
+        dL_damp[a2] = out[4 * a2 + 3];
+    }
     return TDSE_OK;
 }
 

@@ -31,7 +31,8 @@ EXPORTS = [
     "tdse_build_potential", "tdse_set_cap", "tdse_set_cap_quadratic", "tdse_finalize_setup",
     "tdse_init_gaussian", "tdse_set_state", "tdse_get_state", "tdse_step", "tdse_detect",
     "tdse_copy_scalars", "tdse_set_timing", "tdse_timing_read", "tdse_get_tile", "tdse_set_tile",
-    "tdse_bind_pingpong",
+    "tdse_bind_pingpong", "tdse_adjoint_workspace_size", "tdse_bind_adjoint", "tdse_adjoint",
+    "tdse_potential_vjp",
 ]
 
 
@@ -73,7 +74,8 @@ class DetectOut(ctypes.Structure):
 class Tile(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("waves", ctypes.c_int32), ("zc", ctypes.c_int32),
                 ("fused", ctypes.c_int32), ("fused_rows", ctypes.c_int32),
-                ("fused_zc", ctypes.c_int32), ("vec_elems", ctypes.c_int32),
+                ("fused_zc", ctypes.c_int32), ("fused_prefetch", ctypes.c_int32),
+                ("vec_elems", ctypes.c_int32),
                 ("vec_groups", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("band_rows", ctypes.c_int32)]
 
@@ -118,6 +120,12 @@ def load():
         "tdse_set_timing": (i32, [vp, i32]),
         "tdse_timing_read": (i32, [vp, dp, ctypes.POINTER(i64)]),
         "tdse_bind_pingpong": (i32, [vp, vp, vp]),
+        "tdse_adjoint_workspace_size": (i32, [ctypes.POINTER(Desc), i64, i32,
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+        "tdse_bind_adjoint": (i32, [vp, vp, ctypes.c_size_t, i64, i32]),
+        "tdse_adjoint": (i32, [vp, vp, vp, vp, vp]),
+        "tdse_potential_vjp": (i32, [vp, ctypes.POINTER(Atom), i64, ctypes.POINTER(PotParams), vp,
+                                     dp, dp]),
         "tdse_get_tile": (i32, [vp, ctypes.POINTER(Tile)]),
         "tdse_set_tile": (i32, [vp, ctypes.POINTER(Tile)]),
     }
@@ -312,6 +320,47 @@ class Sim:
         n = d.n_records
         return (self.records[:n].double().cpu().numpy(), self.scalars[:n].cpu().numpy())
 
+    # -- adjoint -----------------------------------------------------------
+    def bind_adjoint(self, n_steps: int, ckpt_every: int = 100):
+        """Allocate and attach the adjoint workspace; the next n_steps steps
+        (from level 0) store checkpoints every ckpt_every steps."""
+        n = ctypes.c_size_t()
+        self._check(self.lib.tdse_adjoint_workspace_size(ctypes.byref(self.desc), int(n_steps),
+                                                         int(ckpt_every), ctypes.byref(n)), None)
+        self.adj_ws = self.torch.empty(int(n.value), dtype=self.torch.uint8, device=self.device)
+        self._check(self.lib.tdse_bind_adjoint(self.h, self.adj_ws.data_ptr(), self.adj_ws.numel(),
+                                               int(n_steps), int(ckpt_every)))
+
+    def adjoint(self, dL_drho):
+        """(dL/dV [nz][ny][nx] float64, dL/dpsiR^0, dL/dpsiI^{-1/2}) for a loss
+        whose derivative with respect to the records is dL_drho."""
+        t = self.torch
+        rb = dL_drho.to(self.device, self.dtype).contiguous()
+        shape = (self.desc.nz, self.desc.ny, self.desc.nx)
+        gV = t.empty(shape, dtype=t.float64, device=self.device)
+        gR = t.empty(shape, dtype=self.dtype, device=self.device)
+        gI = t.empty(shape, dtype=self.dtype, device=self.device)
+        self._check(self.lib.tdse_adjoint(self.h, rb.data_ptr(), gV.data_ptr(), gR.data_ptr(),
+                                          gI.data_ptr()))
+        return gV, gR, gI
+
+    def potential_vjp(self, atoms: np.ndarray, dL_dV, soft=0.1, cutoff=6.0,
+                      kappa=14.3996454784, a0=0.529177210903, screened=True):
+        """(dL/dpositions [n][3], dL/damplitudes [n]) as numpy arrays."""
+        atoms = np.ascontiguousarray(atoms, dtype=np.float64).reshape(-1, 5)
+        arr = (Atom * max(len(atoms), 1))()
+        for i, a in enumerate(atoms):
+            arr[i] = Atom(*[float(x) for x in a])
+        p = PotParams(float(soft), float(cutoff), float(kappa), float(a0), int(bool(screened)), 0)
+        gv = dL_dV.to(self.device, self.torch.float64).contiguous()
+        dpos = np.zeros((len(atoms), 3))
+        damp = np.zeros(len(atoms))
+        dp_ = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.tdse_potential_vjp(self.h, arr, len(atoms), ctypes.byref(p),
+                                                gv.data_ptr(), dpos.ctypes.data_as(dp_),
+                                                damp.ctypes.data_as(dp_)))
+        return dpos, damp
+
     # -- measurement / tuning ------------------------------------------------
     def set_timing(self, on: bool):
         self._check(self.lib.tdse_set_timing(self.h, int(bool(on))))
@@ -329,10 +378,11 @@ class Sim:
         return t
 
     def set_tile(self, rows=None, waves=None, zc=None, fused=None, fused_rows=None,
-                 fused_zc=None):
+                 fused_zc=None, fused_prefetch=None):
         t = self.get_tile()
         for name, v in (("rows", rows), ("waves", waves), ("zc", zc), ("fused", fused),
-                        ("fused_rows", fused_rows), ("fused_zc", fused_zc)):
+                        ("fused_rows", fused_rows), ("fused_zc", fused_zc),
+                        ("fused_prefetch", fused_prefetch)):
             if v is not None:
                 setattr(t, name, int(v))
         self._check(self.lib.tdse_set_tile(self.h, ctypes.byref(t)))

@@ -39,10 +39,11 @@ def candidates(nz: int):
             for zc in (8, 16, 32, 64, 128, 256):
                 if zc <= nz:
                     yield dict(fused=0, rows=rows, waves=waves, zc=zc)
-    for fr in (2, 3, 4, 6):
-        for zc in (16, 32, 64, 128, 256):
-            if zc <= nz:
-                yield dict(fused=1, fused_rows=fr, fused_zc=zc)
+    for pf in (1, 0):
+        for fr in (2, 3, 4, 6):
+            for zc in (16, 32, 64, 128, 256):
+                if zc <= nz:
+                    yield dict(fused=1, fused_rows=fr, fused_zc=zc, fused_prefetch=pf)
 
 
 def autotune(sim, steps: int = 20, reps: int = 3, cands=None):

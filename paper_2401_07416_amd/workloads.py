@@ -151,6 +151,29 @@ def c3_headline(seed: int = 2401) -> Workload:
                     dt_frac=0.9, steps=10000, k_det=250, record_every=50)
 
 
+def c5_adjoint(seed: int = 5, nxy: int = 128, nz: int = 256, steps: int = 4000) -> Workload:
+    """Adjoint-gradient workload: 128x128x256 (25.6 x 25.6 x 51.2 A), FP32
+    forward, a 3 x 8 x 8 slab at a = 3.2 A (top layer z = 18 A, layers 2.5 A
+    apart, Z in {6, 8, 14}), amplitudes 1, 24-plane CAP, 10 eV packet with
+    sigma = 4 A at z = 34 A, detection plane at z = 26 A every 20 steps,
+    4000 steps with checkpoints every 100."""
+    L = 0.2 * nxy
+    atoms = slab_atoms(seed, 8, 8, L, L, z_top=18.0)
+    return Workload(name=f"adjoint-{nxy}x{nxy}x{nz}", nx=nxy, ny=nxy, nz=nz, dx=0.2, dy=0.2,
+                    dz=0.2, hbar=HBAR_EV_FS, mass=ME_EV_FS2_A2, atoms=atoms,
+                    cap=(24, 24, 50.0), r0=(L / 2, L / 2, 34.0), sigma=4.0, energy=10.0,
+                    dt_frac=0.9, steps=steps, k_det=130, record_every=20)
+
+
+def perturbed_positions(atoms: np.ndarray, seed: int = 6, scale: float = 0.05) -> np.ndarray:
+    """The atom list with every coordinate moved by N(0, scale) (the target
+    configuration of the adjoint workload)."""
+    rng = np.random.default_rng(seed)
+    out = atoms.copy()
+    out[:, 0:3] += rng.normal(0.0, scale, size=(atoms.shape[0], 3))
+    return out
+
+
 def ragged(precision: str = "f64", seed: int = 11) -> Workload:
     """Odd, non-power-of-two box (37 x 29 x 53) that leaves ragged tiles in
     every direction; a few atoms, a CAP and a packet."""
@@ -180,4 +203,5 @@ ALL = {
     "surface-reduced": c2_reduced,
     "headline": c3_headline,
     "ragged": ragged,
+    "adjoint": c5_adjoint,
 }

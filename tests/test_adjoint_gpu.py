@@ -1,0 +1,186 @@
+"""GPU adjoint: the library's reverse sweep against the oracle's adjoint and
+against central finite differences of the GPU forward run (arXiv 2401.07416
+section 2.1, eqs. (8)-(10), (15); the gradient is of a loss of the detection
+records).  Tolerances: FP64 gradient vs FP64 oracle adjoint <= 1e-10
+(max-norm relative); FP32 gradient vs FP64 oracle <= 2e-3 (relative L2);
+FP64 end-to-end gradient vs central differences <= 1e-5 relative."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2401_07416_amd import autograd as tag
+from paper_2401_07416_amd import tdse, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_problem(seed=0):
+    """Random (seeded) potential, state and record cotangent on a box with a
+    CAP: inputs only, each side forms its own coefficients and time step."""
+    nx, ny, nz = 16, 12, 40
+    sp = (0.22, 0.25, 0.2)
+    hbar, mass = 0.6582119569, 0.0568563
+    rng = np.random.default_rng(seed)
+    V = -30.0 * np.abs(rng.standard_normal((nz, ny, nx)))
+    R0, I0 = rng.standard_normal((nz, ny, nx)), rng.standard_normal((nz, ny, nx))
+    cap = (5, 4, 40.0)
+    h, kdet, N, K = 4, 22, 61, 7
+    rho_bar = rng.standard_normal((N // h + 1, ny, nx))
+    return dict(shape=(nx, ny, nz), sp=sp, hbar=hbar, mass=mass, V=V, R0=R0, I0=I0, cap=cap,
+                h=h, kdet=kdet, N=N, K=K, rho_bar=rho_bar)
+
+
+def oracle_adjoint(p):
+    g = oracle.Grid(*p["shape"], *p["sp"], hbar=p["hbar"], mass=p["mass"])
+    dt = 0.9 * g.hbar / oracle.emax(g, p["V"])
+    W = oracle.cap_quadratic(p["shape"][2], *p["cap"])
+    s = oracle.Sim(g, p["V"], p["R0"], p["I0"], dt, W=W, k_det=p["kdet"], record_every=p["h"],
+                   max_records=p["N"] // p["h"] + 1)
+    return s.adjoint(p["N"], p["rho_bar"], ckpt_every=p["K"]), dt
+
+
+def gpu_adjoint(p, prec, pingpong=True):
+    nx, ny, nz = p["shape"]
+    d = tdse.make_desc(nx, ny, nz, *p["sp"], hbar=p["hbar"], mass=p["mass"], dt_frac=0.9,
+                       precision=prec, k_det=p["kdet"], record_every=p["h"],
+                       max_records=p["N"] // p["h"] + 1)
+    s = tdse.Sim(d, pingpong=pingpong)
+    s.v.copy_(torch.from_numpy(p["V"]))
+    s.set_cap_quadratic(*p["cap"])
+    dt, _ = s.finalize()
+    s.set_state(torch.from_numpy(p["R0"]), torch.from_numpy(p["I0"]), step=0)
+    s.bind_adjoint(p["N"], p["K"])
+    s.step(p["N"])
+    gV, gR, gI = s.adjoint(torch.from_numpy(p["rho_bar"]))
+    return (gV.cpu().numpy(), gR.double().cpu().numpy(), gI.double().cpu().numpy()), dt
+
+
+@pytest.mark.parametrize("pp", [True, False], ids=["onepass", "twopass"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_matches_oracle(prec, pp):
+    p = small_problem()
+    say("adjoint vs oracle", prec, "one-pass" if pp else "two-pass")
+    (rV, rR, rI), dt_o = oracle_adjoint(p)
+    (gV, gR, gI), dt_g = gpu_adjoint(p, prec, pingpong=pp)
+    assert dt_g == pytest.approx(dt_o, rel=1e-13 if prec == "f64" else 1e-6)
+    for got, ref, name in ((gV, rV, "dL/dV"), (gR, rR, "dL/dR0"), (gI, rI, "dL/dI0")):
+        if prec == "f64":
+            e = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+            say(name, "max rel", e)
+            assert e <= 1e-10
+        else:
+            e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            say(name, "rel L2", e)
+            assert e <= 2e-3
+
+
+def test_potential_vjp_matches_oracle():
+    w = workloads.c5_adjoint(nxy=32, nz=64)
+    say("potential vjp")
+    g = oracle.Grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass)
+    gv = np.random.default_rng(3).standard_normal(g.shape)
+    rpos, ramp = oracle.potential_vjp(g, w.atoms, gv, soft=w.soft, cutoff=w.cutoff)
+    d = tdse.make_desc(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, precision="f64")
+    s = tdse.Sim(d, pingpong=False)
+    dpos, damp = s.potential_vjp(w.atoms, torch.from_numpy(gv), soft=w.soft, cutoff=w.cutoff)
+    np.testing.assert_allclose(dpos, rpos, rtol=1e-11, atol=1e-11 * np.max(np.abs(rpos)))
+    np.testing.assert_allclose(damp, ramp, rtol=1e-11, atol=1e-11 * np.max(np.abs(ramp)))
+
+
+def _loss(problem, positions, amps, target):
+    P = tag.detection_integral(positions, amps, problem)
+    return torch.sum((P - target) ** 2)
+
+
+def test_autograd_gradient_matches_finite_differences():
+    """Reduced adjoint workload (32 x 32 x 64 box, 400 steps, checkpoints every
+    50), FP64: dL/dpositions and dL/damplitudes of L = sum (P - T)^2 against
+    central differences with h = 1e-4 A (positions) and 1e-5 (amplitudes)."""
+    w = workloads.c5_adjoint(nxy=32, nz=64, steps=400).with_(r0=(3.2, 3.2, 9.0), sigma=1.5,
+                                                             k_det=40, cap=(8, 8, 50.0))
+    w = w.with_(atoms=workloads.slab_atoms(5, 3, 3, 6.4, 6.4, z_top=6.0))
+    say("autograd fd", w.name)
+    prob = tag.problem_for(w, precision="f64", ckpt_every=50)
+    tgt_atoms = workloads.perturbed_positions(w.atoms)
+    with torch.no_grad():
+        T = tag.detection_integral(torch.from_numpy(tgt_atoms[:, :3]),
+                                   torch.from_numpy(tgt_atoms[:, 4]), prob)
+    pos = torch.from_numpy(w.atoms[:, :3].copy()).requires_grad_(True)
+    amp = torch.from_numpy(w.atoms[:, 4].copy()).requires_grad_(True)
+    L = _loss(prob, pos, amp, T)
+    L.backward()
+    gpos, gamp = pos.grad.numpy(), amp.grad.numpy()
+    assert np.max(np.abs(gpos)) > 0
+    for a, c in [(0, 2), (4, 0), (4, 2), (7, 1), (13, 2), (22, 0)]:
+        hh = 1e-4
+        p1 = w.atoms[:, :3].copy()
+        p1[a, c] += hh
+        p2 = w.atoms[:, :3].copy()
+        p2[a, c] -= hh
+        with torch.no_grad():
+            lp = _loss(prob, torch.from_numpy(p1), torch.from_numpy(w.atoms[:, 4]), T).item()
+            lm = _loss(prob, torch.from_numpy(p2), torch.from_numpy(w.atoms[:, 4]), T).item()
+        fd = (lp - lm) / (2 * hh)
+        say("pos", a, c, gpos[a, c], fd)
+        assert gpos[a, c] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.max(np.abs(gpos)))
+    for a in (1, 9, 20):
+        hh = 1e-5
+        a1 = w.atoms[:, 4].copy()
+        a1[a] += hh
+        a2 = w.atoms[:, 4].copy()
+        a2[a] -= hh
+        with torch.no_grad():
+            lp = _loss(prob, torch.from_numpy(w.atoms[:, :3]), torch.from_numpy(a1), T).item()
+            lm = _loss(prob, torch.from_numpy(w.atoms[:, :3]), torch.from_numpy(a2), T).item()
+        fd = (lp - lm) / (2 * hh)
+        say("amp", a, gamp[a], fd)
+        assert gamp[a] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.max(np.abs(gamp)))
+
+
+def test_full_adjoint_workload_fp32_against_fp64():
+    """128 x 128 x 256, 4000 steps, checkpoints every 100: the FP32 gradient
+    with respect to the 192 positions and amplitudes against the FP64 one,
+    and the FP64 one against central differences on a seeded subset."""
+    w = workloads.c5_adjoint()
+    say("adjoint workload 128x128x256 4000 steps")
+    tgt = workloads.perturbed_positions(w.atoms)
+    grads = {}
+    for prec in ("f64", "f32"):
+        prob = tag.problem_for(w, precision=prec, ckpt_every=100)
+        with torch.no_grad():
+            T = tag.detection_integral(torch.from_numpy(tgt[:, :3]), torch.from_numpy(tgt[:, 4]),
+                                       prob)
+        pos = torch.from_numpy(w.atoms[:, :3].copy()).requires_grad_(True)
+        amp = torch.from_numpy(w.atoms[:, 4].copy()).requires_grad_(True)
+        L = _loss(prob, pos, amp, T)
+        L.backward()
+        grads[prec] = (pos.grad.numpy(), amp.grad.numpy(), prob, T)
+        say(prec, "loss", L.item())
+    g64, g32 = grads["f64"], grads["f32"]
+    e_pos = np.linalg.norm(g32[0] - g64[0]) / np.linalg.norm(g64[0])
+    e_amp = np.linalg.norm(g32[1] - g64[1]) / np.linalg.norm(g64[1])
+    say("fp32 vs fp64 gradient rel L2", e_pos, e_amp)
+    assert e_pos <= 1e-3 and e_amp <= 1e-3
+    prob, T = g64[2], g64[3]
+    rng = np.random.default_rng(12)
+    for a in rng.choice(len(w.atoms), 4, replace=False):
+        for c in range(3):
+            hh = 1e-4
+            p1 = w.atoms[:, :3].copy()
+            p1[a, c] += hh
+            p2 = w.atoms[:, :3].copy()
+            p2[a, c] -= hh
+            with torch.no_grad():
+                lp = _loss(prob, torch.from_numpy(p1), torch.from_numpy(w.atoms[:, 4]), T).item()
+                lm = _loss(prob, torch.from_numpy(p2), torch.from_numpy(w.atoms[:, 4]), T).item()
+            fd = (lp - lm) / (2 * hh)
+            say("pos", a, c, g64[0][a, c], fd)
+            assert g64[0][a, c] == pytest.approx(fd, rel=1e-4, abs=1e-6 * np.max(np.abs(g64[0])))

@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--tile", default=None,
                    help='JSON dict of Sim.set_tile keywords (default: tuned table)')
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-secondary", action="store_true",
+                   help="skip the FP64, adjoint and batched measurements")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU time of the timed oracle sample")
     p.add_argument("--cpu-planes", type=int, default=48)
@@ -114,6 +116,118 @@ def cpu_baseline(w, seconds, planes):
             "sample": f"FP64 oracle, {w.nx}x{w.ny}x{planes}-plane slab of the {w.name} grid "
                       f"around the packet, {steps} steps, {el:.1f} s",
             "ns_per_cell_step": el / (cells * steps) * 1e9}
+
+
+def time_steps(sim, n):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    sim.step(n)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def secondary_fp64(steps=400):
+    """FP64 throughput on the 256x256x512 surface grid (one-pass step)."""
+    from paper_2401_07416_amd import tdse, tuning, workloads
+    w = workloads.c2_surface()
+    sim = tdse.sim_from_workload(w, precision="f64", steps=steps + 20)
+    t = tuning.tile_for(w, "f64")
+    if t:
+        sim.set_tile(**t)
+    sim.step(20)
+    ms = time_steps(sim, steps)
+    v = w.cells * steps / (ms * 1e-3) / 1e9
+    return {"workload": w.name + " FP64", "value": round(v, 2), "unit": "Gcell-steps/s",
+            "ms_per_step": round(ms / steps, 4),
+            "hbm_gbs_alg": round(v * 40, 1), "steps": steps}
+
+
+def secondary_adjoint():
+    """Plain forward, checkpointed forward and adjoint of the 128x128x256,
+    4000-step gradient workload in FP32, timed with HIP events."""
+    import torch
+
+    from paper_2401_07416_amd import autograd as tag
+    from paper_2401_07416_amd import workloads
+    w = workloads.c5_adjoint()
+    prob = tag.problem_for(w, precision="f32", ckpt_every=100)
+
+    def fresh():
+        s = prob.make_sim()
+        s.build_potential(w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0)
+        s.set_cap_quadratic(*w.cap)
+        s.finalize()
+        s.init_gaussian(w.r0, prob.k0(), w.sigma)
+        return s
+
+    warm = fresh()
+    time_steps(warm, 200)
+    del warm
+    ms_plain = time_steps(fresh(), w.steps)
+    sim = fresh()
+    sim.bind_adjoint(w.steps, 100)
+    ms_fwd = time_steps(sim, w.steps)
+    rb = torch.full((w.n_records(), w.ny, w.nx), 1e-3, dtype=torch.float32, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    gV, _, _ = sim.adjoint(rb)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_adj = e0.elapsed_time(e1)
+    cs = w.cells * w.steps
+    return {"workload": w.name + " FP32, 4000 steps, checkpoints every 100",
+            "plain_forward_ms": round(ms_plain, 2),
+            "checkpointed_forward_ms": round(ms_fwd, 2), "adjoint_ms": round(ms_adj, 2),
+            "adjoint_over_plain": round((ms_fwd + ms_adj) / ms_plain, 2),
+            "plain_gcell_steps_s": round(cs / (ms_plain * 1e-3) / 1e9, 1),
+            "backward_gcell_steps_s": round(cs / (ms_adj * 1e-3) / 1e9, 1),
+            "grad_finite": bool(torch.isfinite(gV).all())}
+
+
+def secondary_batch(n_configs=64, batch_steps=400, single_steps=100):
+    """The 64 uneven film grids stepped as one batch (one launch per step,
+    a graph per 50-step record interval) against the same grids run one at
+    a time with the plain path, FP32."""
+    import torch
+
+    from paper_2401_07416_amd import tdse, workloads
+    ws = workloads.c4_batch(n_configs, steps=batch_steps + single_steps + 100)
+    b = tdse.batch_from_workloads(ws, precision="f32", steps=batch_steps + single_steps + 100)
+    b.prepare()
+    b.run(50)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.run(batch_steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    cells = sum(w.cells for w in ws)
+    ok = all(st == tdse.OK for st in b.status())
+    ms_s = 0.0
+    with torch.cuda.stream(b.stream):
+        for m in b.members:
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(b.stream)
+            m.step(single_steps)
+            a1.record(b.stream)
+            a1.synchronize()
+            ms_s += a0.elapsed_time(a1)
+    vb = cells * batch_steps / (ms_b * 1e-3) / 1e9
+    vs = cells * single_steps / (ms_s * 1e-3) / 1e9
+    b.close()
+    return {"workload": f"{n_configs} film grids 128^2x256..256^2x512, {cells} cells, FP32",
+            "batched_gcell_steps_s": round(vb, 1), "one_at_a_time_gcell_steps_s": round(vs, 1),
+            "batched_over_plain": round(vb / vs, 3), "status_ok": ok,
+            "note": "working set 21 GB >> 256 MB MALL"}
 
 
 def copy_probe():
@@ -209,6 +323,15 @@ def main():
         "hbm_bytes_per_cell_step_alg": bytes_per_cell_step,
         "hbm_gbs_whole_step": round(value * bytes_per_cell_step, 1),
     }
+    if not a.no_secondary:
+        sec = {}
+        for name, fn in (("fp64", secondary_fp64), ("adjoint", secondary_adjoint),
+                         ("batched", secondary_batch)):
+            try:
+                sec[name] = fn()
+            except Exception as ex:  # reported, never hidden
+                sec[name] = {"error": repr(ex)}
+        out["secondary"] = sec
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, a.cpu_planes)
         out["cpu_baseline"]["speedup_gpu_over_cpu"] = round(value / out["cpu_baseline"]["value"], 1)

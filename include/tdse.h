@@ -293,6 +293,40 @@ tdse_status tdse_potential_vjp(tdse_handle h, const tdse_atom* atoms, int64_t n,
                                const tdse_pot_params* p, const double* dL_dV, double* dL_dpos,
                                double* dL_damp);
 
+/* Batches: many grids of uneven size stepped together, one launch per step
+ * for all of them, the steps of one record interval captured in a HIP graph
+ * that is replayed (the data-generation use of section 3.2: many
+ * configurations, the same detection schedule).
+ *
+ * tdse_batch_create: one member handle per description (all with the same
+ * precision and record_every h, h even and <= 256; h = 0 runs intervals
+ * of 64 steps), all launching on `stream`, which must not be the null stream
+ * (graphs are captured on it).  Host memory only.
+ * tdse_batch_member: the i-th handle, set up with the single-grid calls
+ * (tdse_bind, tdse_bind_pingpong (required), potential, CAP, finalize,
+ * initial state); its outputs are read with tdse_detect as usual.
+ * tdse_batch_set_tile: one-pass tile shared by the members (fused_rows 2, 3,
+ * 4 or 6; fused_zc >= 1; prefetch flag); invalidates a prepared batch.
+ * tdse_batch_prepare: all members at the same record level; builds the
+ * device tables (a few KB, allocated here, freed by destroy or the next
+ * prepare) and captures the graph of one interval.
+ * tdse_batch_run: n steps, a multiple of the interval; asynchronous.
+ * tdse_batch_status: synchronise; per_config[i] = tdse_detect's status of
+ * member i (TDSE_ERR_NONFINITE flags a configuration whose sums went
+ * non-finite while the others finish); returns the first failure.
+ * tdse_batch_destroy: frees the tables, graph and member handles. */
+typedef struct tdse_batch_ctx* tdse_batch;
+
+tdse_status tdse_batch_create(const tdse_desc* descs, int32_t n, void* stream, tdse_batch* out);
+tdse_status tdse_batch_member(tdse_batch b, int32_t i, tdse_handle* h);
+tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc,
+                                int32_t prefetch);
+tdse_status tdse_batch_prepare(tdse_batch b);
+tdse_status tdse_batch_run(tdse_batch b, int64_t n);
+tdse_status tdse_batch_status(tdse_batch b, int32_t* per_config);
+const char* tdse_batch_last_error(tdse_batch b);
+tdse_status tdse_batch_destroy(tdse_batch b);
+
 /* Kernel timing for measurement: when enabled, each step kernel launch is
  * bracketed by HIP events on the handle's stream.  tdse_timing_read
  * synchronises and returns, per kernel kind (0: eq. (9) half-step, 1: eq. (8)

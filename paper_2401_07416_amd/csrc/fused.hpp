@@ -50,10 +50,13 @@ struct FusedArgs {
 // PF: issue the loads of the next plane (R three planes ahead, I^{n-1/2}
 // and V two ahead, the LDS halo rows) before the eq. (8) part of the
 // current plane, so their latency hides behind it.
+// The body of one workgroup of the one-pass step: logical workgroup L of
+// the grid described by a (z chunk L / nbands, band L % nbands), with the
+// dynamic LDS at smem_raw.
 template <typename T, int W, int M, bool REC, bool PF>
-__global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
+__device__ __forceinline__ void fused_step_body(const FusedArgs<T>& a, int L,
+                                                unsigned char* smem_raw) {
     using VT = vec_t<T, W>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     T* LR = reinterpret_cast<T*>(smem_raw);                  // [ty + 4][nx]
     T* LI = LR + (size_t)(a.ty + 4) * a.nx;                   // [2][ty + 2][nx]
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -63,7 +66,6 @@ __global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
     const int xs = tid - rs * a.tpr;       // x slot
     const bool live = rs < a.rpp;          // threads past the last full row idle
     const int x0 = (live ? xs : 0) * W;
-    const int L = xcd_remap(blockIdx.x, a.nwg);
     const int zchunk = L / a.nbands;
     const int band = L - zchunk * a.nbands;
     const int j0 = band * a.ty;
@@ -345,6 +347,48 @@ __global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
             if (tid == 0) a.part_plane[band] = sp;
         }
     }
+}
+
+template <typename T, int W, int M, bool REC, bool PF>
+__global__ __launch_bounds__(256) void fused_step_kernel(FusedArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    fused_step_body<T, W, M, REC, PF>(a, xcd_remap(blockIdx.x, a.nwg), smem_raw);
+}
+
+// Many grids in one launch.  cfg[c] is the step of configuration c from its
+// state pair 0 into pair 1 (parity 0) or back (parity 1); its workgroups are
+// wg_start[c] .. wg_start[c+1]-1 of the launch, the whole launch remapped so
+// that neighbouring tiles of one grid share an XCD.  Record slots come from
+// the device counter *rec_idx so a captured graph can be replayed.
+template <typename T>
+struct BatchStep {
+    const FusedArgs<T>* cfg;
+    const int* wg_start;
+    const long* rec_idx;
+    int n, total_wg, parity, flux_slot;
+};
+
+template <typename T, int W, int M, bool REC, bool PF>
+__global__ __launch_bounds__(256) void fused_batch_kernel(BatchStep<T> b) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int Lg = xcd_remap(blockIdx.x, b.total_wg);
+    int lo = 0, hi = b.n;  // wg_start[lo] <= Lg < wg_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (b.wg_start[mid] <= Lg) lo = mid; else hi = mid;
+    }
+    FusedArgs<T> a = b.cfg[lo];
+    if (b.parity) {
+        const T* r0 = a.R0;
+        const T* i0 = a.I0;
+        a.R0 = a.R1;
+        a.I0 = a.I1;
+        a.R1 = const_cast<T*>(r0);
+        a.I1 = const_cast<T*>(i0);
+    }
+    a.flux_slots += (long)b.flux_slot * 2 * a.nbands;
+    if (REC) a.rec_plane += (*b.rec_idx) * (long)a.nx * a.ny;
+    fused_step_body<T, W, M, REC, PF>(a, Lg - b.wg_start[lo], smem_raw);
 }
 
 }  // namespace tdse

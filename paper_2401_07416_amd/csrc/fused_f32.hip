@@ -47,4 +47,40 @@ hipError_t launch_fused_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t l
     }
 }
 
+namespace {
+
+template <int W, int M>
+hipError_t gob(bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st, const BatchStep<float>& b) {
+    if (pf) {
+        if (rec) hipLaunchKernelGGL((fused_batch_kernel<float, W, M, true, true>), grid, dim3(256), lds, st, b);
+        else hipLaunchKernelGGL((fused_batch_kernel<float, W, M, false, true>), grid, dim3(256), lds, st, b);
+    } else {
+        if (rec) hipLaunchKernelGGL((fused_batch_kernel<float, W, M, true, false>), grid, dim3(256), lds, st, b);
+        else hipLaunchKernelGGL((fused_batch_kernel<float, W, M, false, false>), grid, dim3(256), lds, st, b);
+    }
+    return hipGetLastError();
+}
+
+template <int W>
+hipError_t gob_m(int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+                 const BatchStep<float>& b) {
+    switch (m) {
+        case 2: return gob<W, 2>(rec, pf, grid, lds, st, b);
+        case 3: return gob<W, 3>(rec, pf, grid, lds, st, b);
+        case 4: return gob<W, 4>(rec, pf, grid, lds, st, b);
+        default: return gob<W, 6>(rec, pf, grid, lds, st, b);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fused_batch_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds,
+                                  hipStream_t st, const BatchStep<float>& b) {
+    switch (w) {
+        case 4: return gob_m<4>(m, rec, pf, grid, lds, st, b);
+        case 2: return gob_m<2>(m, rec, pf, grid, lds, st, b);
+        default: return gob_m<1>(m, rec, pf, grid, lds, st, b);
+    }
+}
+
 }  // namespace tdse

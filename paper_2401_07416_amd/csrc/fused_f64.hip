@@ -46,4 +46,39 @@ hipError_t launch_fused_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t l
     }
 }
 
+namespace {
+
+template <int W, int M>
+hipError_t gob(bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st, const BatchStep<double>& b) {
+    if (pf) {
+        if (rec) hipLaunchKernelGGL((fused_batch_kernel<double, W, M, true, true>), grid, dim3(256), lds, st, b);
+        else hipLaunchKernelGGL((fused_batch_kernel<double, W, M, false, true>), grid, dim3(256), lds, st, b);
+    } else {
+        if (rec) hipLaunchKernelGGL((fused_batch_kernel<double, W, M, true, false>), grid, dim3(256), lds, st, b);
+        else hipLaunchKernelGGL((fused_batch_kernel<double, W, M, false, false>), grid, dim3(256), lds, st, b);
+    }
+    return hipGetLastError();
+}
+
+template <int W>
+hipError_t gob_m(int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+                 const BatchStep<double>& b) {
+    switch (m) {
+        case 2: return gob<W, 2>(rec, pf, grid, lds, st, b);
+        case 3: return gob<W, 3>(rec, pf, grid, lds, st, b);
+        case 4: return gob<W, 4>(rec, pf, grid, lds, st, b);
+        default: return gob<W, 6>(rec, pf, grid, lds, st, b);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fused_batch_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds,
+                                  hipStream_t st, const BatchStep<double>& b) {
+    switch (w) {
+        case 2: return gob_m<2>(m, rec, pf, grid, lds, st, b);
+        default: return gob_m<1>(m, rec, pf, grid, lds, st, b);
+    }
+}
+
 }  // namespace tdse

@@ -39,7 +39,7 @@ struct FinArgs {
 
 // Folds the pending per-step flux partials into the accumulator in step
 // order and, on record steps, writes {plane_sum, naive_norm, Q, flux_acc}.
-__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+__device__ __forceinline__ void finalize_body(const FinArgs& a) {
     __shared__ double red[256];
     const int t = threadIdx.x;
     double acc = a.acc[0];
@@ -69,6 +69,29 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         }
     }
     if (t == 0) a.acc[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) { finalize_body(a); }
+
+// One workgroup per configuration of a batch; pending count, record flag and
+// the device record counter are shared by the launch.
+struct BatchFin {
+    const FinArgs* cfg;
+    const long* rec_idx;
+    int n_pending, record;
+};
+
+__global__ __launch_bounds__(256) void finalize_batch_kernel(BatchFin b) {
+    FinArgs a = b.cfg[blockIdx.x];
+    a.n_pending = b.n_pending;
+    a.record = b.record;
+    a.rec_idx = b.record ? *b.rec_idx : 0;
+    finalize_body(a);
+}
+
+// Advance the device record counter of a batch (one lane, vector store).
+__global__ void bump_counter_kernel(long* c) {
+    if (threadIdx.x == 0) c[0] = c[0] + 1;
 }
 
 // ---------------------------------------------------------------------------

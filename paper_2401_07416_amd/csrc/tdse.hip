@@ -77,6 +77,29 @@ struct tdse_ctx {
     size_t ev_used = 0;
 };
 
+// A batch: many handles stepped together by one launch per step, the steps
+// of one record interval captured in a HIP graph.
+struct tdse_batch_ctx {
+    std::vector<tdse_ctx*> members;
+    hipStream_t stream = nullptr;
+    int precision = TDSE_F32;
+    int64_t h = 0;       // record interval shared by the members
+    int S = 0;           // steps per graph replay
+    int W = 0, M = 4, zc = 64;
+    bool pf = true;
+    size_t lds = 0;
+    int total_wg = 0;
+    void* d_cfg = nullptr;     // FusedArgs<T>[n]
+    int* d_wg = nullptr;       // [n + 1]
+    long* d_rec = nullptr;     // record counter
+    void* d_fin = nullptr;     // FinArgs[n]
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool prepared = false;
+    int64_t step = 0;
+    std::string err;
+};
+
 namespace {
 
 constexpr size_t ALIGN = 256;
@@ -208,6 +231,10 @@ hipError_t launch_adjoint_f32(int w, int g, int phase, dim3 grid, dim3 block, hi
                               const AdjArgs<float>& a);
 hipError_t launch_adjoint_f64(int w, int g, int phase, dim3 grid, dim3 block, hipStream_t st,
                               const AdjArgs<double>& a);
+hipError_t launch_fused_batch_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds,
+                                  hipStream_t st, const BatchStep<float>& b);
+hipError_t launch_fused_batch_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds,
+                                  hipStream_t st, const BatchStep<double>& b);
 hipError_t launch_fused_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
                             const FusedArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
 }  // namespace tdse
@@ -644,6 +671,136 @@ void default_fused_tile(tdse_ctx* h) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+static tdse_status bfail(tdse_batch_ctx* b, tdse_status s, const std::string& m) {
+    b->err = m;
+    return s;
+}
+
+static void batch_free_device(tdse_batch_ctx* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_cfg) (void)hipFree(b->d_cfg);
+    if (b->d_wg) (void)hipFree(b->d_wg);
+    if (b->d_rec) (void)hipFree(b->d_rec);
+    if (b->d_fin) (void)hipFree(b->d_fin);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->d_cfg = b->d_fin = nullptr;
+    b->d_wg = nullptr;
+    b->d_rec = nullptr;
+    b->prepared = false;
+}
+
+template <typename T>
+static hipError_t batch_enqueue_interval(tdse_batch_ctx* b) {
+    const size_t n = b->members.size();
+    for (int j = 0; j < b->S; ++j) {
+        BatchStep<T> st;
+        st.cfg = static_cast<const FusedArgs<T>*>(b->d_cfg);
+        st.wg_start = b->d_wg;
+        st.rec_idx = b->d_rec;
+        st.n = (int)n;
+        st.total_wg = b->total_wg;
+        st.parity = j & 1;
+        st.flux_slot = j;
+        const bool rec = b->h > 0 && j == b->S - 1;
+        hipError_t e;
+        if constexpr (sizeof(T) == 8)
+            e = launch_fused_batch_f64(b->W, b->M, rec, b->pf, dim3(b->total_wg), b->lds, b->stream, st);
+        else
+            e = launch_fused_batch_f32(b->W, b->M, rec, b->pf, dim3(b->total_wg), b->lds, b->stream, st);
+        if (e != hipSuccess) return e;
+    }
+    BatchFin f;
+    f.cfg = static_cast<const FinArgs*>(b->d_fin);
+    f.rec_idx = b->d_rec;
+    f.n_pending = b->S;
+    f.record = b->h > 0 ? 1 : 0;
+    hipLaunchKernelGGL(finalize_batch_kernel, dim3((unsigned)n), dim3(256), 0, b->stream, f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (b->h > 0) {
+        hipLaunchKernelGGL(bump_counter_kernel, dim3(1), dim3(64), 0, b->stream, b->d_rec);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+template <typename T>
+static tdse_status batch_prepare_t(tdse_batch_ctx* b) {
+    const size_t n = b->members.size();
+    std::vector<FusedArgs<T>> cfg(n);
+    std::vector<FinArgs> fin(n);
+    std::vector<int> wg(n + 1, 0);
+    size_t lds = 0;
+    int W = 0;
+    for (size_t i = 0; i < n; ++i) {
+        tdse_ctx* h = b->members[i];
+        h->fm = b->M;
+        h->fzc = (int)std::min<int64_t>(b->zc, h->d.nz);
+        const FusedDims fd = fused_dims(h, b->M, h->fzc);
+        if (!fd.ok) return bfail(b, TDSE_ERR_UNSUPPORTED, "member grid does not fit the one-pass tile");
+        if (W == 0) W = fd.W;
+        if (fd.W != W) return bfail(b, TDSE_ERR_UNSUPPORTED, "members need the same vector width");
+        cfg[i] = make_fused_args<T>(h, fd, b->h > 0, 0, 0);
+        cfg[i].rec_plane = static_cast<T*>(h->rec);  // record 0; the kernel adds the counter
+        lds = std::max(lds, fd.lds);
+        wg[i + 1] = wg[i] + fd.nwg;
+        const tdse_desc& d = h->d;
+        FinArgs& a = fin[i];
+        a.flux_ring = h->flux_ring;
+        a.n_pending = 0;
+        a.ytiles = fd.nbands;
+        a.has_up = !(d.bc[2] == TDSE_BC_ZERO && d.k_det + 1 >= d.nz);
+        a.record = 0;
+        a.rec_idx = 0;
+        a.dV = d.dx * d.dy * d.dz;
+        a.dv_cz = a.dV * h->c[2];
+        a.acc = h->acc;
+        a.part_q = h->part_q;
+        a.part_naive = h->part_naive;
+        a.n_part = (long)fd.nzc * fd.nbands;
+        a.part_plane = h->part_plane;
+        a.scalars = h->scal;
+    }
+    b->W = W;
+    b->lds = lds;
+    b->total_wg = wg[n];
+    if (hipMalloc(&b->d_cfg, n * sizeof(FusedArgs<T>)) != hipSuccess ||
+        hipMalloc(&b->d_fin, n * sizeof(FinArgs)) != hipSuccess ||
+        hipMalloc(&b->d_wg, (n + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->d_rec, sizeof(long)) != hipSuccess) {
+        batch_free_device(b);
+        return bfail(b, TDSE_ERR_OOM, "batch tables");
+    }
+    hipError_t e = hipMemcpyAsync(b->d_cfg, cfg.data(), n * sizeof(FusedArgs<T>), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_fin, fin.data(), n * sizeof(FinArgs), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_wg, wg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        batch_free_device(b);
+        return bfail(b, TDSE_ERR_DEVICE, std::string("batch tables: ") + hipGetErrorString(e));
+    }
+    // capture one interval of S steps + finalisation + counter bump
+    e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = batch_enqueue_interval<T>(b);
+        e = hipStreamEndCapture(b->stream, &b->graph);
+        if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        batch_free_device(b);
+        return bfail(b, TDSE_ERR_DEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+    }
+    b->prepared = true;
+    return TDSE_OK;
+}
 
 extern "C" {
 
@@ -1399,6 +1556,113 @@ tdse_status tdse_potential_vjp(tdse_handle h, const tdse_atom* atoms, int64_t n,
         dL_dpos[3 * a2 + 2] = out[4 * a2 + 2];
         dL_damp[a2] = out[4 * a2 + 3];
     }
+    return TDSE_OK;
+}
+
+tdse_status tdse_batch_create(const tdse_desc* descs, int32_t n, void* stream, tdse_batch* out) {
+    if (!descs || n < 1 || !out) return TDSE_ERR_ARG;
+    *out = nullptr;
+    tdse_batch_ctx* b = new (std::nothrow) tdse_batch_ctx();
+    if (!b) return TDSE_ERR_OOM;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->precision = descs[0].precision;
+    b->h = descs[0].record_every;
+    for (int32_t i = 0; i < n; ++i) {
+        if (descs[i].precision != b->precision || descs[i].record_every != b->h) {
+            for (tdse_ctx* m : b->members) tdse_destroy(m);
+            delete b;
+            return TDSE_ERR_ARG;
+        }
+        tdse_handle h = nullptr;
+        tdse_status s = tdse_create(&descs[i], stream, &h);
+        if (s != TDSE_OK) {
+            for (tdse_ctx* m : b->members) tdse_destroy(m);
+            delete b;
+            return s;
+        }
+        b->members.push_back(h);
+    }
+    if (b->h > 256 || (b->h > 0 && b->h % 2)) {
+        for (tdse_ctx* m : b->members) tdse_destroy(m);
+        delete b;
+        return TDSE_ERR_UNSUPPORTED;
+    }
+    b->S = b->h > 0 ? (int)b->h : 64;
+    *out = b;
+    return TDSE_OK;
+}
+
+tdse_status tdse_batch_member(tdse_batch b, int32_t i, tdse_handle* h) {
+    if (!b || !h || i < 0 || i >= (int32_t)b->members.size()) return TDSE_ERR_ARG;
+    *h = b->members[(size_t)i];
+    return TDSE_OK;
+}
+
+tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc, int32_t prefetch) {
+    if (!b) return TDSE_ERR_ARG;
+    if (fused_rows != 2 && fused_rows != 3 && fused_rows != 4 && fused_rows != 6) return bfail(b, TDSE_ERR_ARG, "fused_rows");
+    if (fused_zc < 1) return bfail(b, TDSE_ERR_ARG, "fused_zc");
+    batch_free_device(b);
+    b->M = fused_rows;
+    b->zc = fused_zc;
+    b->pf = prefetch != 0;
+    return TDSE_OK;
+}
+
+tdse_status tdse_batch_prepare(tdse_batch b) {
+    if (!b) return TDSE_ERR_ARG;
+    batch_free_device(b);
+    int64_t step = -1;
+    for (tdse_ctx* h : b->members) {
+        if (!h->ready || !h->R2) return bfail(b, TDSE_ERR_STATE, "every member needs a state and tdse_bind_pingpong");
+        if (h->pending) return bfail(b, TDSE_ERR_STATE, "pending flux partials");
+        if (step < 0) step = h->step;
+        if (h->step != step) return bfail(b, TDSE_ERR_STATE, "members at different steps");
+    }
+    if (b->h > 0 && step % b->h) return bfail(b, TDSE_ERR_STATE, "members must sit on a record level");
+    b->step = step;
+    return b->precision == TDSE_F64 ? batch_prepare_t<double>(b) : batch_prepare_t<float>(b);
+}
+
+tdse_status tdse_batch_run(tdse_batch b, int64_t n) {
+    if (!b || n < 0) return TDSE_ERR_ARG;
+    if (!b->prepared) return bfail(b, TDSE_ERR_STATE, "tdse_batch_prepare first");
+    if (n % b->S) return bfail(b, TDSE_ERR_ARG, "n must be a multiple of the record interval (64 without records)");
+    for (tdse_ctx* h : b->members) {
+        if (h->step != b->step) return bfail(b, TDSE_ERR_STATE, "a member was stepped outside the batch");
+        if (b->h > 0 && (b->step + n) / b->h + 1 > h->d.max_records)
+            return bfail(b, TDSE_ERR_CAPACITY, "record buffer would overflow");
+    }
+    if (n == 0) return TDSE_OK;
+    const long next = b->h > 0 ? (long)(b->step / b->h + 1) : 0;
+    hipError_t e = hipMemcpyAsync(b->d_rec, &next, sizeof(long), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    for (int64_t r = 0; r < n / b->S && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, b->stream);
+    if (e != hipSuccess) return bfail(b, TDSE_ERR_DEVICE, std::string("batch run: ") + hipGetErrorString(e));
+    b->step += n;
+    for (tdse_ctx* h : b->members) h->step += n;
+    return TDSE_OK;
+}
+
+tdse_status tdse_batch_status(tdse_batch b, int32_t* per_config) {
+    if (!b || !per_config) return TDSE_ERR_ARG;
+    tdse_status worst = TDSE_OK;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        tdse_detect_out o;
+        tdse_status s = tdse_detect(b->members[i], &o);
+        per_config[i] = s;
+        if (s != TDSE_OK && worst == TDSE_OK) worst = s;
+    }
+    return worst;
+}
+
+const char* tdse_batch_last_error(tdse_batch b) { return b ? b->err.c_str() : ""; }
+
+tdse_status tdse_batch_destroy(tdse_batch b) {
+    if (!b) return TDSE_OK;
+    batch_free_device(b);
+    for (tdse_ctx* h : b->members) tdse_destroy(h);
+    delete b;
     return TDSE_OK;
 }
 

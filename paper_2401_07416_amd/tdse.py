@@ -32,7 +32,9 @@ EXPORTS = [
     "tdse_init_gaussian", "tdse_set_state", "tdse_get_state", "tdse_step", "tdse_detect",
     "tdse_copy_scalars", "tdse_set_timing", "tdse_timing_read", "tdse_get_tile", "tdse_set_tile",
     "tdse_bind_pingpong", "tdse_adjoint_workspace_size", "tdse_bind_adjoint", "tdse_adjoint",
-    "tdse_potential_vjp",
+    "tdse_potential_vjp", "tdse_batch_create", "tdse_batch_member", "tdse_batch_set_tile",
+    "tdse_batch_prepare", "tdse_batch_run", "tdse_batch_status", "tdse_batch_last_error",
+    "tdse_batch_destroy",
 ]
 
 
@@ -126,6 +128,14 @@ def load():
         "tdse_adjoint": (i32, [vp, vp, vp, vp, vp]),
         "tdse_potential_vjp": (i32, [vp, ctypes.POINTER(Atom), i64, ctypes.POINTER(PotParams), vp,
                                      dp, dp]),
+        "tdse_batch_create": (i32, [ctypes.POINTER(Desc), i32, vp, ctypes.POINTER(vp)]),
+        "tdse_batch_member": (i32, [vp, i32, ctypes.POINTER(vp)]),
+        "tdse_batch_set_tile": (i32, [vp, i32, i32, i32]),
+        "tdse_batch_prepare": (i32, [vp]),
+        "tdse_batch_run": (i32, [vp, i64]),
+        "tdse_batch_status": (i32, [vp, ctypes.POINTER(i32)]),
+        "tdse_batch_last_error": (ctypes.c_char_p, [vp]),
+        "tdse_batch_destroy": (i32, [vp]),
         "tdse_get_tile": (i32, [vp, ctypes.POINTER(Tile)]),
         "tdse_set_tile": (i32, [vp, ctypes.POINTER(Tile)]),
     }
@@ -198,7 +208,7 @@ class Sim:
     workspace, the records [max_records][ny][nx], the FP64 record scalars
     [max_records][4] and optionally the FP64 pixel integral [ny][nx]."""
 
-    def __init__(self, desc: Desc, device=None, stream=None, pingpong=True):
+    def __init__(self, desc: Desc, device=None, stream=None, pingpong=True, handle=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libtdse needs a HIP device")
@@ -221,10 +231,15 @@ class Sim:
             self.scalars = torch.zeros((nrec, 4), dtype=torch.float64, device=self.device)
             self.pixel = (torch.zeros((desc.ny, desc.nx), dtype=torch.float64, device=self.device)
                           if desc.flags & FLAG_PIXEL_INTEGRAL else None)
-            h = ctypes.c_void_p()
-            self._check(self.lib.tdse_create(ctypes.byref(desc),
-                                             ctypes.c_void_p(self.stream.cuda_stream),
-                                             ctypes.byref(h)), None)
+            if handle is None:
+                h = ctypes.c_void_p()
+                self._check(self.lib.tdse_create(ctypes.byref(desc),
+                                                 ctypes.c_void_p(self.stream.cuda_stream),
+                                                 ctypes.byref(h)), None)
+                self.owned = True
+            else:
+                h = handle
+                self.owned = False
             self.h = h
             self._check(self.lib.tdse_bind(
                 self.h, self.psi_r.data_ptr(), self.psi_i.data_ptr(), self.v.data_ptr(),
@@ -248,7 +263,8 @@ class Sim:
 
     def close(self):
         if getattr(self, "h", None):
-            self.lib.tdse_destroy(self.h)
+            if getattr(self, "owned", True):
+                self.lib.tdse_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -413,3 +429,87 @@ def sim_from_workload(w, precision: Optional[str] = None, steps: Optional[int] =
         k0 = tuple(kk * c for c in w.k_dir)
     s.init_gaussian(w.r0, k0, w.sigma)
     return s
+
+
+class Batch:
+    """Many simulations of uneven grid size stepped together (one launch per
+    step for all of them, one HIP graph per record interval).  Members are
+    Sim objects sharing the batch's stream; set each one up with the usual
+    calls, then prepare() and run()."""
+
+    def __init__(self, descs, device=None):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self.stream = torch.cuda.Stream(device=self.device)
+        arr = (Desc * len(descs))(*descs)
+        b = ctypes.c_void_p()
+        st = self.lib.tdse_batch_create(arr, len(descs), ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(b))
+        if st != OK:
+            raise TdseError(st, f"{status_string(st)}: batch_create")
+        self.b = b
+        self.members = []
+        for i, d in enumerate(descs):
+            h = ctypes.c_void_p()
+            self._check(self.lib.tdse_batch_member(self.b, i, ctypes.byref(h)))
+            self.members.append(Sim(d, device=self.device, stream=self.stream, handle=h))
+        torch.cuda.synchronize(self.device)
+
+    def _check(self, st):
+        if st != OK:
+            raise TdseError(st, f"{status_string(st)}: {self.lib.tdse_batch_last_error(self.b).decode()}")
+
+    def set_tile(self, fused_rows=4, fused_zc=64, prefetch=True):
+        self._check(self.lib.tdse_batch_set_tile(self.b, int(fused_rows), int(fused_zc),
+                                                 int(bool(prefetch))))
+
+    def prepare(self):
+        self.torch.cuda.synchronize(self.device)
+        self._check(self.lib.tdse_batch_prepare(self.b))
+
+    def run(self, n: int):
+        self._check(self.lib.tdse_batch_run(self.b, int(n)))
+
+    def status(self):
+        out = (ctypes.c_int32 * len(self.members))()
+        self.lib.tdse_batch_status(self.b, out)
+        return list(out)
+
+    def close(self):
+        if getattr(self, "b", None):
+            for m in self.members:
+                m.h = None
+            self.lib.tdse_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_from_workloads(ws, precision="f32", steps=None, device=None) -> Batch:
+    """A batch whose members are set up from seeded workload descriptions."""
+    descs = []
+    for w in ws:
+        n = w.steps if steps is None else steps
+        descs.append(make_desc(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass,
+                               dt_frac=w.dt_frac, bc=w.bc, precision=precision, k_det=w.k_det,
+                               record_every=w.record_every, max_records=w.n_records(n)))
+    b = Batch(descs, device=device)
+    for w, s in zip(ws, b.members):
+        with b.torch.cuda.stream(b.stream):
+            if w.atoms is not None and len(w.atoms):
+                s.build_potential(w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
+                                  screened=w.screened)
+            if w.cap is not None:
+                s.set_cap_quadratic(*w.cap)
+            s.finalize()
+            k0 = w.k0 if w.k0 is not None else tuple(wavevector(w.energy, w.hbar, w.mass) * c
+                                                     for c in w.k_dir)
+            s.init_gaussian(w.r0, k0, w.sigma)
+    b.torch.cuda.synchronize(b.device)
+    return b

@@ -174,6 +174,72 @@ def perturbed_positions(atoms: np.ndarray, seed: int = 6, scale: float = 0.05) -
     return out
 
 
+def hydroxyhexyl() -> np.ndarray:
+    """A rigid HO(CH2)6 chain (20 atoms: 6 C, 12 H, O, H) along +z from the
+    origin, from textbook bond lengths (C-C 1.54, C-H 1.09, C-O 1.43,
+    O-H 0.96 A) and tetrahedral angles: an all-trans zigzag in the xz plane
+    with the methylene hydrogens above and below that plane.  Rows are
+    x, y, z, Z."""
+    half = np.deg2rad(109.47) / 2
+    dz, dx = 1.54 * np.sin(half), 1.54 * np.cos(half) / 2
+    out = []
+    for c in range(6):
+        x = dx if c % 2 else -dx
+        z = c * dz
+        out.append([x, 0.0, z, 6.0])
+        # the two hydrogens point away from the chain, out of the zigzag plane
+        hx = np.sign(x) * 1.09 * np.cos(np.deg2rad(54.75))
+        hy = 1.09 * np.sin(np.deg2rad(54.75))
+        out.append([x + hx, hy, z, 1.0])
+        out.append([x + hx, -hy, z, 1.0])
+    xo = -dx if 6 % 2 == 0 else dx
+    zo = 5 * dz + 1.43 * np.sin(half)
+    out.append([xo, 0.0, zo, 8.0])
+    out.append([xo + 0.96 * np.cos(half), 0.0, zo + 0.96 * np.sin(half), 1.0])
+    return np.array(out, dtype=np.float64)
+
+
+def film_atoms(seed: int, lx: float, ly: float, z_base: float, n_side: int = 4,
+               displacement: float = 0.2) -> np.ndarray:
+    """Monolayer of rigid 20-atom molecules on an n_side x n_side lattice,
+    each rotated in plane by an angle uniform in [0, 2 pi) and shifted by
+    `displacement` in a uniform random direction; amplitudes 1."""
+    rng = np.random.default_rng(seed)
+    mol = hydroxyhexyl()
+    out = []
+    for j in range(n_side):
+        for i in range(n_side):
+            th = rng.uniform(0.0, 2 * np.pi)
+            ph = rng.uniform(0.0, 2 * np.pi)
+            c, s_ = np.cos(th), np.sin(th)
+            x0 = (i + 0.5) * lx / n_side + displacement * np.cos(ph)
+            y0 = (j + 0.5) * ly / n_side + displacement * np.sin(ph)
+            for x, y, z, Z in mol:
+                out.append([x0 + c * x - s_ * y, y0 + s_ * x + c * y, z_base + z, Z, 1.0])
+    return np.array(out, dtype=np.float64)
+
+
+def c4_film(b: int, steps: int = 8000) -> Workload:
+    """Configuration b of the batched data-generation set: N_x = N_y =
+    128 + 16 m (m uniform in 0..8, seed 7416 + b), N_z = 2 N_x, dx = 0.2 A; a
+    4 x 4 film of HO(CH2)6 chains based at z = 0.25 L_z; 15 eV packet with
+    sigma = min(8 A, L_z/16) at z = 0.65 L_z; detection at 0.55 L_z every 50
+    steps; 24-plane CAP."""
+    rng = np.random.default_rng(7416 + b)
+    n = 128 + 16 * int(rng.integers(0, 9))
+    nz = 2 * n
+    L, Lz = 0.2 * n, 0.2 * nz
+    atoms = film_atoms(7416 + b, L, L, 0.25 * Lz)
+    return Workload(name=f"film-{b}-{n}x{n}x{nz}", nx=n, ny=n, nz=nz, dx=0.2, dy=0.2, dz=0.2,
+                    hbar=HBAR_EV_FS, mass=ME_EV_FS2_A2, atoms=atoms, cap=(24, 24, 50.0),
+                    r0=(L / 2, L / 2, 0.65 * Lz), sigma=min(8.0, Lz / 16), energy=15.0,
+                    dt_frac=0.9, steps=steps, k_det=int(round(0.55 * nz)), record_every=50)
+
+
+def c4_batch(n: int = 64, steps: int = 8000):
+    return [c4_film(b, steps) for b in range(n)]
+
+
 def ragged(precision: str = "f64", seed: int = 11) -> Workload:
     """Odd, non-power-of-two box (37 x 29 x 53) that leaves ragged tiles in
     every direction; a few atoms, a CAP and a packet."""

@@ -1,0 +1,99 @@
+"""GPU batches: many grids of uneven size stepped by one launch per step and
+one HIP graph per record interval must give exactly what each grid gives
+alone (the cell arithmetic and tile-independent reductions are shared), and
+match the oracle (arXiv 2401.07416 section 2.1, eqs. (8)-(10), (15))."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_07416_amd import tdse, workloads
+from tests import gpu_harness as H
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_set(steps):
+    """Four uneven grids with the film physics (x extents that all take
+    4-wide vectors)."""
+    out = []
+    for b, n in enumerate((32, 48, 40, 64)):
+        w = workloads.c4_film(b, steps)
+        nz = 2 * n
+        L, Lz = 0.2 * n, 0.2 * nz
+        w = w.with_(nx=n, ny=n, nz=nz, atoms=workloads.film_atoms(100 + b, L, L, 0.25 * Lz),
+                    r0=(L / 2, L / 2, 0.65 * Lz), sigma=min(8.0, Lz / 16),
+                    k_det=int(round(0.55 * nz)), cap=(8, 8, 50.0), record_every=10,
+                    name=f"film-small-{n}")
+        out.append(w)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_equals_single_runs(prec):
+    steps = 60
+    ws = small_set(steps)
+    say("batch of", [w.name for w in ws], prec)
+    b = tdse.batch_from_workloads(ws, precision=prec, steps=steps)
+    b.set_tile(fused_rows=3, fused_zc=16, prefetch=True)
+    b.prepare()
+    b.run(steps)
+    assert all(s == tdse.OK for s in b.status())
+    for w, m in zip(ws, b.members):
+        single = H.gpu_run(w, steps, precision=prec)
+        assert bool((m.psi_r == single.psi_r).all()) and bool((m.psi_i == single.psi_i).all())
+        n = m.detect().n_records
+        assert n == steps // w.record_every + 1
+        assert bool((m.records[:n] == single.records[:n]).all())
+        np.testing.assert_allclose(m.scalars[:n].cpu().numpy(), single.scalars[:n].cpu().numpy(),
+                                   rtol=1e-12, atol=1e-15)
+        assert m.detect().flux == pytest.approx(single.detect().flux, rel=1e-11, abs=1e-15)
+
+
+def test_batch_member_matches_oracle():
+    steps = 40
+    ws = small_set(steps)
+    b = tdse.batch_from_workloads(ws, precision="f64", steps=steps)
+    b.prepare()
+    b.run(steps)
+    w, m = ws[0], b.members[0]
+    say("batch member vs oracle", w.name)
+    ref = H.oracle_run(w, steps)
+    say(H.compare(m, ref, tol_state=1e-11, tol_rec=1e-11, tol_scal=1e-12, tol_flux=1e-12))
+
+
+def test_batch_flags_a_poisoned_configuration():
+    steps = 20
+    ws = small_set(steps)
+    b = tdse.batch_from_workloads(ws, precision="f32", steps=steps)
+    with torch.cuda.stream(b.stream):
+        b.members[2].psi_r[5, 5, 5] = float("nan")
+    torch.cuda.synchronize()
+    b.prepare()
+    b.run(steps)
+    st = b.status()
+    say("status", st)
+    assert st[2] == tdse.ERR_NONFINITE
+    assert [s for i, s in enumerate(st) if i != 2] == [tdse.OK] * 3
+    for i in (0, 1, 3):
+        assert bool(torch.isfinite(b.members[i].psi_r).all())
+
+
+def test_batch_rejects_misuse():
+    ws = small_set(20)
+    b = tdse.batch_from_workloads(ws, precision="f32", steps=20)
+    with pytest.raises(tdse.TdseError):
+        b.run(10)  # not prepared
+    b.prepare()
+    with pytest.raises(tdse.TdseError) as e:
+        b.run(15)  # not a multiple of the record interval
+    assert e.value.status == tdse.ERR_ARG
+    with pytest.raises(tdse.TdseError) as e:
+        b.run(40)  # past the record buffers
+    assert e.value.status == tdse.ERR_CAPACITY

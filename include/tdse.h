@@ -341,12 +341,15 @@ tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count);
  * tdse_bind_pingpong), fused_rows = rows per thread (2, 3, 4 or 6; the band
  * is band_rows = (256 / threads per row) * fused_rows - 2 rows), fused_zc =
  * z planes per workgroup, fused_prefetch != 0 issues the next plane's loads
- * before the current plane's eq. (8) part.  tdse_create picks defaults;
- * tdse_set_tile checks and replaces them.  The last four fields are
- * read-only. */
+ * before the current plane's eq. (8) part.  graph != 0 (default) lets
+ * tdse_step replay a captured HIP graph for whole record intervals of
+ * one-pass steps when the handle's stream is not the null stream, timing is
+ * off and no adjoint is bound (h even, <= 256).  tdse_create picks
+ * defaults; tdse_set_tile checks and replaces them.  The last four fields
+ * are read-only. */
 typedef struct tdse_tile {
     int32_t rows, waves, zc;
-    int32_t fused, fused_rows, fused_zc, fused_prefetch;
+    int32_t fused, fused_rows, fused_zc, fused_prefetch, graph;
     int32_t vec_elems, vec_groups, lanes, band_rows;
 } tdse_tile;
 

@@ -89,9 +89,13 @@ __global__ __launch_bounds__(256) void finalize_batch_kernel(BatchFin b) {
     finalize_body(a);
 }
 
-// Advance the device record counter of a batch (one lane, vector store).
+// Advance / set the device record counter of a batch (one lane, vector store).
 __global__ void bump_counter_kernel(long* c) {
     if (threadIdx.x == 0) c[0] = c[0] + 1;
+}
+
+__global__ void set_counter_kernel(long* c, long v) {
+    if (threadIdx.x == 0) c[0] = v;
 }
 
 // ---------------------------------------------------------------------------

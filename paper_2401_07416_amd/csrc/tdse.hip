@@ -23,8 +23,14 @@
 
 using namespace tdse;
 
+struct tdse_batch_ctx;
+
 struct tdse_ctx {
     tdse_desc d;
+    // whole record intervals of one-pass steps replay a captured graph (an
+    // internal one-member batch) when the stream is not the null stream
+    bool graph_on = true;
+    tdse_batch_ctx* gb = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
     // x layout and tile
@@ -96,6 +102,7 @@ struct tdse_batch_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool prepared = false;
+    bool owns = true;    // members are destroyed with the batch
     int64_t step = 0;
     std::string err;
 };
@@ -802,6 +809,15 @@ static tdse_status batch_prepare_t(tdse_batch_ctx* b) {
     return TDSE_OK;
 }
 
+// Drop the captured single-grid graph (tables and graph of the internal
+// one-member batch) after anything it baked in changes.
+static void graph_invalidate(tdse_ctx* h) {
+    if (!h->gb) return;
+    batch_free_device(h->gb);
+    delete h->gb;
+    h->gb = nullptr;
+}
+
 extern "C" {
 
 int32_t tdse_abi_version(void) { return 1; }
@@ -901,6 +917,7 @@ tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out) {
 
 tdse_status tdse_destroy(tdse_handle h) {
     if (!h) return TDSE_OK;
+    graph_invalidate(h);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
     return TDSE_OK;
@@ -924,6 +941,7 @@ tdse_status tdse_bind(tdse_handle h, void* psi_r, void* psi_i, void* v, void* wo
     if (scalars && !aligned(scalars)) return fail(h, TDSE_ERR_ARG, "scalars not 256-byte aligned");
     if ((d.flags & TDSE_FLAG_PIXEL_INTEGRAL) && !aligned(pixel))
         return fail(h, TDSE_ERR_ARG, "pixel not 256-byte aligned");
+    graph_invalidate(h);
     h->R = psi_r;
     h->I = psi_i;
     h->V = v;
@@ -1088,6 +1106,7 @@ tdse_status tdse_set_cap(tdse_handle h, const double* w, int64_t nz) {
         h->wcap.assign((size_t)nz, 0.0);
     }
     if (h->finalized) {
+        graph_invalidate(h);
         tdse_status s = upload_tables(h);
         if (s != TDSE_OK) return s;
         h->ready = false;
@@ -1142,6 +1161,7 @@ tdse_status tdse_finalize_setup(tdse_handle h, double* dt_out, double* e_max_out
     double dt = d.dt > 0 ? d.dt : d.dt_frac * bound;
     if (dt > bound * (1.0 + 1e-12) && !(d.flags & TDSE_FLAG_ALLOW_UNSTABLE))
         return fail(h, TDSE_ERR_UNSTABLE, "dt exceeds hbar / E_max");
+    graph_invalidate(h);
     h->dt = dt;
     h->emax = em;
     h->c[0] = d.hbar * dt / (2.0 * d.mass * d.dx * d.dx);
@@ -1267,13 +1287,9 @@ tdse_status tdse_get_state(tdse_handle h, void* psi_r, void* psi_i, int64_t* ste
     return TDSE_OK;
 }
 
-tdse_status tdse_step(tdse_handle h, int64_t n) {
-    if (!h || n < 0) return TDSE_ERR_ARG;
-    if (!h->ready) return fail(h, TDSE_ERR_STATE, "no state: init_gaussian or set_state first");
+static tdse_status step_plain(tdse_ctx* h, int64_t n) {
     const tdse_desc& d = h->d;
     const int64_t hrec = d.record_every;
-    if (hrec > 0 && (h->step + n) / hrec + 1 > d.max_records)
-        return fail(h, TDSE_ERR_CAPACITY, "record buffer would overflow");
     // one-pass steps come in pairs so the state ends in the bound buffers;
     // an odd step runs as two in-place half-steps
     const FusedDims fd = fused_dims(h, h->fm, h->fzc);
@@ -1329,6 +1345,58 @@ tdse_status tdse_step(tdse_handle h, int64_t n) {
         h->pending = 0;
     }
     return TDSE_OK;
+}
+
+tdse_status tdse_step(tdse_handle h, int64_t n) {
+    if (!h || n < 0) return TDSE_ERR_ARG;
+    if (!h->ready) return fail(h, TDSE_ERR_STATE, "no state: init_gaussian or set_state first");
+    const tdse_desc& d = h->d;
+    const int64_t hrec = d.record_every;
+    if (hrec > 0 && (h->step + n) / hrec + 1 > d.max_records)
+        return fail(h, TDSE_ERR_CAPACITY, "record buffer would overflow");
+    const FusedDims fd = fused_dims(h, h->fm, h->fzc);
+    const bool graph_ok = h->fused && h->R2 && fd.ok && h->graph_on && h->stream != nullptr &&
+                          !h->timing && !h->adj_ws && hrec > 0 && hrec % 2 == 0 && hrec <= 256;
+    if (!graph_ok) return step_plain(h, n);
+    // plain steps up to the next record level, graph replays of whole
+    // intervals, plain steps for the rest
+    const int64_t pre = std::min<int64_t>((hrec - h->step % hrec) % hrec, n);
+    tdse_status st = step_plain(h, pre);
+    if (st != TDSE_OK) return st;
+    const int64_t q = (n - pre) / hrec;
+    if (q > 0) {
+        if (!h->gb) {
+            tdse_batch_ctx* b = new (std::nothrow) tdse_batch_ctx();
+            if (!b) return fail(h, TDSE_ERR_OOM, "graph context");
+            b->members.push_back(h);
+            b->owns = false;
+            b->stream = h->stream;
+            b->precision = d.precision;
+            b->h = hrec;
+            b->S = (int)hrec;
+            b->M = h->fm;
+            b->zc = h->fzc;
+            b->pf = h->fpf;
+            b->step = h->step;
+            st = d.precision == TDSE_F64 ? batch_prepare_t<double>(b) : batch_prepare_t<float>(b);
+            if (st != TDSE_OK) {
+                std::string m = b->err;
+                batch_free_device(b);
+                delete b;
+                return fail(h, st, "graph capture: " + m);
+            }
+            h->gb = b;
+        }
+        tdse_batch_ctx* b = h->gb;
+        hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, h->stream, b->d_rec,
+                           (long)(h->step / hrec + 1));
+        hipError_t e = hipGetLastError();
+        for (int64_t r = 0; r < q && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, h->stream);
+        if (e != hipSuccess) return hip_check(h, e, "graph launch");
+        h->step += q * hrec;
+        b->step = h->step;
+    }
+    return step_plain(h, n - pre - q * hrec);
 }
 
 tdse_status tdse_detect(tdse_handle h, tdse_detect_out* out) {
@@ -1401,6 +1469,7 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
     out->fused_rows = h->fm;
     out->fused_zc = h->fzc;
     out->fused_prefetch = h->fpf ? 1 : 0;
+    out->graph = h->graph_on ? 1 : 0;
     out->vec_elems = h->W;
     out->vec_groups = h->G;
     out->lanes = h->NL;
@@ -1424,10 +1493,12 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
         if (!fused_dims(h, t->fused_rows, fzc).ok)
             return fail(h, TDSE_ERR_UNSUPPORTED, "one-pass tile does not fit this grid");
     }
+    graph_invalidate(h);
     h->rows = t->rows;
     h->waves = t->waves;
     h->zc = (int)std::min<int64_t>(t->zc, h->d.nz);
     h->fused = t->fused != 0;
+    h->graph_on = t->graph != 0;
     h->fm = t->fused_rows;
     h->fzc = fzc;
     h->fpf = t->fused_prefetch != 0;
@@ -1443,6 +1514,7 @@ tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2) {
     for (int i = 0; i < 5; ++i)
         for (int j = i + 1; j < 5; ++j)
             if (used[i] == used[j]) return fail(h, TDSE_ERR_ARG, "aliased arrays");
+    graph_invalidate(h);
     h->R2 = psi_r2;
     h->I2 = psi_i2;
     h->fused = fused_dims(h, h->fm, h->fzc).ok;
@@ -1635,8 +1707,8 @@ tdse_status tdse_batch_run(tdse_batch b, int64_t n) {
     }
     if (n == 0) return TDSE_OK;
     const long next = b->h > 0 ? (long)(b->step / b->h + 1) : 0;
-    hipError_t e = hipMemcpyAsync(b->d_rec, &next, sizeof(long), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, b->stream, b->d_rec, next);
+    hipError_t e = hipGetLastError();
     for (int64_t r = 0; r < n / b->S && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, b->stream);
     if (e != hipSuccess) return bfail(b, TDSE_ERR_DEVICE, std::string("batch run: ") + hipGetErrorString(e));
     b->step += n;
@@ -1661,7 +1733,8 @@ const char* tdse_batch_last_error(tdse_batch b) { return b ? b->err.c_str() : ""
 tdse_status tdse_batch_destroy(tdse_batch b) {
     if (!b) return TDSE_OK;
     batch_free_device(b);
-    for (tdse_ctx* h : b->members) tdse_destroy(h);
+    if (b->owns)
+        for (tdse_ctx* h : b->members) tdse_destroy(h);
     delete b;
     return TDSE_OK;
 }

@@ -77,7 +77,7 @@ class Tile(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("waves", ctypes.c_int32), ("zc", ctypes.c_int32),
                 ("fused", ctypes.c_int32), ("fused_rows", ctypes.c_int32),
                 ("fused_zc", ctypes.c_int32), ("fused_prefetch", ctypes.c_int32),
-                ("vec_elems", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("vec_elems", ctypes.c_int32),
                 ("vec_groups", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("band_rows", ctypes.c_int32)]
 
@@ -311,6 +311,7 @@ class Sim:
         pr = psi_r.to(self.device, self.dtype).contiguous()
         pi = psi_i.to(self.device, self.dtype).contiguous()
         self._keep = (pr, pi)  # alive until the asynchronous copy has run
+        t.cuda.synchronize(self.device)  # the copies above ran on torch's stream
         self._check(self.lib.tdse_set_state(self.h, pr.data_ptr(), pi.data_ptr(), int(step),
                                             float(flux)))
         t.cuda.current_stream(self.device).synchronize()
@@ -394,11 +395,11 @@ class Sim:
         return t
 
     def set_tile(self, rows=None, waves=None, zc=None, fused=None, fused_rows=None,
-                 fused_zc=None, fused_prefetch=None):
+                 fused_zc=None, fused_prefetch=None, graph=None):
         t = self.get_tile()
         for name, v in (("rows", rows), ("waves", waves), ("zc", zc), ("fused", fused),
                         ("fused_rows", fused_rows), ("fused_zc", fused_zc),
-                        ("fused_prefetch", fused_prefetch)):
+                        ("fused_prefetch", fused_prefetch), ("graph", graph)):
             if v is not None:
                 setattr(t, name, int(v))
         self._check(self.lib.tdse_set_tile(self.h, ctypes.byref(t)))
@@ -406,7 +407,7 @@ class Sim:
 
 def sim_from_workload(w, precision: Optional[str] = None, steps: Optional[int] = None,
                       pixel=False, device=None, max_records: Optional[int] = None,
-                      pingpong=True) -> Sim:
+                      pingpong=True, stream=None) -> Sim:
     """Set up a simulation from a seeded workload description (potential on
     the device, CAP, dt, Gaussian packet)."""
     prec = precision or w.precision
@@ -415,7 +416,10 @@ def sim_from_workload(w, precision: Optional[str] = None, steps: Optional[int] =
     d = make_desc(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, dt_frac=w.dt_frac,
                   bc=w.bc, precision=prec, k_det=w.k_det, record_every=w.record_every,
                   max_records=nrec, flags=FLAG_PIXEL_INTEGRAL if pixel else 0)
-    s = Sim(d, device=device, pingpong=pingpong)
+    s = Sim(d, device=device, pingpong=pingpong, stream=stream)
+    if stream is not None:
+        import torch
+        torch.cuda.synchronize()
     if w.atoms is not None and len(w.atoms):
         s.build_potential(w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
                           screened=w.screened)

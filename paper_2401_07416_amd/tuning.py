@@ -73,3 +73,38 @@ def autotune(sim, steps: int = 20, reps: int = 3, cands=None):
         res.append((best, tile))
     res.sort()
     return res
+
+
+def autotune_batch(batch, intervals: int = 2, cands=None):
+    """Time one-pass tiles on a batch (the members advance; use a scratch
+    batch).  Each candidate is (fused_rows, fused_zc, prefetch); returns
+    [(ms_per_step, tile)] sorted, and leaves the batch prepared with the best."""
+    import torch
+
+    from .tdse import TdseError
+    res = []
+    step = batch.members[0].detect().step
+    interval = None
+    for tile in (cands or [(m, zc, pf) for pf in (1, 0) for m in (2, 3, 4)
+                           for zc in (16, 32, 64, 128)]):
+        try:
+            batch.set_tile(*tile)
+            batch.prepare()
+        except TdseError:
+            continue
+        if interval is None:
+            w = batch.members[0].desc.record_every
+            interval = int(w) if w > 0 else 64
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(batch.stream)
+        batch.run(intervals * interval)
+        e1.record(batch.stream)
+        e1.synchronize()
+        step += intervals * interval
+        res.append((e0.elapsed_time(e1) / (intervals * interval), tile))
+    res.sort()
+    if res:
+        batch.set_tile(*res[0][1])
+        batch.prepare()
+    return res

@@ -131,6 +131,28 @@ def test_runs_are_bitwise_reproducible():
     assert a.detect().flux == b.detect().flux
 
 
+def test_graph_replay_matches_plain_launches():
+    """On a stream of its own the handle replays a captured graph for whole
+    record intervals; the bits must equal plain launches."""
+    import torch
+    w = workloads.c2_reduced().with_(steps=200)
+    say("graph replay")
+    plain = H.gpu_run(w, 200, precision="f32")
+    st = torch.cuda.Stream()
+    g = tdse.sim_from_workload(w, precision="f32", steps=200, stream=st)
+    assert g.get_tile().graph == 1
+    for n in (7, 150, 43):
+        g.step(n)
+    d = g.detect()
+    assert d.step == 200
+    torch.cuda.synchronize()
+    assert bool((plain.psi_r == g.psi_r).all()) and bool((plain.psi_i == g.psi_i).all())
+    assert bool((plain.records == g.records).all())
+    np.testing.assert_allclose(g.scalars.cpu().numpy(), plain.scalars.cpu().numpy(), rtol=1e-12,
+                               atol=1e-15)
+    assert d.flux == pytest.approx(plain.detect().flux, rel=1e-11, abs=1e-15)
+
+
 def test_chunked_steps_and_resume_are_exact():
     w = workloads.c2_reduced().with_(steps=300)
     say("resume")

@@ -306,7 +306,8 @@ tdse_status tdse_potential_vjp(tdse_handle h, const tdse_atom* atoms, int64_t n,
  * (tdse_bind, tdse_bind_pingpong (required), potential, CAP, finalize,
  * initial state); its outputs are read with tdse_detect as usual.
  * tdse_batch_set_tile: one-pass tile shared by the members (fused_rows 2, 3,
- * 4 or 6; fused_zc >= 1; prefetch flag); invalidates a prepared batch.
+ * 4 or 6; fused_zc >= 1; prefetch flag; threads per workgroup 64, 128 or
+ * 256); invalidates a prepared batch.
  * tdse_batch_prepare: all members at the same record level; builds the
  * device tables (a few KB, allocated here, freed by destroy or the next
  * prepare) and captures the graph of one interval.
@@ -320,7 +321,7 @@ typedef struct tdse_batch_ctx* tdse_batch;
 tdse_status tdse_batch_create(const tdse_desc* descs, int32_t n, void* stream, tdse_batch* out);
 tdse_status tdse_batch_member(tdse_batch b, int32_t i, tdse_handle* h);
 tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc,
-                                int32_t prefetch);
+                                int32_t prefetch, int32_t threads);
 tdse_status tdse_batch_prepare(tdse_batch b);
 tdse_status tdse_batch_run(tdse_batch b, int64_t n);
 tdse_status tdse_batch_status(tdse_batch b, int32_t* per_config);
@@ -339,17 +340,19 @@ tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count);
  * 2, 4 or 8), waves = wavefronts per workgroup (1..4), zc = z planes per
  * workgroup.  One-pass kernel: fused != 0 selects it (needs
  * tdse_bind_pingpong), fused_rows = rows per thread (2, 3, 4 or 6; the band
- * is band_rows = (256 / threads per row) * fused_rows - 2 rows), fused_zc =
+ * is band_rows = (fused_threads / threads per row) * fused_rows - 2 rows), fused_zc =
  * z planes per workgroup, fused_prefetch != 0 issues the next plane's loads
  * before the current plane's eq. (8) part.  graph != 0 (default) lets
  * tdse_step replay a captured HIP graph for whole record intervals of
  * one-pass steps when the handle's stream is not the null stream, timing is
  * off and no adjoint is bound (h even, <= 256).  tdse_create picks
- * defaults; tdse_set_tile checks and replaces them.  The last four fields
- * are read-only. */
+ * defaults; tdse_set_tile checks and replaces them.  fused_threads = threads
+ * per workgroup of the one-pass kernel (64, 128 or 256; the band is
+ * (fused_threads / threads per row) * fused_rows - 2 rows).  The last four
+ * fields are read-only. */
 typedef struct tdse_tile {
     int32_t rows, waves, zc;
-    int32_t fused, fused_rows, fused_zc, fused_prefetch, graph;
+    int32_t fused, fused_rows, fused_zc, fused_prefetch, graph, fused_threads;
     int32_t vec_elems, vec_groups, lanes, band_rows;
 } tdse_tile;
 

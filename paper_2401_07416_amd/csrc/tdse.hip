@@ -37,8 +37,8 @@ struct tdse_ctx {
     int W = 1, G = 1, NL = 1;
     int rows = 2, waves = 4, zc = 16;
     // one-pass (fused) step: rows per thread M, z chunk, enabled flag
-    int fm = 4, fzc = 64;
-    bool fpf = true;
+    int fm = 3, fzc = 64, ft = 256;
+    bool fpf = false;
     bool fused = false;
     // adjoint: checkpoints every adj_K steps of an adj_N-step forward run
     void* adj_ws = nullptr;
@@ -91,8 +91,8 @@ struct tdse_batch_ctx {
     int precision = TDSE_F32;
     int64_t h = 0;       // record interval shared by the members
     int S = 0;           // steps per graph replay
-    int W = 0, M = 4, zc = 64;
-    bool pf = true;
+    int W = 0, M = 3, zc = 64, nt = 256;
+    bool pf = false;
     size_t lds = 0;
     int total_wg = 0;
     void* d_cfg = nullptr;     // FusedArgs<T>[n]
@@ -232,17 +232,17 @@ hipError_t launch_half_f64_w2(int g, int rows, int mode, dim3 grid, dim3 block, 
                               const HalfArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_half_f64_w1(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
                               const HalfArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_fused_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+hipError_t launch_fused_f32(int w, int m, bool rec, bool pf, dim3 grid, int nt, size_t lds, hipStream_t st,
                             const FusedArgs<float>& a, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_adjoint_f32(int w, int g, int phase, dim3 grid, dim3 block, hipStream_t st,
                               const AdjArgs<float>& a);
 hipError_t launch_adjoint_f64(int w, int g, int phase, dim3 grid, dim3 block, hipStream_t st,
                               const AdjArgs<double>& a);
-hipError_t launch_fused_batch_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds,
+hipError_t launch_fused_batch_f32(int w, int m, bool rec, bool pf, dim3 grid, int nt, size_t lds,
                                   hipStream_t st, const BatchStep<float>& b);
-hipError_t launch_fused_batch_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds,
+hipError_t launch_fused_batch_f64(int w, int m, bool rec, bool pf, dim3 grid, int nt, size_t lds,
                                   hipStream_t st, const BatchStep<double>& b);
-hipError_t launch_fused_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+hipError_t launch_fused_f64(int w, int m, bool rec, bool pf, dim3 grid, int nt, size_t lds, hipStream_t st,
                             const FusedArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
 }  // namespace tdse
 
@@ -354,21 +354,22 @@ tdse_status launch_half(tdse_ctx* h, int mode, int rows, int waves, int zc, long
 // Geometry of the one-pass kernel: W-element vectors, tpr threads per row,
 // rpp rows per pass of a 256-thread workgroup, band of ty = rpp*m - 2 rows.
 struct FusedDims {
-    int W, tpr, rpp, ty, nbands, nzc, nwg;
+    int W, tpr, rpp, ty, nbands, nzc, nwg, threads;
     size_t lds;
     bool ok;
 };
 
-FusedDims fused_dims(const tdse_ctx* h, int m, int zc) {
+FusedDims fused_dims(const tdse_ctx* h, int m, int zc, int threads = 0) {
     const tdse_desc& d = h->d;
     FusedDims f{};
     const int es = d.precision == TDSE_F64 ? 8 : 4;
     const int wl32[3] = {4, 2, 1}, wl64[2] = {2, 1};
     const int* wl = es == 8 ? wl64 : wl32;
     const int nw = es == 8 ? 2 : 3;
+    f.threads = threads > 0 ? threads : h->ft;
     f.ok = false;
     for (int i = 0; i < nw; ++i) {
-        if (d.nx % wl[i] == 0 && d.nx / wl[i] <= 256) {
+        if (d.nx % wl[i] == 0 && d.nx / wl[i] <= f.threads) {
             f.W = wl[i];
             f.ok = true;
             break;
@@ -376,7 +377,7 @@ FusedDims fused_dims(const tdse_ctx* h, int m, int zc) {
     }
     if (!f.ok) return f;
     f.tpr = (int)(d.nx / f.W);
-    f.rpp = 256 / f.tpr;
+    f.rpp = f.threads / f.tpr;
     f.ty = f.rpp * m - 2;
     f.nbands = f.ty > 0 ? (int)((d.ny + f.ty - 1) / f.ty) : 0;
     f.nzc = (int)((d.nz + zc - 1) / zc);
@@ -439,10 +440,10 @@ tdse_status launch_fused(tdse_ctx* h, const FusedDims& f, bool rec, long rec_idx
     hipError_t e;
     if (h->d.precision == TDSE_F64) {
         FusedArgs<double> a = make_fused_args<double>(h, f, rec, rec_idx, flux_slot);
-        e = launch_fused_f64(f.W, h->fm, rec, h->fpf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+        e = launch_fused_f64(f.W, h->fm, rec, h->fpf, dim3(f.nwg), f.threads, f.lds, h->stream, a, e0, e1);
     } else {
         FusedArgs<float> a = make_fused_args<float>(h, f, rec, rec_idx, flux_slot);
-        e = launch_fused_f32(f.W, h->fm, rec, h->fpf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+        e = launch_fused_f32(f.W, h->fm, rec, h->fpf, dim3(f.nwg), f.threads, f.lds, h->stream, a, e0, e1);
     }
     return hip_check(h, e, "one-pass step launch");
 }
@@ -658,19 +659,41 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
 
 
 void default_fused_tile(tdse_ctx* h) {
+    // first (threads per workgroup, rows per thread, z chunk) in order of
+    // preference that keeps at least ~8 waves per CU busy; z chunks of 8
+    // only if nothing else does; else the shape with the most threads
     const tdse_desc& d = h->d;
-    h->fzc = (int)std::min<int64_t>(64, d.nz);
-    for (int m : {4, 3, 2}) {
-        const FusedDims f = fused_dims(h, m, h->fzc);
-        if (f.ok && f.ty <= d.ny + 2) {
-            h->fm = m;
-            const int target = 1536;
-            int nzc = std::max(1, target / std::max(1, f.nbands));
-            h->fzc = (int)std::min<int64_t>(d.nz, std::max<int64_t>(8, (d.nz + nzc - 1) / nzc));
-            return;
+    const long target = 256L * 512;
+    long best = -1;
+    int bft = 256, bm = 3, bzc = (int)std::min<int64_t>(64, d.nz);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int ft : {256, 128, 64}) {
+            for (int m : {3, 4, 2}) {
+                for (int zc0 : {64, 32, 16, 8}) {
+                    if ((pass == 0) != (zc0 >= 16)) continue;
+                    const int zc = (int)std::min<int64_t>(zc0, d.nz);
+                    const FusedDims f = fused_dims(h, m, zc, ft);
+                    if (!f.ok) continue;
+                    const long th = (long)f.nwg * ft;
+                    if (th >= target) {
+                        h->ft = ft;
+                        h->fm = m;
+                        h->fzc = zc;
+                        return;
+                    }
+                    if (th > best) {
+                        best = th;
+                        bft = ft;
+                        bm = m;
+                        bzc = zc;
+                    }
+                }
+            }
         }
     }
-    h->fm = 2;
+    h->ft = bft;
+    h->fm = bm;
+    h->fzc = bzc;
 }
 
 }  // namespace
@@ -718,9 +741,9 @@ static hipError_t batch_enqueue_interval(tdse_batch_ctx* b) {
         const bool rec = b->h > 0 && j == b->S - 1;
         hipError_t e;
         if constexpr (sizeof(T) == 8)
-            e = launch_fused_batch_f64(b->W, b->M, rec, b->pf, dim3(b->total_wg), b->lds, b->stream, st);
+            e = launch_fused_batch_f64(b->W, b->M, rec, b->pf, dim3(b->total_wg), b->nt, b->lds, b->stream, st);
         else
-            e = launch_fused_batch_f32(b->W, b->M, rec, b->pf, dim3(b->total_wg), b->lds, b->stream, st);
+            e = launch_fused_batch_f32(b->W, b->M, rec, b->pf, dim3(b->total_wg), b->nt, b->lds, b->stream, st);
         if (e != hipSuccess) return e;
     }
     BatchFin f;
@@ -750,7 +773,8 @@ static tdse_status batch_prepare_t(tdse_batch_ctx* b) {
         tdse_ctx* h = b->members[i];
         h->fm = b->M;
         h->fzc = (int)std::min<int64_t>(b->zc, h->d.nz);
-        const FusedDims fd = fused_dims(h, b->M, h->fzc);
+        h->ft = b->nt;
+        const FusedDims fd = fused_dims(h, b->M, h->fzc, b->nt);
         if (!fd.ok) return bfail(b, TDSE_ERR_UNSUPPORTED, "member grid does not fit the one-pass tile");
         if (W == 0) W = fd.W;
         if (fd.W != W) return bfail(b, TDSE_ERR_UNSUPPORTED, "members need the same vector width");
@@ -1377,6 +1401,7 @@ tdse_status tdse_step(tdse_handle h, int64_t n) {
             b->M = h->fm;
             b->zc = h->fzc;
             b->pf = h->fpf;
+            b->nt = h->ft;
             b->step = h->step;
             st = d.precision == TDSE_F64 ? batch_prepare_t<double>(b) : batch_prepare_t<float>(b);
             if (st != TDSE_OK) {
@@ -1470,6 +1495,7 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
     out->fused_zc = h->fzc;
     out->fused_prefetch = h->fpf ? 1 : 0;
     out->graph = h->graph_on ? 1 : 0;
+    out->fused_threads = h->ft;
     out->vec_elems = h->W;
     out->vec_groups = h->G;
     out->lanes = h->NL;
@@ -1488,9 +1514,11 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
         return fail(h, TDSE_ERR_ARG, "fused_rows must be 2, 3, 4 or 6");
     if (h->pending != 0) return fail(h, TDSE_ERR_STATE, "pending flux partials");
     const int fzc = (int)std::min<int64_t>(t->fused_zc, h->d.nz);
+    if (t->fused_threads != 64 && t->fused_threads != 128 && t->fused_threads != 256)
+        return fail(h, TDSE_ERR_ARG, "fused_threads must be 64, 128 or 256");
     if (t->fused) {
         if (!h->R2) return fail(h, TDSE_ERR_STATE, "one-pass step needs tdse_bind_pingpong");
-        if (!fused_dims(h, t->fused_rows, fzc).ok)
+        if (!fused_dims(h, t->fused_rows, fzc, t->fused_threads).ok)
             return fail(h, TDSE_ERR_UNSUPPORTED, "one-pass tile does not fit this grid");
     }
     graph_invalidate(h);
@@ -1502,6 +1530,7 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
     h->fm = t->fused_rows;
     h->fzc = fzc;
     h->fpf = t->fused_prefetch != 0;
+    h->ft = t->fused_threads;
     return TDSE_OK;
 }
 
@@ -1670,14 +1699,17 @@ tdse_status tdse_batch_member(tdse_batch b, int32_t i, tdse_handle* h) {
     return TDSE_OK;
 }
 
-tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc, int32_t prefetch) {
+tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc, int32_t prefetch,
+                                int32_t threads) {
     if (!b) return TDSE_ERR_ARG;
+    if (threads != 64 && threads != 128 && threads != 256) return bfail(b, TDSE_ERR_ARG, "threads");
     if (fused_rows != 2 && fused_rows != 3 && fused_rows != 4 && fused_rows != 6) return bfail(b, TDSE_ERR_ARG, "fused_rows");
     if (fused_zc < 1) return bfail(b, TDSE_ERR_ARG, "fused_zc");
     batch_free_device(b);
     b->M = fused_rows;
     b->zc = fused_zc;
     b->pf = prefetch != 0;
+    b->nt = threads;
     return TDSE_OK;
 }
 

@@ -77,7 +77,8 @@ class Tile(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("waves", ctypes.c_int32), ("zc", ctypes.c_int32),
                 ("fused", ctypes.c_int32), ("fused_rows", ctypes.c_int32),
                 ("fused_zc", ctypes.c_int32), ("fused_prefetch", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("vec_elems", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("fused_threads", ctypes.c_int32),
+                ("vec_elems", ctypes.c_int32),
                 ("vec_groups", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("band_rows", ctypes.c_int32)]
 
@@ -130,7 +131,7 @@ def load():
                                      dp, dp]),
         "tdse_batch_create": (i32, [ctypes.POINTER(Desc), i32, vp, ctypes.POINTER(vp)]),
         "tdse_batch_member": (i32, [vp, i32, ctypes.POINTER(vp)]),
-        "tdse_batch_set_tile": (i32, [vp, i32, i32, i32]),
+        "tdse_batch_set_tile": (i32, [vp, i32, i32, i32, i32]),
         "tdse_batch_prepare": (i32, [vp]),
         "tdse_batch_run": (i32, [vp, i64]),
         "tdse_batch_status": (i32, [vp, ctypes.POINTER(i32)]),
@@ -395,11 +396,12 @@ class Sim:
         return t
 
     def set_tile(self, rows=None, waves=None, zc=None, fused=None, fused_rows=None,
-                 fused_zc=None, fused_prefetch=None, graph=None):
+                 fused_zc=None, fused_prefetch=None, graph=None, fused_threads=None):
         t = self.get_tile()
         for name, v in (("rows", rows), ("waves", waves), ("zc", zc), ("fused", fused),
                         ("fused_rows", fused_rows), ("fused_zc", fused_zc),
-                        ("fused_prefetch", fused_prefetch), ("graph", graph)):
+                        ("fused_prefetch", fused_prefetch), ("graph", graph),
+                        ("fused_threads", fused_threads)):
             if v is not None:
                 setattr(t, name, int(v))
         self._check(self.lib.tdse_set_tile(self.h, ctypes.byref(t)))
@@ -465,9 +467,9 @@ class Batch:
         if st != OK:
             raise TdseError(st, f"{status_string(st)}: {self.lib.tdse_batch_last_error(self.b).decode()}")
 
-    def set_tile(self, fused_rows=4, fused_zc=64, prefetch=True):
+    def set_tile(self, fused_rows=3, fused_zc=64, prefetch=False, threads=256):
         self._check(self.lib.tdse_batch_set_tile(self.b, int(fused_rows), int(fused_zc),
-                                                 int(bool(prefetch))))
+                                                 int(bool(prefetch)), int(threads)))
 
     def prepare(self):
         self.torch.cuda.synchronize(self.device)

@@ -39,11 +39,17 @@ def candidates(nz: int):
             for zc in (8, 16, 32, 64, 128, 256):
                 if zc <= nz:
                     yield dict(fused=0, rows=rows, waves=waves, zc=zc)
-    for pf in (1, 0):
-        for fr in (2, 3, 4, 6):
-            for zc in (16, 32, 64, 128, 256):
+    for ft in (256, 128, 64):
+        for fr in (2, 3, 4):
+            for zc in (8, 16, 32, 64, 128):
                 if zc <= nz:
-                    yield dict(fused=1, fused_rows=fr, fused_zc=zc, fused_prefetch=pf)
+                    yield dict(fused=1, fused_rows=fr, fused_zc=zc, fused_prefetch=0,
+                               fused_threads=ft)
+    for fr in (2, 3):
+        for zc in (16, 64):
+            if zc <= nz:
+                yield dict(fused=1, fused_rows=fr, fused_zc=zc, fused_prefetch=1,
+                           fused_threads=256)
 
 
 def autotune(sim, steps: int = 20, reps: int = 3, cands=None):
@@ -85,8 +91,8 @@ def autotune_batch(batch, intervals: int = 2, cands=None):
     res = []
     step = batch.members[0].detect().step
     interval = None
-    for tile in (cands or [(m, zc, pf) for pf in (1, 0) for m in (2, 3, 4)
-                           for zc in (16, 32, 64, 128)]):
+    for tile in (cands or [(m, zc, 0, ft) for ft in (256, 128, 64) for m in (2, 3, 4)
+                           for zc in (16, 32, 64)]):
         try:
             batch.set_tile(*tile)
             batch.prepare()

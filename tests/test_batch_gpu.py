@@ -35,13 +35,14 @@ def small_set(steps):
     return out
 
 
+@pytest.mark.parametrize("threads", [256, 64])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_batch_equals_single_runs(prec):
+def test_batch_equals_single_runs(prec, threads):
     steps = 60
     ws = small_set(steps)
-    say("batch of", [w.name for w in ws], prec)
+    say("batch of", [w.name for w in ws], prec, "threads", threads)
     b = tdse.batch_from_workloads(ws, precision=prec, steps=steps)
-    b.set_tile(fused_rows=3, fused_zc=16, prefetch=True)
+    b.set_tile(fused_rows=3, fused_zc=16, prefetch=True, threads=threads)
     b.prepare()
     b.run(steps)
     assert all(s == tdse.OK for s in b.status())

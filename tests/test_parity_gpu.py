@@ -94,7 +94,10 @@ TILES = [dict(fused=0, rows=1, waves=1, zc=4), dict(fused=0, rows=2, waves=4, zc
          dict(fused=0, rows=4, waves=2, zc=7), dict(fused=0, rows=8, waves=1, zc=128),
          dict(fused=0, rows=2, waves=3, zc=33), dict(fused=1, fused_rows=2, fused_zc=8),
          dict(fused=1, fused_rows=3, fused_zc=33), dict(fused=1, fused_rows=4, fused_zc=128),
-         dict(fused=1, fused_rows=2, fused_zc=5)]
+         dict(fused=1, fused_rows=2, fused_zc=5),
+         dict(fused=1, fused_rows=3, fused_zc=16, fused_threads=64),
+         dict(fused=1, fused_rows=2, fused_zc=7, fused_threads=128),
+         dict(fused=1, fused_rows=4, fused_zc=32, fused_threads=64, fused_prefetch=1)]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -163,8 +166,9 @@ def test_chunked_steps_and_resume_are_exact():
     first = H.gpu_run(w, 140, precision="f32")
     r, i, step, flux = first.get_state()
     second = tdse.sim_from_workload(w, precision="f32", steps=300)
-    second.records.copy_(first.records)
-    second.scalars.copy_(first.scalars)
+    nr = first.records.shape[0]
+    second.records[:nr].copy_(first.records)
+    second.scalars[:nr].copy_(first.scalars)
     second.set_state(r, i, step=step, flux=flux)
     second.step(160)
     assert bool((full.psi_r == second.psi_r).all()) and bool((full.psi_i == second.psi_i).all())

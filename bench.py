@@ -55,24 +55,31 @@ def parse():
     return p.parse_args()
 
 
+KERNEL_SOURCES = ("kernels.hpp", "dispatch.hpp", "fused.hpp", "fused_f32.hip", "fused_f64.hip",
+                  "half_f32_w4.hip", "half_f32_w2.hip", "half_f32_w1.hip", "half_f64_w2.hip",
+                  "half_f64_w1.hip")
+
+
 def kernel_src_sha():
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "dispatch.hpp", "fused.hpp"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2401_07416_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload_name, precision, kind):
+def traffic_from_profiles(workload_name, precision, kind, tile):
     """HBM bytes per launch of the dominant kernel from the committed PMC
     summary, scaled by the copy-kernel calibration; null if the kernel
-    source changed since the counters were taken."""
+    source or the tile changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{kind}_{workload_name}_{precision}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_src_sha") != kernel_src_sha():
+        return None
+    if any(tile.get(k) != v for k, v in t.get("tile", {"missing": True}).items()):
         return None
     return float(t["hbm_bytes_per_launch"])
 
@@ -298,7 +305,7 @@ def main():
         avg = tot_ms / launches
         alg_bytes = words[dom] * es * cells
         achieved = alg_bytes / (avg * 1e-3) / 1e9
-        traffic = traffic_from_profiles(w.name, prec, dom)
+        traffic = traffic_from_profiles(w.name, prec, dom, t.as_dict())
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": names[dom], "avg_launch_ms": round(avg, 5),

@@ -153,6 +153,63 @@ def secondary_fp64(steps=400):
             "hbm_gbs_alg": round(v * 40, 1), "steps": steps}
 
 
+def secondary_interp():
+    """Unit-cell interpolation (section 2.3) onto the 512x512x1024 FP32 mesh
+    from a 24x28x360-sample cell table: the paper's pipeline bottleneck
+    (step (ii) of section 3.2), here one HBM-bound setup kernel."""
+    import torch
+
+    from paper_2401_07416_amd import tdse, workloads
+    table = torch.from_numpy(workloads.unit_cell_table()).cuda()
+    d = tdse.make_desc(512, 512, 1024, 0.2, 0.2, 0.2, 0.6582119569, 0.0568563, precision="f32")
+    s = tdse.Sim(d, pingpong=False)
+    sp = (2.556 / 24, 4.427 / 28, 0.2)
+    s.interpolate_potential(table, sp)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(s.stream)
+    for _ in range(reps):
+        s.interpolate_potential(table, sp)
+    e1.record(s.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    cells = 512 * 512 * 1024
+    return {"workload": "unit-cell table 24x28x360 -> 512x512x1024 FP32 mesh", "ms": round(ms, 3),
+            "gcells_per_s": round(cells / (ms * 1e-3) / 1e9, 1),
+            "write_gbs": round(4 * cells / (ms * 1e-3) / 1e9, 1)}
+
+
+def secondary_dissim(K=879, T=77, P=128 * 128):
+    """Eq. (16) over the paper's sample size (879 trajectories), 77 frames
+    of 128x128 detector pixels, FP32: the pairwise contraction on the vector
+    ALU (3 flops per pair, frame and pixel)."""
+    import torch
+
+    from paper_2401_07416_amd import tdse
+    g = torch.Generator(device="cuda")
+    g.manual_seed(16)
+    frames = torch.rand((K, T, P), generator=g, device="cuda", dtype=torch.float32)
+    w = torch.full((T,), 1.0 / T, dtype=torch.float64, device="cuda")
+    tdse.dissimilarity(frames, w, 0.04)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        tdse.dissimilarity(frames, w, 0.04)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = 3.0 * K * (K - 1) / 2 * T * P
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"workload": f"d_kj of {K} trajectories x {T} frames x {P} pixels, FP32", "ms": round(ms, 2),
+            "tflops_alg": round(tf, 1), "bound": "alu", "peak_tflops_fp32_vector": 157.3,
+            "frac": round(tf / 157.3, 4)}
+
+
 def secondary_adjoint():
     """Plain forward, checkpointed forward and adjoint of the 128x128x256,
     4000-step gradient workload in FP32, timed with HIP events."""
@@ -294,10 +351,12 @@ def main():
     es = 8 if prec == "f64" else 4
     # algorithmic bytes per launch: a half-step reads the stencil array, the
     # updated array and V and writes the updated array (4 words per cell); the
-    # one-pass step reads R, I, V and writes R, I (5 words per cell)
-    words = {"half_i": 4, "half_r": 4, "fused": 5}
+    # one-pass step reads R, I, V and writes R, I (5 words per cell); the
+    # two-step sweep moves the same 5 words per cell for two steps
+    words = {"half_i": 4, "half_r": 4, "fused": 5, "two_step": 5}
     names = {"half_i": "half_step eq.(9) imaginary", "half_r": "half_step eq.(8) real",
-             "fused": "fused_step eqs.(9)+(8) one-pass"}
+             "fused": "fused_step eqs.(9)+(8) one-pass",
+             "two_step": "fused2 two-step sweep eqs.(9)+(8)+(9)+(8)"}
     roof = None
     dom = max(kt, key=lambda k: kt[k][0])
     tot_ms, launches = kt[dom]
@@ -312,8 +371,9 @@ def main():
                 "alg_bytes_per_launch": alg_bytes,
                 "launches": {k: v[1] for k, v in kt.items()},
                 "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()}}
-    fused_share = kt["fused"][1] / max(1, a.steps)
-    bytes_per_cell_step = es * (5 * fused_share + 8 * (1 - fused_share))
+    # algorithmic bytes per cell-step of the launches the timed steps ran
+    alg_words = sum(words[k] * kt[k][1] for k in kt)
+    bytes_per_cell_step = es * alg_words / max(1, a.steps)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-steps/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms / a.steps, 5),
@@ -330,10 +390,22 @@ def main():
         "hbm_bytes_per_cell_step_alg": bytes_per_cell_step,
         "hbm_gbs_whole_step": round(value * bytes_per_cell_step, 1),
     }
+    if roof is not None:
+        # the practical ceiling: streaming kernels with the copy's and the
+        # one-pass step's mix of read and written streams, 1 GiB per stream
+        try:
+            copy_gbs = tdse.hbm_probe("copy")
+            mix_gbs = tdse.hbm_probe("mix")
+            roof["practical"] = {"copy_gbs": round(copy_gbs, 1), "mix_gbs": round(mix_gbs, 1),
+                                 "frac_of_mix": round(roof["achieved"] / mix_gbs, 4)}
+        except Exception as e:  # measurement context only
+            roof["practical"] = {"error": str(e)}
+        torch.cuda.empty_cache()
     if not a.no_secondary:
         sec = {}
         for name, fn in (("fp64", secondary_fp64), ("adjoint", secondary_adjoint),
-                         ("batched", secondary_batch)):
+                         ("batched", secondary_batch), ("interpolation", secondary_interp),
+                         ("dissimilarity", secondary_dissim)):
             try:
                 sec[name] = fn()
             except Exception as ex:  # reported, never hidden

@@ -186,6 +186,23 @@ tdse_status tdse_bind(tdse_handle h, void* psi_r, void* psi_i, void* v, void* wo
 tdse_status tdse_build_potential(tdse_handle h, const tdse_atom* atoms, int64_t n,
                                  const tdse_pot_params* p);
 
+/* Fill the bound V by interpolating a potential given on one unit cell
+ * (section 2.3: the potential of one cell is repeated in x and y and
+ * interpolated onto the mesh points; the paper does not name the scheme,
+ * this is trilinear).  table: device memory, double [uz][uy][ux], x
+ * fastest, owned by the caller and read only; its sample (a, b, c) sits at
+ * origin + (a sx, b sy, c sz) with spacing = {sx, sy, sz} > 0 and origin
+ * host arrays of 3.  The cell repeats in x and y with periods ux sx and
+ * uy sy; beyond the first and last table planes in z the table is held
+ * constant.  Mesh point (i, j, k) sits at (i dx, j dy, k dz).  Computed in
+ * FP64, stored in the state precision; asynchronous on the handle's stream
+ * (the table must stay valid until the stream reaches the call).  Like
+ * tdse_build_potential it replaces V before tdse_finalize_setup.
+ * TDSE_ERR_ARG for null pointers, sizes < 1 or more than 2^31 samples,
+ * non-positive spacing; TDSE_ERR_STATE before tdse_bind. */
+tdse_status tdse_interpolate_potential(tdse_handle h, const double* table, int32_t ux, int32_t uy,
+                                      int32_t uz, const double* spacing, const double* origin);
+
 /* CAP rates W[nz] >= 0 (host memory, energy units); NULL clears the CAP. */
 tdse_status tdse_set_cap(tdse_handle h, const double* w, int64_t nz);
 
@@ -331,29 +348,79 @@ tdse_status tdse_batch_destroy(tdse_batch b);
 /* Kernel timing for measurement: when enabled, each step kernel launch is
  * bracketed by HIP events on the handle's stream.  tdse_timing_read
  * synchronises and returns, per kernel kind (0: eq. (9) half-step, 1: eq. (8)
- * half-step, 2: one-pass step), the summed kernel milliseconds ms[3] and
- * launch counts count[3] since the last read, and clears them. */
+ * half-step, 2: one-pass step, 3: two-step sweep), the summed kernel
+ * milliseconds ms[4] and launch counts count[4] since the last read, and
+ * clears them. */
 tdse_status tdse_set_timing(tdse_handle h, int32_t enable);
 tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count);
+
+/* Trajectory dissimilarity, eq. (16) (section 3.2): for trajectories k, j
+ * the time average over [t0, t1] of the L2 distance between their
+ * detector-plane densities,
+ *   out[k][j] = sum_t w[t] sqrt(dA sum_p (frames[k][t][p] - frames[j][t][p])^2),
+ * the time integral as a quadrature over the frames with weights w (which
+ * carry the 1 / (t1 - t0)), the plane integral as dA (pixel area) times the
+ * pixel sum.  frames: device, [K][T][P] in precision (TDSE_F32 or
+ * TDSE_F64), the trajectories on a common detector grid and common frame
+ * times (records of configurations with equal grids and time steps);
+ * weights: device double [T]; out: device double [K][K] (symmetric, zero
+ * diagonal); workspace: device, >= tdse_dissimilarity_workspace_size bytes.
+ * All caller-owned.  The sums are formed from the differences (no
+ * cancellation), FP32 frames in FP32 over chunks of 32 pixels and FP64
+ * beyond; the result is bitwise reproducible.  Asynchronous on stream (a
+ * hipStream_t, may be null).  TDSE_ERR_ARG for null pointers, sizes < 1,
+ * dA <= 0 or a short workspace; TDSE_ERR_DEVICE for launch errors. */
+tdse_status tdse_dissimilarity_workspace_size(int32_t K, int32_t T, size_t* bytes);
+tdse_status tdse_dissimilarity(int32_t precision, const void* frames, int32_t K, int32_t T, int64_t P,
+                               const double* weights, double dA, double* out, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
+/* HBM probe: the practical bandwidth ceiling of this device, measured by
+ * streaming kernels that do no part of the method.  kind 0: a copy, bufs[0]
+ * -> bufs[1]; kind 1: the one-pass step's mix, three read streams bufs[0..2]
+ * and two written streams bufs[3..4] (d = a + b c, e = b - a c, elementwise).
+ * Each buffer is n floats (n a multiple of 4) of device memory, 16-byte
+ * aligned, all distinct, owned by the caller; the written buffers are
+ * overwritten.  grid = workgroups of 256 threads (0: 4096).  Runs one warm-up
+ * pass and reps timed passes on stream (a hipStream_t, may be null),
+ * synchronises it and returns the average milliseconds per pass in
+ * *ms_per_pass.  TDSE_ERR_ARG for bad arguments, TDSE_ERR_DEVICE for HIP
+ * errors. */
+tdse_status tdse_hbm_probe(int32_t kind, void* const* bufs, int64_t n, int32_t grid, int32_t reps,
+                           void* stream, double* ms_per_pass);
 
 /* Tile shapes.  Two-pass half-step kernels: rows = y rows per wavefront (1,
  * 2, 4 or 8), waves = wavefronts per workgroup (1..4), zc = z planes per
  * workgroup.  One-pass kernel: fused != 0 selects it (needs
- * tdse_bind_pingpong), fused_rows = rows per thread (2, 3, 4 or 6; the band
- * is band_rows = (fused_threads / threads per row) * fused_rows - 2 rows), fused_zc =
- * z planes per workgroup, fused_prefetch != 0 issues the next plane's loads
- * before the current plane's eq. (8) part.  graph != 0 (default) lets
- * tdse_step replay a captured HIP graph for whole record intervals of
- * one-pass steps when the handle's stream is not the null stream, timing is
- * off and no adjoint is bound (h even, <= 256).  tdse_create picks
- * defaults; tdse_set_tile checks and replaces them.  fused_threads = threads
- * per workgroup of the one-pass kernel (64, 128 or 256; the band is
- * (fused_threads / threads per row) * fused_rows - 2 rows).  The last four
- * fields are read-only. */
+ * tdse_bind_pingpong), fused_rows = rows per thread (2, 3, 4 or 6),
+ * fused_threads = threads per workgroup (64, 128 or 256), so the band is
+ * band_rows = (fused_threads / threads per row) * fused_rows - 2 rows;
+ * fused_zc = z planes per workgroup, fused_prefetch != 0 issues the next
+ * plane's loads before the current plane's eq. (8) part.  graph != 0
+ * (default) lets tdse_step replay a captured HIP graph for whole record
+ * intervals of one-pass steps when the handle's stream is not the null
+ * stream, timing is off, no adjoint is bound and the two-step sweep is off
+ * (h even, <= 256).
+ *
+ * Two-step sweep (temporal blocking: eqs. (9), (8), (9), (8) in one pass,
+ * 20 B per cell per two steps in FP32): two_step != 0 selects it on top of
+ * the one-pass kernel (which still takes single steps: a step whose level
+ * is recorded first, an odd last step, the level before an adjoint
+ * checkpoint).  two_step_tx = interior tile width (a multiple of the vector
+ * width, >= 8), two_step_rows = rows per thread (2 or 3), so the interior
+ * tile height is two_step_ty = (256 / ((tx + 8) / vector width)) * rows - 8
+ * (read-only); two_step_zc = z planes per workgroup, two_step_prefetch != 0
+ * loads the next plane's inputs one iteration ahead.  The sweep needs at
+ * most ny tiles per plane and its LDS ((2 x 4) buffers of (ty + 10) x (tx +
+ * 8) values) within the device's per-workgroup limit.
+ *
+ * tdse_create picks defaults; tdse_set_tile checks and replaces them.  The
+ * last five fields are read-only. */
 typedef struct tdse_tile {
     int32_t rows, waves, zc;
     int32_t fused, fused_rows, fused_zc, fused_prefetch, graph, fused_threads;
-    int32_t vec_elems, vec_groups, lanes, band_rows;
+    int32_t two_step, two_step_tx, two_step_rows, two_step_zc, two_step_prefetch;
+    int32_t vec_elems, vec_groups, lanes, band_rows, two_step_ty;
 } tdse_tile;
 
 tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out);

@@ -18,6 +18,11 @@ Parity status of each function (the pins live in ``tests/test_oracle_*.py``):
       periodic images, brute-force points)
   adjoint / potential_vjp             : pinned (central finite differences of the
       forward oracle, directional derivatives, checkpoint-interval invariance)
+  interp_potential                    : pinned (coincident grids copy the table,
+      fields linear in each axis are reproduced, cell periodicity, a
+      library trilinear interpolator on a periodically padded table)
+  dissimilarity                       : pinned (metric axioms, a closed form
+      for constant frames, brute force with numpy)
 """
 from __future__ import annotations
 
@@ -121,6 +126,10 @@ def lib():
         L.og_unstep.argtypes = [sp, ctypes.c_int64]
         L.og_adjoint.argtypes = [sp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp, _dp]
         L.og_adjoint.restype = ctypes.c_int
+        L.og_interp_potential.argtypes = [gp, _dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                          _dp, _dp, _dp]
+        L.og_dissimilarity.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _dp,
+                                       ctypes.c_double, _dp]
         L.og_potential_vjp.argtypes = [gp, _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp,
                                        _dp]
@@ -353,3 +362,27 @@ class Sim:
                             _ptr(gV), _ptr(gR), _ptr(gI)) != 0:
             raise MemoryError("oracle adjoint allocation")
         return gV, gR, gI
+
+
+def interp_potential(grid: Grid, table: np.ndarray, spacing, origin=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Trilinear interpolation of a unit-cell table [uz][uy][ux] (periodic in
+    x and y, held constant beyond its z range) onto the mesh (section 2.3)."""
+    table = np.ascontiguousarray(table, dtype=np.float64)
+    uz, uy, ux = table.shape
+    sp = np.ascontiguousarray(spacing, dtype=np.float64)
+    org = np.ascontiguousarray(origin, dtype=np.float64)
+    V = np.zeros(grid.shape)
+    lib().og_interp_potential(grid.ref(), _ptr(table), ux, uy, uz, _ptr(sp), _ptr(org), _ptr(V))
+    return V
+
+
+def dissimilarity(frames: np.ndarray, weights, dA: float) -> np.ndarray:
+    """d_kj of eq. (16) for frames [K][T][P] with time-quadrature weights w[T]
+    (including 1 / (t1 - t0)) and pixel area dA."""
+    frames = np.ascontiguousarray(frames, dtype=np.float64)
+    K, T, P = frames.shape
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    assert w.shape == (T,)
+    out = np.zeros((K, K))
+    lib().og_dissimilarity(_ptr(frames), K, T, P, _ptr(w), float(dA), _ptr(out))
+    return out

@@ -809,3 +809,92 @@ void og_potential_vjp(const og_grid* g, const double* atoms, int64_t n, double s
         damp[a] = sa;
     }
 }
+
+/*
+ * Potential on the mesh from a table over one unit cell (section 2.3: the
+ * potential of one cell, repeated in x and y and interpolated onto the mesh
+ * points; the interpolation is step (ii) of section 3.2).  The paper does not
+ * name the interpolation; this is trilinear.
+ *
+ * table is [uz][uy][ux], x fastest; sample (a, b, c) sits at
+ * (origin[0] + a sx, origin[1] + b sy, origin[2] + c sz) with s = spacing.
+ * The cell repeats in x and y with periods ux sx and uy sy; in z the table is
+ * held constant beyond its first and last sample planes.  Mesh point
+ * (i, j, k) sits at (i dx, j dy, k dz).
+ */
+static void og_axis_weights_periodic(double u, int64_t n, int64_t* a0, int64_t* a1, double* t) {
+    const double f = floor(u);
+    *t = u - f;
+    int64_t a = (int64_t)f % n;
+    if (a < 0) a += n;
+    *a0 = a;
+    *a1 = (a + 1) % n;
+}
+
+void og_interp_potential(const og_grid* g, const double* table, int64_t ux, int64_t uy, int64_t uz,
+                         const double* spacing, const double* origin, double* V) {
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < g->nz; ++k) {
+        /* z: clamp to the table's z range */
+        int64_t c0 = 0, c1 = 0;
+        double tz = 0.0;
+        if (uz > 1) {
+            double w = (k * g->dz - origin[2]) / spacing[2];
+            if (w < 0.0) w = 0.0;
+            if (w > (double)(uz - 1)) w = (double)(uz - 1);
+            c0 = (int64_t)floor(w);
+            if (c0 > uz - 2) c0 = uz - 2;
+            tz = w - (double)c0;
+            c1 = c0 + 1;
+        }
+        for (int64_t j = 0; j < g->ny; ++j) {
+            int64_t b0, b1;
+            double ty;
+            og_axis_weights_periodic((j * g->dy - origin[1]) / spacing[1], uy, &b0, &b1, &ty);
+            for (int64_t i = 0; i < g->nx; ++i) {
+                int64_t a0, a1;
+                double tx;
+                og_axis_weights_periodic((i * g->dx - origin[0]) / spacing[0], ux, &a0, &a1, &tx);
+#define OG_T(a, b, c) table[((c) * uy + (b)) * ux + (a)]
+                /* x, then y, then z */
+                const double v00 = (1.0 - tx) * OG_T(a0, b0, c0) + tx * OG_T(a1, b0, c0);
+                const double v10 = (1.0 - tx) * OG_T(a0, b1, c0) + tx * OG_T(a1, b1, c0);
+                const double v01 = (1.0 - tx) * OG_T(a0, b0, c1) + tx * OG_T(a1, b0, c1);
+                const double v11 = (1.0 - tx) * OG_T(a0, b1, c1) + tx * OG_T(a1, b1, c1);
+#undef OG_T
+                const double v0 = (1.0 - ty) * v00 + ty * v10;
+                const double v1 = (1.0 - ty) * v01 + ty * v11;
+                V[og_idx(g, i, j, k)] = (1.0 - tz) * v0 + tz * v1;
+            }
+        }
+    }
+}
+
+/*
+ * Dissimilarity of detection-plane trajectories, eq. (16): for trajectories
+ * k and j, the time average over [t0, t1] of the L2 distance between their
+ * detector-plane densities.  frames is [K][T][P] (trajectory, frame, pixel);
+ * the time integral is the quadrature sum over frames with weights w[T]
+ * (which carry the 1/(t1 - t0)); the plane integral is dA times the pixel
+ * sum.  out[k][j] = sum_t w_t sqrt(dA sum_p (rho_k,t,p - rho_j,t,p)^2).
+ */
+void og_dissimilarity(const double* frames, int64_t K, int64_t T, int64_t P, const double* w,
+                      double dA, double* out) {
+#pragma omp parallel for schedule(dynamic)
+    for (int64_t k = 0; k < K; ++k) {
+        for (int64_t j = 0; j < K; ++j) {
+            double d = 0.0;
+            for (int64_t t = 0; t < T; ++t) {
+                const double* a = frames + (k * T + t) * P;
+                const double* b = frames + (j * T + t) * P;
+                double s = 0.0;
+                for (int64_t p = 0; p < P; ++p) {
+                    const double e = a[p] - b[p];
+                    s += e * e;
+                }
+                d += w[t] * sqrt(dA * s);
+            }
+            out[k * K + j] = d;
+        }
+    }
+}

@@ -1,0 +1,375 @@
+// Two leapfrog steps per sweep: eqs. (9), (8), (9), (8) of arXiv 2401.07416
+// section 2.1 chained in one z-marching pass (temporal blocking of depth
+// two).  The sweep reads (R^n, I^{n-1/2}, V) once and writes (R^{n+2},
+// I^{n+3/2}) once, 20 B per cell in FP32 for two steps, where the one-pass
+// step moves 20 B per step.  The intermediate level (I^{n+1/2}, R^{n+1})
+// never leaves the chip.
+//
+// Mapping.  A workgroup owns an interior tile of tx x ty cells of every
+// plane of a z chunk, and works on the tile extended by four cells on each
+// side in x and y (ex = tx + 8, ey = ty + 8): each of the four half-steps
+// needs its input one cell further out than its output, so the region on
+// which a phase result is exact shrinks by one cell per phase, from the
+// whole extension for the loaded R^n to the interior for R^{n+2}.  Results
+// on the shrinking rim are computed and discarded.
+//
+// Per iteration k of the z march the four phases run one plane apart:
+//   A1  I^{n+1/2}(k+3)  from R^n(k+2..k+4)
+//   B1  R^{n+1}(k+2)    from I^{n+1/2}(k+1..k+3)
+//   A2  I^{n+3/2}(k+1)  from R^{n+1}(k..k+2)
+//   B2  R^{n+2}(k)      from I^{n+3/2}(k-1..k+1)
+// Each thread keeps the three-plane z windows of the four fields and four
+// planes of V in registers (its W-wide x vectors of M extended rows).  The x
+// and y neighbours of each phase's centre plane come from LDS, where the
+// previous iteration left them: every phase reads the LDS buffers of parity
+// k and writes those of parity k + 1, so one barrier per iteration orders
+// all reads and writes.  The march starts six planes before the chunk so
+// that every stored plane is exact.
+//
+// The cell arithmetic is lap7 / update_I / update_R of kernels.hpp, so the
+// states are bitwise identical to those of the one-pass and two-pass steps.
+// The flux partials of both steps (every step) and, on the second step only,
+// the record fields are reduced per workgroup in a fixed order.
+#pragma once
+
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace tdse {
+
+template <typename T>
+struct Fused2Args {
+    const T* R0;  // R^n
+    const T* I0;  // I^{n-1/2}
+    T* R1;        // R^{n+2}
+    T* I1;        // I^{n+3/2}
+    const T* V;
+    const T* ca;
+    const T* cb;
+    T cx, cy, cz, cv;
+    int nx, ny, nz;
+    int tx, ty, ex, ey;   // interior and extended tile extents
+    int tpr, rpp;         // threads per extended row, extended rows per pass
+    int ntx, ntiles, zc, nzc, nwg;
+    int bcx, bcy, bcz;
+    int k_det, k_up;
+    double* flux_a;       // [2][ntiles], step n -> n+1
+    double* flux_b;       // [2][ntiles], step n+1 -> n+2
+    // record of level n+2 (REC instances only)
+    T* rec_plane;
+    double* part_q;       // [nzc][ntiles]
+    double* part_naive;
+    double* part_plane;   // [ntiles]
+    double* pixel;
+    double pixel_w;
+};
+
+template <typename T, int W, int M, bool REC, bool PF>
+__device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsigned char* smem_raw) {
+    using VT = vec_t<T, W>;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int ex = a.ex, ey = a.ey;
+    const int pbytes = (int)((long)nx * ny * (long)sizeof(T));
+    const long fstride = (long)(ey + 2) * ex;   // one LDS buffer with a pad row on each side
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    // field f (0 R^n, 1 I^{n+1/2}, 2 R^{n+1}, 3 I^{n+3/2}), parity q: row 0
+    auto buf = [&](int f, int q) -> T* { return lds + (2 * f + q) * fstride + ex; };
+
+    const int zchunk = L / a.ntiles;
+    const int tile = L - zchunk * a.ntiles;
+    const int tyi = tile / a.ntx;
+    const int txi = tile - tyi * a.ntx;
+    const int x0 = txi * a.tx, y0 = tyi * a.ty;
+    const int k0 = zchunk * a.zc;
+    const int k1 = min(k0 + a.zc, nz);
+    const int tid = threadIdx.x;
+    const int rs0 = tid / a.tpr;
+    const bool live = rs0 < a.rpp;             // threads past the last full row idle
+    const int rs = live ? rs0 : 0;
+    const int c0 = (live ? tid - rs0 * a.tpr : 0) * W;   // extended column of the vector
+    const int gx = x0 - 4 + c0;                          // unwrapped grid column
+    int colg = gx;
+    if (gx < 0 || gx >= nx) colg = a.bcx ? -1 : ((gx % nx) + nx) % nx;
+    const bool xin = c0 >= 4 && c0 < 4 + a.tx && gx < nx;
+
+    int rowb[M], voff[M], soff[M];
+    bool zc_cell[M];   // cell outside a zero-boundary axis (or idle thread): forced to 0
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        rowb[i] = rs + i * a.rpp;
+        const int gy = y0 - 4 + rowb[i];
+        int rj = gy;
+        if (gy < 0 || gy >= ny) rj = a.bcy ? -1 : ((gy % ny) + ny) % ny;
+        const bool ok = live && rj >= 0 && colg >= 0;
+        zc_cell[i] = !ok;
+        voff[i] = ok ? (rj * nx + colg) * (int)sizeof(T) : OOB;
+        const bool st = live && xin && rowb[i] >= 4 && rowb[i] < 4 + a.ty && gy < ny;
+        soff[i] = st ? voff[i] : OOB;
+    }
+    auto gplane = [&](int p) -> int {
+        if (p < 0) {
+            if (a.bcz) return -1;
+            do p += nz; while (p < 0);
+        } else if (p >= nz) {
+            if (a.bcz) return -1;
+            do p -= nz; while (p >= nz);
+        }
+        return p;
+    };
+    auto prs = [&](const T* base, int gp) {
+        return plane_rsrc(base + (long)(gp < 0 ? 0 : gp) * nx * ny, gp < 0 ? 0 : pbytes);
+    };
+    auto zero_vec = [&]() {
+        VT z;
+#pragma unroll
+        for (int e = 0; e < W; ++e) z.v[e] = T(0);
+        return z;
+    };
+
+    // z windows at the start of iteration k: Rn[0..1] = R^n(k+2..k+3),
+    // Ia = I^{n+1/2}(k+1..k+2), Rb = R^{n+1}(k..k+1), Ib = I^{n+3/2}(k-1..k),
+    // Vw[0..2] = V(k..k+2).  The iteration loads R^n(k+4) into Rn[2],
+    // I^{n-1/2}(k+3) into io and V(k+3) into Vw[3], and adds one plane to
+    // each field.
+    VT Rn[3][M], Ia[2][M], Rb[2][M], Ib[2][M], Vw[4][M], io[M];
+    VT pR[M], pI[M], pV[M];   // prefetched inputs of the next iteration
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            Ia[s][i] = zero_vec();
+            Rb[s][i] = zero_vec();
+            Ib[s][i] = zero_vec();
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Vw[s][i] = zero_vec();
+    }
+
+    // one phase on plane p: centre c, z neighbours zl / zr, x / y neighbours
+    // from LDS buffer src (the centre plane), old value uo, potential v;
+    // IS_R selects eq. (8), else eq. (9).  The result goes to out and, from
+    // live threads, to LDS buffer dst (if not null).
+    auto phase = [&](auto is_r, int p, const VT(&zl)[M], const VT(&c)[M], const VT(&zr)[M],
+                     const T* src, const VT(&uo)[M], const VT(&v)[M], VT(&out)[M], T* dst) {
+        constexpr bool IS_R = decltype(is_r)::value;
+        const int gp = gplane(p);
+        const T cap = gp >= 0 ? a.ca[gp] : T(1);
+        const T cbp = gp >= 0 ? a.cb[gp] : T(1);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const T* row = src + rowb[i] * ex + c0;
+            const VT yl = *reinterpret_cast<const VT*>(row - ex);
+            const VT yr = *reinterpret_cast<const VT*>(row + ex);
+            const T xle = row[-1], xre = row[W];
+            const bool zero = zc_cell[i] || gp < 0;
+            VT o;
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                const T cc = c[i].v[e];
+                const T xl = e > 0 ? c[i].v[e - 1] : xle;
+                const T xr = e < W - 1 ? c[i].v[e + 1] : xre;
+                const T lap = lap7(cc, xl, xr, yl.v[e], yr.v[e], zl[i].v[e], zr[i].v[e], a.cx, a.cy, a.cz);
+                const T u = IS_R ? update_R(lap, v[i].v[e], cc, uo[i].v[e], a.cv, cap, cbp)
+                                 : update_I(lap, v[i].v[e], cc, uo[i].v[e], a.cv, cap, cbp);
+                o.v[e] = zero ? T(0) : u;
+            }
+            out[i] = o;
+            if (dst && live) *reinterpret_cast<VT*>(dst + rowb[i] * ex + c0) = o;
+        }
+    };
+    using IsR = std::integral_constant<bool, true>;
+    using IsI = std::integral_constant<bool, false>;
+
+    auto load3 = [&](int pr, int pi, VT(&r)[M], VT(&iv)[M], VT(&vv)[M]) {
+        const int gr = gplane(pr), gi = gplane(pi);
+        const auto rR = prs(a.R0, gr), rI = prs(a.I0, gi), rV = prs(a.V, gi);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            r[i] = bload<T, W>(rR, voff[i]);
+            iv[i] = bload<T, W>(rI, voff[i]);
+            vv[i] = bload<T, W>(rV, voff[i]);
+        }
+    };
+
+    const int ks = k0 - 6;
+    // prologue: R^n(ks+2), R^n(ks+3) into the window, R^n(ks+3) staged for A1
+    {
+        const auto r2 = prs(a.R0, gplane(ks + 2)), r3 = prs(a.R0, gplane(ks + 3));
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            Rn[0][i] = bload<T, W>(r2, voff[i]);
+            Rn[1][i] = bload<T, W>(r3, voff[i]);
+        }
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) *reinterpret_cast<VT*>(buf(0, 0) + rowb[i] * ex + c0) = Rn[1][i];
+        }
+        if (PF) load3(ks + 4, ks + 3, pR, pI, pV);
+    }
+    __syncthreads();
+
+    double fa0 = 0.0, fa1 = 0.0, fb0 = 0.0, fb1 = 0.0, q = 0.0, nv = 0.0, pl = 0.0;
+    for (int k = ks; k < k1; ++k) {
+        const int par = (k - ks) & 1;
+        if (PF) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                Rn[2][i] = pR[i];
+                io[i] = pI[i];
+                Vw[3][i] = pV[i];
+            }
+            if (k + 1 < k1) load3(k + 5, k + 4, pR, pI, pV);
+        } else {
+            load3(k + 4, k + 3, Rn[2], io, Vw[3]);
+        }
+        // stage R^n(k+4) for the next iteration's A1
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) *reinterpret_cast<VT*>(buf(0, par ^ 1) + rowb[i] * ex + c0) = Rn[2][i];
+        }
+        VT nA[M], nB[M], nC[M], nD[M];
+        // A1: I^{n+1/2}(k+3)
+        phase(IsI{}, k + 3, Rn[0], Rn[1], Rn[2], buf(0, par), io, Vw[3], nA, buf(1, par ^ 1));
+        // B1: R^{n+1}(k+2)
+        phase(IsR{}, k + 2, Ia[0], Ia[1], nA, buf(1, par), Rn[0], Vw[2], nB, buf(2, par ^ 1));
+        // A2: I^{n+3/2}(k+1)
+        phase(IsI{}, k + 1, Rb[0], Rb[1], nB, buf(2, par), Ia[0], Vw[1], nC, buf(3, par ^ 1));
+        // B2: R^{n+2}(k)
+        phase(IsR{}, k, Ib[0], Ib[1], nC, buf(3, par), Rb[0], Vw[0], nD, nullptr);
+        const int pB = k + 2, pC = k + 1, pD = k;
+        if (pC >= k0 && pC < k1) {
+            const auto rI = prs(a.I1, pC);
+#pragma unroll
+            for (int i = 0; i < M; ++i) bstore<T, W>(rI, soff[i], nC[i]);
+        }
+        if (pD >= k0) {
+            const auto rR = prs(a.R1, pD);
+#pragma unroll
+            for (int i = 0; i < M; ++i) bstore<T, W>(rR, soff[i], nD[i]);
+        }
+        // flux partials of both steps over the stored cells
+        const bool inB = pB >= k0 && pB < k1;
+        // (the two faces are the same plane when nz = 1)
+        if (inB && (pB == a.k_det || pB == a.k_up)) {
+            const bool det = pB == a.k_det, up = pB == a.k_up;
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                if (soff[i] == OOB) continue;
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    const double s = (double)Rn[0][i].v[e] + (double)nB[i].v[e];
+                    if (det) fa0 += (double)nA[i].v[e] * s;
+                    if (up) fa1 += (double)Ia[0][i].v[e] * s;
+                }
+            }
+        }
+        if (pD >= k0 && (pD == a.k_det || pD == a.k_up)) {
+            const bool det = pD == a.k_det, up = pD == a.k_up;
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                if (soff[i] == OOB) continue;
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    const double s = (double)Rb[0][i].v[e] + (double)nD[i].v[e];
+                    if (det) fb0 += (double)nC[i].v[e] * s;
+                    if (up) fb1 += (double)Ib[0][i].v[e] * s;
+                }
+            }
+        }
+        if (REC && pD >= k0) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                if (soff[i] == OOB) continue;
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    const double dc = (double)Ib[1][i].v[e], du = (double)Rb[0][i].v[e];
+                    const double dn = (double)nD[i].v[e];
+                    q += dc * dc + du * dn;
+                    nv += dn * dn + dc * dc;
+                }
+                if (pD == a.k_det) {
+                    VT rv;
+                    const long poff = soff[i] / (int)sizeof(T);
+#pragma unroll
+                    for (int e = 0; e < W; ++e) {
+                        const double dn = (double)nD[i].v[e], dc = (double)Ib[1][i].v[e];
+                        const double rho = dn * dn + dc * dc;
+                        rv.v[e] = (T)rho;
+                        pl += rho;
+                        if (a.pixel) a.pixel[poff + e] += a.pixel_w * rho;
+                    }
+                    stv<T, W>(a.rec_plane + poff, rv);
+                }
+            }
+        }
+        // shift the windows one plane up
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            Rn[0][i] = Rn[1][i];
+            Rn[1][i] = Rn[2][i];
+            Ia[0][i] = Ia[1][i];
+            Ia[1][i] = nA[i];
+            Rb[0][i] = Rb[1][i];
+            Rb[1][i] = nB[i];
+            Ib[0][i] = Ib[1][i];
+            Ib[1][i] = nC[i];
+            Vw[0][i] = Vw[1][i];
+            Vw[1][i] = Vw[2][i];
+            Vw[2][i] = Vw[3][i];
+        }
+        __syncthreads();
+    }
+
+    // fixed-order workgroup sums of the partials
+    __shared__ double red[256];
+    const bool has_det = a.k_det >= k0 && a.k_det < k1;
+    const bool has_up = a.k_up >= k0 && a.k_up < k1;
+    auto wg_sum = [&](double v) -> double {
+        __syncthreads();
+        red[tid] = v;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o && tid + o < (int)blockDim.x) red[tid] += red[tid + o];
+            __syncthreads();
+        }
+        return red[0];
+    };
+    if (has_det) {
+        const double sa = wg_sum(fa0);
+        const double sb = wg_sum(fb0);
+        if (tid == 0) {
+            a.flux_a[tile] = sa;
+            a.flux_b[tile] = sb;
+        }
+    }
+    if (has_up) {
+        const double sa = wg_sum(fa1);
+        const double sb = wg_sum(fb1);
+        if (tid == 0) {
+            a.flux_a[a.ntiles + tile] = sa;
+            a.flux_b[a.ntiles + tile] = sb;
+        }
+    }
+    if (REC) {
+        const double sq = wg_sum(q);
+        const double sn = wg_sum(nv);
+        const long slot = (long)zchunk * a.ntiles + tile;
+        if (tid == 0) {
+            a.part_q[slot] = sq;
+            a.part_naive[slot] = sn;
+        }
+        if (has_det) {
+            const double sp = wg_sum(pl);
+            if (tid == 0) a.part_plane[tile] = sp;
+        }
+    }
+}
+
+template <typename T, int W, int M, bool REC, bool PF>
+__global__ __launch_bounds__(256) void fused2_kernel(Fused2Args<T> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    fused2_body<T, W, M, REC, PF>(a, xcd_remap(blockIdx.x, a.nwg), smem_raw);
+}
+
+}  // namespace tdse

@@ -370,4 +370,61 @@ __global__ __launch_bounds__(256) void potential_vjp_kernel(VjpArgs p) {
     }
 }
 
+// Potential from a table over one unit cell (section 2.3: the cell's
+// potential is repeated in x and y and interpolated onto the mesh points),
+// trilinear.  Sample (a, b, c) of the table [uz][uy][ux] sits at origin +
+// (a sx, b sy, c sz); the cell repeats in x and y, and the table is held
+// constant beyond its first and last z planes.
+struct InterpArgs {
+    const double* table;
+    int ux, uy, uz;
+    double sx, sy, sz, ox, oy, oz;
+    int nx, ny, nz;
+    double dx, dy, dz;
+};
+
+// fractional table coordinate u -> lower sample (wrapped), upper sample and weight
+__device__ __forceinline__ void cell_axis(double u, int n, int* a0, int* a1, double* t) {
+    const double f = floor(u);
+    *t = u - f;
+    long a = (long)f % n;
+    if (a < 0) a += n;
+    *a0 = (int)a;
+    *a1 = (int)((a + 1) % n);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void interp_potential_kernel(InterpArgs a, T* V) {
+    const long nxy = (long)a.nx * a.ny;
+    const long n = nxy * a.nz;
+    for (long c = (long)blockIdx.x * 256 + threadIdx.x; c < n; c += (long)gridDim.x * 256) {
+        const int k = (int)(c / nxy);
+        const long r = c - (long)k * nxy;
+        const int j = (int)(r / a.nx);
+        const int i = (int)(r - (long)j * a.nx);
+        int x0, x1, y0, y1, z0 = 0, z1 = 0;
+        double tx, ty, tz = 0.0;
+        cell_axis(((double)i * a.dx - a.ox) / a.sx, a.ux, &x0, &x1, &tx);
+        cell_axis(((double)j * a.dy - a.oy) / a.sy, a.uy, &y0, &y1, &ty);
+        if (a.uz > 1) {
+            double w = ((double)k * a.dz - a.oz) / a.sz;
+            w = fmin(fmax(w, 0.0), (double)(a.uz - 1));
+            z0 = min((int)floor(w), a.uz - 2);
+            tz = w - (double)z0;
+            z1 = z0 + 1;
+        }
+        const double* p0 = a.table + (long)z0 * a.uy * a.ux;
+        const double* p1 = a.table + (long)z1 * a.uy * a.ux;
+        const long r0 = (long)y0 * a.ux, r1 = (long)y1 * a.ux;
+        const double sx = 1.0 - tx, sy = 1.0 - ty;
+        const double b00 = sx * p0[r0 + x0] + tx * p0[r0 + x1];
+        const double b10 = sx * p0[r1 + x0] + tx * p0[r1 + x1];
+        const double b01 = sx * p1[r0 + x0] + tx * p1[r0 + x1];
+        const double b11 = sx * p1[r1 + x0] + tx * p1[r1 + x1];
+        const double c0 = sy * b00 + ty * b10;
+        const double c1 = sy * b01 + ty * b11;
+        V[c] = (T)((1.0 - tz) * c0 + tz * c1);
+    }
+}
+
 }  // namespace tdse

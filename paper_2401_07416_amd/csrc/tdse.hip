@@ -19,6 +19,7 @@
 #include "kernels.hpp"
 #include "setup_kernels.hpp"
 #include "fused.hpp"
+#include "fused2.hpp"
 #include "adjoint.hpp"
 
 using namespace tdse;
@@ -40,6 +41,11 @@ struct tdse_ctx {
     int fm = 3, fzc = 64, ft = 256;
     bool fpf = false;
     bool fused = false;
+    // two-step sweep: interior tile width, rows per thread, z chunk
+    bool two = false;
+    int t2x = 56, t2m = 2, t2zc = 64;
+    bool t2pf = false;
+    int lds_max = 65536;   // dynamic + static LDS per workgroup of the device
     // adjoint: checkpoints every adj_K steps of an adj_N-step forward run
     void* adj_ws = nullptr;
     int64_t adj_N = 0;
@@ -244,6 +250,10 @@ hipError_t launch_fused_batch_f64(int w, int m, bool rec, bool pf, dim3 grid, in
                                   hipStream_t st, const BatchStep<double>& b);
 hipError_t launch_fused_f64(int w, int m, bool rec, bool pf, dim3 grid, int nt, size_t lds, hipStream_t st,
                             const FusedArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_fused2_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+                             const Fused2Args<float>& a, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_fused2_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+                             const Fused2Args<double>& a, hipEvent_t e0, hipEvent_t e1);
 }  // namespace tdse
 
 namespace {
@@ -314,7 +324,7 @@ HalfArgs<T> make_args(tdse_ctx* h, int mode, int rows, int waves, int zc, long r
 }
 
 // Event pair around the next launch when timing is on.  kind: 0 = eq. (9)
-// half-step, 1 = eq. (8) half-step, 2 = one-pass step.
+// half-step, 1 = eq. (8) half-step, 2 = one-pass step, 3 = two-step sweep.
 tdse_status timing_events(tdse_ctx* h, int kind, hipEvent_t* e0, hipEvent_t* e1) {
     *e0 = *e1 = nullptr;
     if (!h->timing) return TDSE_OK;
@@ -446,6 +456,115 @@ tdse_status launch_fused(tdse_ctx* h, const FusedDims& f, bool rec, long rec_idx
         e = launch_fused_f32(f.W, h->fm, rec, h->fpf, dim3(f.nwg), f.threads, f.lds, h->stream, a, e0, e1);
     }
     return hip_check(h, e, "one-pass step launch");
+}
+
+// Geometry of the two-step sweep for interior tile width tx, rows per
+// thread m and z chunk zc (256 threads per workgroup).
+struct Fused2Dims {
+    int W, tx, ty, ex, ey, tpr, rpp, ntx, nty, ntiles, nzc, nwg;
+    size_t lds;
+    bool ok;
+};
+
+Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc) {
+    const tdse_desc& d = h->d;
+    Fused2Dims f{};
+    f.ok = false;
+    const int es = d.precision == TDSE_F64 ? 8 : 4;
+    const int wl32[3] = {4, 2, 1}, wl64[2] = {2, 1};
+    const int* wl = es == 8 ? wl64 : wl32;
+    const int nw = es == 8 ? 2 : 3;
+    if (tx < 8 || (m != 2 && m != 3) || zc < 1) return f;
+    f.W = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (d.nx % wl[i] == 0 && tx % wl[i] == 0 && (tx + 8) / wl[i] <= 256) {
+            f.W = wl[i];
+            break;
+        }
+    }
+    if (!f.W) return f;
+    f.tx = tx;
+    f.ex = tx + 8;
+    f.tpr = f.ex / f.W;
+    f.rpp = 256 / f.tpr;
+    f.ey = f.rpp * m;
+    f.ty = f.ey - 8;
+    if (f.ty < 1) return f;
+    f.ntx = (int)((d.nx + tx - 1) / tx);
+    f.nty = (int)((d.ny + f.ty - 1) / f.ty);
+    f.ntiles = f.ntx * f.nty;
+    f.nzc = (int)((d.nz + zc - 1) / zc);
+    f.nwg = f.ntiles * f.nzc;
+    f.lds = (size_t)8 * (f.ey + 2) * f.ex * es;
+    // flux and partial slots are sized for ny per step / plane; 2 KB of
+    // static LDS for the reductions
+    f.ok = f.ntiles <= d.ny && f.lds + 2048 <= (size_t)h->lds_max &&
+           (long)f.nwg < (1L << 31);
+    return f;
+}
+
+template <typename T>
+Fused2Args<T> make_fused2_args(tdse_ctx* h, const Fused2Dims& f, bool rec, long rec_idx,
+                               int flux_slot) {
+    const tdse_desc& d = h->d;
+    Fused2Args<T> a;
+    a.R0 = static_cast<const T*>(h->R);
+    a.I0 = static_cast<const T*>(h->I);
+    a.R1 = static_cast<T*>(h->R2);
+    a.I1 = static_cast<T*>(h->I2);
+    a.V = static_cast<const T*>(h->V);
+    a.ca = static_cast<const T*>(h->ca);
+    a.cb = static_cast<const T*>(h->cb);
+    a.cx = (T)h->c[0];
+    a.cy = (T)h->c[1];
+    a.cz = (T)h->c[2];
+    a.cv = (T)h->c[3];
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    a.tx = f.tx;
+    a.ty = f.ty;
+    a.ex = f.ex;
+    a.ey = f.ey;
+    a.tpr = f.tpr;
+    a.rpp = f.rpp;
+    a.ntx = f.ntx;
+    a.ntiles = f.ntiles;
+    a.zc = h->t2zc;
+    a.nzc = f.nzc;
+    a.nwg = f.nwg;
+    a.bcx = d.bc[0] == TDSE_BC_ZERO;
+    a.bcy = d.bc[1] == TDSE_BC_ZERO;
+    a.bcz = d.bc[2] == TDSE_BC_ZERO;
+    a.k_det = (int)d.k_det;
+    const bool has_up = !(a.bcz && d.k_det + 1 >= d.nz);
+    a.k_up = has_up ? (int)((d.k_det + 1) % d.nz) : -1;
+    a.flux_a = h->flux_ring + (size_t)flux_slot * 2 * f.ntiles;
+    a.flux_b = h->flux_ring + (size_t)(flux_slot + 1) * 2 * f.ntiles;
+    a.rec_plane = rec ? static_cast<T*>(h->rec) + (size_t)rec_idx * d.nx * d.ny : nullptr;
+    a.part_q = h->part_q;
+    a.part_naive = h->part_naive;
+    a.part_plane = h->part_plane;
+    a.pixel = (rec && (d.flags & TDSE_FLAG_PIXEL_INTEGRAL)) ? h->pix : nullptr;
+    a.pixel_w = (double)d.record_every * h->dt;
+    return a;
+}
+
+// Two steps n -> n+2 into the second state pair; the record of level n+2
+// if rec.  Flux partials go to ring slots flux_slot and flux_slot + 1.
+tdse_status launch_fused2(tdse_ctx* h, const Fused2Dims& f, bool rec, long rec_idx, int flux_slot) {
+    hipEvent_t e0, e1;
+    tdse_status s = timing_events(h, 3, &e0, &e1);
+    if (s != TDSE_OK) return s;
+    hipError_t e;
+    if (h->d.precision == TDSE_F64) {
+        Fused2Args<double> a = make_fused2_args<double>(h, f, rec, rec_idx, flux_slot);
+        e = launch_fused2_f64(f.W, h->t2m, rec, h->t2pf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+    } else {
+        Fused2Args<float> a = make_fused2_args<float>(h, f, rec, rec_idx, flux_slot);
+        e = launch_fused2_f32(f.W, h->t2m, rec, h->t2pf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+    }
+    return hip_check(h, e, "two-step sweep launch");
 }
 
 // Fold n_pending steps of flux partials (slots per step each) into the
@@ -932,8 +1051,13 @@ tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out) {
         delete h;
         return TDSE_ERR_DEVICE;
     }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess &&
+        lds > 0)
+        h->lds_max = lds;
     default_tile(h);
     default_fused_tile(h);
+    h->t2zc = (int)std::min<int64_t>(h->t2zc, d->nz);
     h->wcap.assign((size_t)d->nz, 0.0);
     *out = h;
     return TDSE_OK;
@@ -1117,6 +1241,43 @@ static tdse_status upload_tables(tdse_ctx* h) {
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return TDSE_OK;
+}
+
+tdse_status tdse_interpolate_potential(tdse_handle h, const double* table, int32_t ux, int32_t uy,
+                                      int32_t uz, const double* spacing, const double* origin) {
+    if (!h || !table || !spacing || !origin || ux < 1 || uy < 1 || uz < 1) return TDSE_ERR_ARG;
+    if (!h->bound) return fail(h, TDSE_ERR_STATE, "bind before building the potential");
+    for (int c = 0; c < 3; ++c)
+        if (!(spacing[c] > 0) || !std::isfinite(spacing[c]) || !std::isfinite(origin[c]))
+            return fail(h, TDSE_ERR_ARG, "bad table spacing or origin");
+    if ((int64_t)ux * uy * uz > ((int64_t)1 << 31)) return fail(h, TDSE_ERR_ARG, "table too large");
+    const tdse_desc& d = h->d;
+    InterpArgs a;
+    a.table = table;
+    a.ux = ux;
+    a.uy = uy;
+    a.uz = uz;
+    a.sx = spacing[0];
+    a.sy = spacing[1];
+    a.sz = spacing[2];
+    a.ox = origin[0];
+    a.oy = origin[1];
+    a.oz = origin[2];
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    a.dx = d.dx;
+    a.dy = d.dy;
+    a.dz = d.dz;
+    const long n = (long)d.nx * d.ny * d.nz;
+    const unsigned g = (unsigned)std::min<long>((n + 255) / 256, 32768);
+    if (d.precision == TDSE_F64)
+        hipLaunchKernelGGL(interp_potential_kernel<double>, dim3(g), dim3(256), 0, h->stream, a,
+                           static_cast<double*>(h->V));
+    else
+        hipLaunchKernelGGL(interp_potential_kernel<float>, dim3(g), dim3(256), 0, h->stream, a,
+                           static_cast<float*>(h->V));
+    return hip_check(h, hipGetLastError(), "interpolation launch");
 }
 
 tdse_status tdse_set_cap(tdse_handle h, const double* w, int64_t nz) {
@@ -1311,18 +1472,62 @@ tdse_status tdse_get_state(tdse_handle h, void* psi_r, void* psi_i, int64_t* ste
     return TDSE_OK;
 }
 
+// The step loop.  Each step runs as one of: OP_H, the two in-place
+// half-step kernels; OP_F1, the one-pass kernel into the second state pair;
+// OP_F2, the two-step sweep into the second pair.  F1 and F2 swap the pairs,
+// so the plan keeps their count even and the state ends in the bound
+// arrays.  A pair of steps goes to F2 unless the level between them is
+// recorded or checkpointed.
+enum StepOp : char { OP_H = 0, OP_F1 = 1, OP_F2 = 2 };
+
 static tdse_status step_plain(tdse_ctx* h, int64_t n) {
     const tdse_desc& d = h->d;
     const int64_t hrec = d.record_every;
-    // one-pass steps come in pairs so the state ends in the bound buffers;
-    // an odd step runs as two in-place half-steps
     const FusedDims fd = fused_dims(h, h->fm, h->fzc);
     const bool use_fused = h->fused && h->R2 && fd.ok;
-    const int64_t n_fused = use_fused ? (n / 2) * 2 : 0;
+    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc);
+    const bool use_f2 = use_fused && h->two && f2.ok;
     const TileDims td = tile_dims(h, h->rows, h->waves, h->zc);
-    for (int64_t it = 0; it < n; ++it) {
+    auto is_rec = [&](int64_t s) { return hrec > 0 && (s + 1) % hrec == 0; };
+    auto ckpt_at = [&](int64_t level) {
+        return h->adj_ws && level < h->adj_N && level % h->adj_K == 0;
+    };
+    std::vector<char> ops;
+    ops.reserve((size_t)n);
+    for (int64_t i = 0; i < n;) {
+        const int64_t s = h->step + i;
+        if (use_f2 && i + 1 < n && !is_rec(s) && !ckpt_at(s + 1)) {
+            ops.push_back(OP_F2);
+            i += 2;
+        } else {
+            ops.push_back(use_fused ? OP_F1 : OP_H);
+            i += 1;
+        }
+    }
+    if (use_fused && ops.size() % 2 == 1) {
+        size_t j = ops.size();
+        while (j > 0 && ops[j - 1] != OP_F1) --j;
+        if (j > 0) {
+            ops[j - 1] = OP_H;
+        } else {
+            j = ops.size();
+            while (ops[j - 1] != OP_F2) --j;
+            ops[j - 1] = OP_F1;
+            ops.insert(ops.begin() + (long)j, (char)OP_F1);
+        }
+    }
+    // flux slots per step and partial slots per record of each kind
+    auto slots_of = [&](char op) { return op == OP_F2 ? f2.ntiles : op == OP_F1 ? fd.nbands : td.ytiles; };
+    auto parts_of = [&](char op) {
+        return op == OP_F2 ? (long)f2.nzc * f2.ntiles
+                           : op == OP_F1 ? (long)fd.nzc * fd.nbands : (long)td.nzc * td.ytiles;
+    };
+    char pend_op = OP_H;
+    tdse_status st;
+    for (char op : ops) {
         const int64_t s = h->step;
-        if (h->adj_ws && s < h->adj_N && s % h->adj_K == 0) {
+        const int k = op == OP_F2 ? 2 : 1;
+        if (ckpt_at(s)) {
             // checkpoint of level s for the adjoint
             const AdjLayout L = adj_layout(d, h->adj_N, h->adj_K);
             char* w = static_cast<char*>(h->adj_ws) + L.ckpt + 2 * (size_t)(s / h->adj_K) * L.arr;
@@ -1330,19 +1535,21 @@ static tdse_status step_plain(tdse_ctx* h, int64_t n) {
             HIPCHK(h, hipMemcpyAsync(w, h->R, bytes, hipMemcpyDeviceToDevice, h->stream));
             HIPCHK(h, hipMemcpyAsync(w + L.arr, h->I, bytes, hipMemcpyDeviceToDevice, h->stream));
         }
-        const bool record = hrec > 0 && ((s + 1) % hrec == 0);
-        const long rec_idx = record ? (long)((s + 1) / hrec) : 0;
-        const bool fused = it < n_fused;
-        const int slots = fused ? fd.nbands : td.ytiles;
-        const long nparts = fused ? (long)fd.nzc * fd.nbands : (long)td.nzc * td.ytiles;
-        if (!fused && it == n_fused && h->pending > 0) {
-            // partial slots of one-pass steps use another layout: fold them first
-            tdse_status st = launch_finalize(h, h->pending, false, 0, fd.nbands, 0);
+        // partial slots of another kind or a full ring: fold them first
+        if (h->pending > 0 && (op != pend_op || h->pending + k > h->F)) {
+            st = launch_finalize(h, h->pending, false, 0, slots_of(pend_op), 0);
             if (st != TDSE_OK) return st;
             h->pending = 0;
         }
-        tdse_status st;
-        if (fused) {
+        pend_op = op;
+        const bool record = is_rec(s + k - 1);
+        const long rec_idx = record ? (long)((s + k) / hrec) : 0;
+        if (op == OP_F2) {
+            st = launch_fused2(h, f2, record, rec_idx, h->pending);
+            if (st != TDSE_OK) return st;
+            std::swap(h->R, h->R2);
+            std::swap(h->I, h->I2);
+        } else if (op == OP_F1) {
             st = launch_fused(h, fd, record, rec_idx, h->pending);
             if (st != TDSE_OK) return st;
             std::swap(h->R, h->R2);
@@ -1354,17 +1561,16 @@ static tdse_status step_plain(tdse_ctx* h, int64_t n) {
                              h->pending);
             if (st != TDSE_OK) return st;
         }
-        h->pending += 1;
-        h->step += 1;
+        h->pending += k;
+        h->step += k;
         if (record || h->pending == h->F) {
-            st = launch_finalize(h, h->pending, record, rec_idx, slots, nparts);
+            st = launch_finalize(h, h->pending, record, rec_idx, slots_of(op), parts_of(op));
             if (st != TDSE_OK) return st;
             h->pending = 0;
         }
     }
     if (h->pending > 0) {
-        const bool last_fused = n_fused == n;
-        tdse_status st = launch_finalize(h, h->pending, false, 0, last_fused ? fd.nbands : td.ytiles, 0);
+        st = launch_finalize(h, h->pending, false, 0, slots_of(pend_op), 0);
         if (st != TDSE_OK) return st;
         h->pending = 0;
     }
@@ -1379,8 +1585,10 @@ tdse_status tdse_step(tdse_handle h, int64_t n) {
     if (hrec > 0 && (h->step + n) / hrec + 1 > d.max_records)
         return fail(h, TDSE_ERR_CAPACITY, "record buffer would overflow");
     const FusedDims fd = fused_dims(h, h->fm, h->fzc);
+    const bool two = h->two && fused2_dims(h, h->t2x, h->t2m, h->t2zc).ok;
     const bool graph_ok = h->fused && h->R2 && fd.ok && h->graph_on && h->stream != nullptr &&
-                          !h->timing && !h->adj_ws && hrec > 0 && hrec % 2 == 0 && hrec <= 256;
+                          !h->timing && !h->adj_ws && !two && hrec > 0 && hrec % 2 == 0 &&
+                          hrec <= 256;
     if (!graph_ok) return step_plain(h, n);
     // plain steps up to the next record level, graph replays of whole
     // intervals, plain steps for the rest
@@ -1470,7 +1678,7 @@ tdse_status tdse_set_timing(tdse_handle h, int32_t enable) {
 tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count) {
     if (!h || !ms || !count) return TDSE_ERR_ARG;
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         ms[k] = 0.0;
         count[k] = 0;
     }
@@ -1496,6 +1704,13 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
     out->fused_prefetch = h->fpf ? 1 : 0;
     out->graph = h->graph_on ? 1 : 0;
     out->fused_threads = h->ft;
+    out->two_step = h->two ? 1 : 0;
+    out->two_step_tx = h->t2x;
+    out->two_step_rows = h->t2m;
+    out->two_step_zc = h->t2zc;
+    out->two_step_prefetch = h->t2pf ? 1 : 0;
+    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc);
+    out->two_step_ty = f2.ok ? f2.ty : 0;
     out->vec_elems = h->W;
     out->vec_groups = h->G;
     out->lanes = h->NL;
@@ -1521,6 +1736,13 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
         if (!fused_dims(h, t->fused_rows, fzc, t->fused_threads).ok)
             return fail(h, TDSE_ERR_UNSUPPORTED, "one-pass tile does not fit this grid");
     }
+    if (t->two_step_zc < 1) return fail(h, TDSE_ERR_ARG, "z chunks must be >= 1");
+    const int t2zc = (int)std::min<int64_t>(t->two_step_zc, h->d.nz);
+    if (t->two_step) {
+        if (!t->fused) return fail(h, TDSE_ERR_ARG, "the two-step sweep runs with the one-pass step");
+        if (!fused2_dims(h, t->two_step_tx, t->two_step_rows, t2zc).ok)
+            return fail(h, TDSE_ERR_UNSUPPORTED, "two-step tile does not fit this grid");
+    }
     graph_invalidate(h);
     h->rows = t->rows;
     h->waves = t->waves;
@@ -1531,6 +1753,11 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
     h->fzc = fzc;
     h->fpf = t->fused_prefetch != 0;
     h->ft = t->fused_threads;
+    h->two = t->two_step != 0;
+    h->t2x = t->two_step_tx;
+    h->t2m = t->two_step_rows;
+    h->t2zc = t2zc;
+    h->t2pf = t->two_step_prefetch != 0;
     return TDSE_OK;
 }
 

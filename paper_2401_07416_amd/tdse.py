@@ -34,7 +34,8 @@ EXPORTS = [
     "tdse_bind_pingpong", "tdse_adjoint_workspace_size", "tdse_bind_adjoint", "tdse_adjoint",
     "tdse_potential_vjp", "tdse_batch_create", "tdse_batch_member", "tdse_batch_set_tile",
     "tdse_batch_prepare", "tdse_batch_run", "tdse_batch_status", "tdse_batch_last_error",
-    "tdse_batch_destroy",
+    "tdse_batch_destroy", "tdse_hbm_probe", "tdse_interpolate_potential",
+    "tdse_dissimilarity_workspace_size", "tdse_dissimilarity",
 ]
 
 
@@ -78,9 +79,12 @@ class Tile(ctypes.Structure):
                 ("fused", ctypes.c_int32), ("fused_rows", ctypes.c_int32),
                 ("fused_zc", ctypes.c_int32), ("fused_prefetch", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("fused_threads", ctypes.c_int32),
+                ("two_step", ctypes.c_int32), ("two_step_tx", ctypes.c_int32),
+                ("two_step_rows", ctypes.c_int32), ("two_step_zc", ctypes.c_int32),
+                ("two_step_prefetch", ctypes.c_int32),
                 ("vec_elems", ctypes.c_int32),
                 ("vec_groups", ctypes.c_int32), ("lanes", ctypes.c_int32),
-                ("band_rows", ctypes.c_int32)]
+                ("band_rows", ctypes.c_int32), ("two_step_ty", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -139,6 +143,11 @@ def load():
         "tdse_batch_destroy": (i32, [vp]),
         "tdse_get_tile": (i32, [vp, ctypes.POINTER(Tile)]),
         "tdse_set_tile": (i32, [vp, ctypes.POINTER(Tile)]),
+        "tdse_hbm_probe": (i32, [i32, ctypes.POINTER(vp), i64, i32, i32, vp, dp]),
+        "tdse_interpolate_potential": (i32, [vp, vp, i32, i32, i32, dp, dp]),
+        "tdse_dissimilarity_workspace_size": (i32, [i32, i32, ctypes.POINTER(ctypes.c_size_t)]),
+        "tdse_dissimilarity": (i32, [i32, vp, i32, i32, i64, vp, ctypes.c_double, vp, vp,
+                                     ctypes.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -284,6 +293,19 @@ class Sim:
         p = PotParams(float(soft), float(cutoff), float(kappa), float(a0), int(bool(screened)), 0)
         self._check(self.lib.tdse_build_potential(self.h, arr, len(atoms), ctypes.byref(p)))
 
+    def interpolate_potential(self, table, spacing, origin=(0.0, 0.0, 0.0)):
+        """Fill V by trilinear interpolation of a unit-cell table [uz][uy][ux]
+        (FP64; a numpy array or a device tensor), periodic in x and y."""
+        import torch
+        t = torch.as_tensor(table, dtype=torch.float64).to(self.device).contiguous()
+        uz, uy, ux = t.shape
+        sp = (ctypes.c_double * 3)(*[float(x) for x in spacing])
+        org = (ctypes.c_double * 3)(*[float(x) for x in origin])
+        with torch.cuda.device(self.device):
+            self._check(self.lib.tdse_interpolate_potential(self.h, ctypes.c_void_p(t.data_ptr()),
+                                                            ux, uy, uz, sp, org))
+            self.stream.synchronize()  # the table must outlive the launch
+
     def set_cap(self, w: Optional[np.ndarray]):
         if w is None:
             self._check(self.lib.tdse_set_cap(self.h, None, self.desc.nz))
@@ -384,11 +406,12 @@ class Sim:
         self._check(self.lib.tdse_set_timing(self.h, int(bool(on))))
 
     def timing_read(self):
-        """{kind: (ms, launches)} for 'half_i', 'half_r', 'fused' since the last read."""
-        ms = (ctypes.c_double * 3)()
-        n = (ctypes.c_int64 * 3)()
+        """{kind: (ms, launches)} for 'half_i', 'half_r', 'fused', 'two_step'
+        since the last read."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
         self._check(self.lib.tdse_timing_read(self.h, ms, n))
-        return {k: (ms[i], n[i]) for i, k in enumerate(("half_i", "half_r", "fused"))}
+        return {k: (ms[i], n[i]) for i, k in enumerate(("half_i", "half_r", "fused", "two_step"))}
 
     def get_tile(self) -> Tile:
         t = Tile()
@@ -396,15 +419,71 @@ class Sim:
         return t
 
     def set_tile(self, rows=None, waves=None, zc=None, fused=None, fused_rows=None,
-                 fused_zc=None, fused_prefetch=None, graph=None, fused_threads=None):
+                 fused_zc=None, fused_prefetch=None, graph=None, fused_threads=None,
+                 two_step=None, two_step_tx=None, two_step_rows=None, two_step_zc=None,
+                 two_step_prefetch=None):
         t = self.get_tile()
         for name, v in (("rows", rows), ("waves", waves), ("zc", zc), ("fused", fused),
                         ("fused_rows", fused_rows), ("fused_zc", fused_zc),
                         ("fused_prefetch", fused_prefetch), ("graph", graph),
-                        ("fused_threads", fused_threads)):
+                        ("fused_threads", fused_threads), ("two_step", two_step),
+                        ("two_step_tx", two_step_tx), ("two_step_rows", two_step_rows),
+                        ("two_step_zc", two_step_zc), ("two_step_prefetch", two_step_prefetch)):
             if v is not None:
                 setattr(t, name, int(v))
         self._check(self.lib.tdse_set_tile(self.h, ctypes.byref(t)))
+
+
+def hbm_probe(kind: str = "copy", gib: float = 1.0, grid: int = 0, reps: int = 5, device=None):
+    """Practical HBM bandwidth of the device in GB/s: 'copy' (one read and
+    one written stream) or 'mix' (the one-pass step's three read and two
+    written streams), over buffers of `gib` GiB each."""
+    import torch
+    lib = load()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    n = int(gib * (1 << 30)) // 16 * 4
+    k = {"copy": 0, "mix": 1}[kind]
+    bufs = [torch.ones(n, dtype=torch.float32, device=dev) for _ in range(2 if k == 0 else 5)]
+    ptrs = (ctypes.c_void_p * len(bufs))(*[b.data_ptr() for b in bufs])
+    ms = ctypes.c_double()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    st = lib.tdse_hbm_probe(k, ptrs, n, int(grid), int(reps), ctypes.c_void_p(stream), ctypes.byref(ms))
+    if st != OK:
+        raise TdseError(st, lib.tdse_status_string(st).decode())
+    nbytes = len(bufs) * n * 4
+    del bufs
+    return nbytes / (ms.value * 1e-3) / 1e9
+
+
+def dissimilarity(frames, weights, dA: float):
+    """d_kj of eq. (16) on the GPU: frames [K][T][P] (a float32 or float64
+    CUDA tensor), time-quadrature weights [T] (with the 1 / (t1 - t0)), pixel
+    area dA.  Returns a [K][K] float64 CUDA tensor."""
+    import torch
+    lib = load()
+    if frames.dim() != 3 or not frames.is_cuda:
+        raise ValueError("frames must be a [K][T][P] CUDA tensor")
+    prec = {torch.float32: F32, torch.float64: F64}[frames.dtype]
+    frames = frames.contiguous()
+    K, T, P = frames.shape
+    dev = frames.device
+    w = torch.as_tensor(weights, dtype=torch.float64).to(dev).contiguous()
+    if w.shape != (T,):
+        raise ValueError("weights must have one entry per frame")
+    nb = ctypes.c_size_t()
+    st = lib.tdse_dissimilarity_workspace_size(K, T, ctypes.byref(nb))
+    if st != OK:
+        raise TdseError(st, lib.tdse_status_string(st).decode())
+    ws = torch.empty(max(1, nb.value // 8), dtype=torch.float64, device=dev)
+    out = torch.empty((K, K), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    st = lib.tdse_dissimilarity(prec, ctypes.c_void_p(frames.data_ptr()), K, T, P,
+                                ctypes.c_void_p(w.data_ptr()), float(dA),
+                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                nb.value, ctypes.c_void_p(stream))
+    if st != OK:
+        raise TdseError(st, lib.tdse_status_string(st).decode())
+    return out
 
 
 def sim_from_workload(w, precision: Optional[str] = None, steps: Optional[int] = None,

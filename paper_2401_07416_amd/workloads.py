@@ -257,6 +257,32 @@ def ragged(precision: str = "f64", seed: int = 11) -> Workload:
                     k_det=20, record_every=7, precision=precision)
 
 
+def unit_cell_table(seed: int = 7, ux: int = 24, uy: int = 28, uz: int = 360,
+                    cell=(2.556, 4.427), z_top: float = 28.35, wells: int = 6):
+    """Synthetic stand-in for a DFT potential of one surface unit cell (the
+    paper's tables are DFT output, not available here): a table [uz][uy][ux]
+    in eV on a cell of cell[0] x cell[1] A and uz planes 0.2 A apart, with
+    a few deep periodic wells per layer below z_top and a smooth decay into
+    the vacuum above it.  Seeded; no part of the method."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(ux) * cell[0] / ux
+    y = np.arange(uy) * cell[1] / uy
+    z = np.arange(uz) * 0.2
+    X, Y = np.meshgrid(x, y)
+    t = np.zeros((uz, uy, ux))
+    for layer in range(4):
+        zl = z_top - 2.1 * layer
+        for _ in range(wells):
+            cx, cy = rng.uniform(0, cell[0]), rng.uniform(0, cell[1])
+            dx = (X - cx + cell[0] / 2) % cell[0] - cell[0] / 2
+            dy = (Y - cy + cell[1] / 2) % cell[1] - cell[1] / 2
+            r2 = dx ** 2 + dy ** 2
+            depth = rng.uniform(20.0, 60.0)
+            t -= depth * np.exp(-r2[None] / 0.18 - (z[:, None, None] - zl) ** 2 / 0.18)
+    t -= 8.0 / (1.0 + np.exp((z - z_top) / 0.7))[:, None, None]
+    return t
+
+
 def random_state(shape, seed: int):
     """Seeded smooth-ish random initial arrays (for pins that need generic data)."""
     rng = np.random.default_rng(seed)

@@ -19,9 +19,11 @@ def wave_vector(w, k_of_energy):
     return k_of_energy(w.energy, w.hbar, w.mass) * np.array(w.k_dir, dtype=np.float64)
 
 
-def oracle_setup(w):
+def oracle_setup(w, V=None):
     g = oracle_grid(w)
-    if w.atoms is not None and len(w.atoms):
+    if V is not None:
+        pass
+    elif w.atoms is not None and len(w.atoms):
         V = oracle.potential(g, w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
                              screened=w.screened)
     else:
@@ -33,8 +35,8 @@ def oracle_setup(w):
     return g, V, W, dt, R, I
 
 
-def oracle_run(w, steps, pixel=False):
-    g, V, W, dt, R, I = oracle_setup(w)
+def oracle_run(w, steps, pixel=False, V=None):
+    g, V, W, dt, R, I = oracle_setup(w, V)
     s = oracle.Sim(g, V, R, I, dt, W=W, k_det=w.k_det, record_every=w.record_every,
                    max_records=max(w.n_records(steps), 1), pixel=pixel)
     if w.record_every > 0:

@@ -212,6 +212,25 @@ tdse_status tdse_set_cap(tdse_handle h, const double* w, int64_t nz);
  *   W_k = w_max ((k - (nz-1-n_top))/n_top)^2 for k >= nz - n_top. */
 tdse_status tdse_set_cap_quadratic(tdse_handle h, int64_t n_bottom, int64_t n_top, double w_max);
 
+/* The CAP as eq. (10) prints it, one-sided at the bottom of the domain:
+ * W_k = (alpha / dz) (r_cut - k dz)^2 for k dz < r_cut, else 0 (rates in
+ * energy units, applied as in tdse_set_cap).  The paper's constant is
+ * garbled (alpha = 1e8 eV with an electron charge, and r_cut = 0, which
+ * would leave the region empty; section 2.3 instead appends 100 planes at
+ * the bottom for the CAP); here alpha is energy per length and r_cut a
+ * length, both >= 0, so r_cut = 100 dz over an appended region of 100
+ * planes reproduces the paper's set-up.  TDSE_ERR_ARG for negative or
+ * non-finite values. */
+tdse_status tdse_set_cap_paper(tdse_handle h, double alpha, double r_cut);
+
+/* The time step eq. (11) recommends, dt = m min(dx, dy, dz)^2 / (5 hbar),
+ * for d's spacings and units (host only).  It exceeds the Gershgorin
+ * bound hbar / E_max that tdse_finalize_setup enforces (by 1.2x on a cubic
+ * grid with V = 0, more with a deep V) while staying inside the exact
+ * leapfrog limit 2 hbar / max|E| when V is shallow: to run with it, pass it
+ * as d->dt with TDSE_FLAG_ALLOW_UNSTABLE. */
+tdse_status tdse_time_step_paper(const tdse_desc* d, double* dt);
+
 /* Reduce min/max of V on the device, form E_max and dt, and build the
  * per-plane coefficient tables.  Synchronises.  Returns TDSE_ERR_UNSTABLE
  * if an absolute dt exceeds hbar / E_max and TDSE_FLAG_ALLOW_UNSTABLE is

@@ -21,6 +21,9 @@ Parity status of each function (the pins live in ``tests/test_oracle_*.py``):
   interp_potential                    : pinned (coincident grids copy the table,
       fields linear in each axis are reproduced, cell periodicity, a
       library trilinear interpolator on a periodically padded table)
+  cap_paper / dt_paper                : pinned (support, value at the bottom plane,
+      constant second difference; the 0.48 as of the paper's grid and the
+      1.2 ratio to the Gershgorin step on a free cubic grid)
   dissimilarity                       : pinned (metric axioms, a closed form
       for constant frames, brute force with numpy)
 """
@@ -126,6 +129,10 @@ def lib():
         L.og_unstep.argtypes = [sp, ctypes.c_int64]
         L.og_adjoint.argtypes = [sp, ctypes.c_int64, _dp, ctypes.c_int64, _dp, _dp, _dp]
         L.og_adjoint.restype = ctypes.c_int
+        L.og_cap_paper.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, _dp]
+        L.og_dt_paper.argtypes = [gp]
+        L.og_dt_paper.restype = ctypes.c_double
         L.og_interp_potential.argtypes = [gp, _dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                           _dp, _dp, _dp]
         L.og_dissimilarity.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _dp,
@@ -386,3 +393,15 @@ def dissimilarity(frames: np.ndarray, weights, dA: float) -> np.ndarray:
     out = np.zeros((K, K))
     lib().og_dissimilarity(_ptr(frames), K, T, P, _ptr(w), float(dA), _ptr(out))
     return out
+
+
+def cap_paper(nz: int, dz: float, alpha: float, r_cut: float) -> np.ndarray:
+    """Eq. (10) as printed, one-sided at the bottom (alpha: energy / length)."""
+    W = np.zeros(int(nz))
+    lib().og_cap_paper(int(nz), float(dz), float(alpha), float(r_cut), _ptr(W))
+    return W
+
+
+def dt_paper(grid: Grid) -> float:
+    """Eq. (11): m min(dx, dy, dz)^2 / (5 hbar)."""
+    return float(lib().og_dt_paper(grid.ref()))

@@ -898,3 +898,23 @@ void og_dissimilarity(const double* frames, int64_t K, int64_t T, int64_t P, con
         }
     }
 }
+
+/*
+ * The CAP of eq. (10) taken literally, one-sided at the bottom: a rate
+ * W_k = (alpha / dz) (r_cut - k dz)^2 where k dz < r_cut, else 0.  The
+ * paper's constant is garbled; alpha is read as energy per length.
+ */
+void og_cap_paper(int64_t nz, double dz, double alpha, double r_cut, double* W) {
+    for (int64_t k = 0; k < nz; ++k) {
+        const double z = k * dz;
+        W[k] = (z < r_cut) ? alpha / dz * (r_cut - z) * (r_cut - z) : 0.0;
+    }
+}
+
+/* The time step eq. (11) recommends: m min(dx, dy, dz)^2 / (5 hbar). */
+double og_dt_paper(const og_grid* g) {
+    double d = g->dx;
+    if (g->dy < d) d = g->dy;
+    if (g->dz < d) d = g->dz;
+    return g->mass / (5.0 * g->hbar) * d * d;
+}

@@ -172,8 +172,8 @@ __device__ __forceinline__ void fused_step_body(const FusedArgs<T>& a, int L,
     // into outI and the LDS buffer of plane p; stored if p is in the chunk.
     auto compute_a = [&](int p, const VT(&io)[M], const VT(&vv)[M], VT(&outI)[M], bool store) {
         const int gp = gplane(p);
-        const T cap = gp >= 0 ? a.ca[gp] : T(1);
-        const T cbp = gp >= 0 ? a.cb[gp] : T(1);
+        const T cap = gp >= 0 ? ld_uniform(a.ca, gp) : T(1);
+        const T cbp = gp >= 0 ? ld_uniform(a.cb, gp) : T(1);
         const int buf = (p - k0 + 2) & 1;
 #pragma unroll
         for (int i = 0; i < M; ++i) {
@@ -259,8 +259,8 @@ __device__ __forceinline__ void fused_step_body(const FusedArgs<T>& a, int L,
         }
         // phase B for plane k: R^{n+1}(k) = eq. (8) from I^{n+1/2}(k-1..k+1)
         const int buf = (k - k0 + 2) & 1;
-        const T cak = a.ca[k];
-        const T cbk = a.cb[k];
+        const T cak = ld_uniform(a.ca, k);
+        const T cbk = ld_uniform(a.cb, k);
         const bool at_det = (k == a.k_det), at_up = (k == a.k_up);
 #pragma unroll
         for (int i = 0; i < M; ++i) {

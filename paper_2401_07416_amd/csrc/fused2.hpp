@@ -154,8 +154,8 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
                      const T* src, const VT(&uo)[M], const VT(&v)[M], VT(&out)[M], T* dst) {
         constexpr bool IS_R = decltype(is_r)::value;
         const int gp = gplane(p);
-        const T cap = gp >= 0 ? a.ca[gp] : T(1);
-        const T cbp = gp >= 0 ? a.cb[gp] : T(1);
+        const T cap = gp >= 0 ? ld_uniform(a.ca, gp) : T(1);
+        const T cbp = gp >= 0 ? ld_uniform(a.cb, gp) : T(1);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             const T* row = src + rowb[i] * ex + c0;

@@ -129,6 +129,16 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, const 
     }
 }
 
+// Load of a read-only table entry at a wave-uniform index through the
+// scalar cache (constant address space), so that it never waits behind the
+// vector loads in flight (a vector load of the same entry would, and a
+// prefetch issued before it would be drained by that wait).
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T* p, int i) {
+    using CT = const __attribute__((address_space(4))) T;
+    return reinterpret_cast<CT*>(reinterpret_cast<uintptr_t>(p))[__builtin_amdgcn_readfirstlane(i)];
+}
+
 // Cell arithmetic shared by the two-pass and the one-pass kernels, so both
 // produce the same bits.
 //   L(X) = cx (X(i+1) - 2X + X(i-1)) + cy (...) + cz (...)
@@ -225,8 +235,8 @@ __global__ __launch_bounds__(256) void half_step_kernel(HalfArgs<T> a) {
                 load_row(a.V, jrow[r], k, vv[r]);
             }
         }
-        const T cak = a.ca[k];
-        const T cbk = a.cb[k];
+        const T cak = ld_uniform(a.ca, k);
+        const T cbk = ld_uniform(a.cb, k);
         const bool at_det = (k == a.k_det);
         const bool at_up = (k == a.k_up);
 

@@ -815,6 +815,35 @@ void default_fused_tile(tdse_ctx* h) {
     h->fzc = bzc;
 }
 
+// The two-step sweep pays a six-plane start per z chunk and a four-cell rim
+// per tile, so it is the default only where chunks of >= 32 planes still
+// give a few hundred workgroups; the first fitting (tile width, z chunk) in
+// order of preference is taken.
+void default_two_step(tdse_ctx* h) {
+    const tdse_desc& d = h->d;
+    const bool f64 = d.precision == TDSE_F64;
+    const int tx32[4] = {64, 56, 32, 24}, tx64[3] = {32, 24, 16};
+    const int* txl = f64 ? tx64 : tx32;
+    const int ntx = f64 ? 3 : 4;
+    h->two = false;
+    h->t2m = 2;
+    h->t2pf = true;
+    h->t2x = txl[0];
+    h->t2zc = (int)std::min<int64_t>(64, d.nz);
+    for (int zc0 : {64, 128, 32}) {
+        if (zc0 > d.nz) continue;
+        for (int i = 0; i < ntx; ++i) {
+            const Fused2Dims f = fused2_dims(h, txl[i], 2, zc0);
+            if (f.ok && f.nwg >= 384) {
+                h->two = true;
+                h->t2x = txl[i];
+                h->t2zc = zc0;
+                return;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1057,7 +1086,7 @@ tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out) {
         h->lds_max = lds;
     default_tile(h);
     default_fused_tile(h);
-    h->t2zc = (int)std::min<int64_t>(h->t2zc, d->nz);
+    default_two_step(h);
     h->wcap.assign((size_t)d->nz, 0.0);
     *out = h;
     return TDSE_OK;
@@ -1314,6 +1343,29 @@ tdse_status tdse_set_cap_quadratic(tdse_handle h, int64_t n_bottom, int64_t n_to
         w[(size_t)k] += w_max * t * t;
     }
     return tdse_set_cap(h, w.data(), nz);
+}
+
+tdse_status tdse_set_cap_paper(tdse_handle h, double alpha, double r_cut) {
+    if (!h) return TDSE_ERR_ARG;
+    if (!(alpha >= 0) || !std::isfinite(alpha) || !(r_cut >= 0) || !std::isfinite(r_cut))
+        return fail(h, TDSE_ERR_ARG, "bad CAP parameters");
+    const int64_t nz = h->d.nz;
+    const double dz = h->d.dz;
+    std::vector<double> w((size_t)nz, 0.0);
+    for (int64_t k = 0; k < nz; ++k) {
+        const double u = r_cut - (double)k * dz;
+        if ((double)k * dz < r_cut) w[(size_t)k] = alpha / dz * u * u;
+    }
+    return tdse_set_cap(h, w.data(), nz);
+}
+
+tdse_status tdse_time_step_paper(const tdse_desc* d, double* dt) {
+    tdse_status s = tdse_validate_desc(d);
+    if (s != TDSE_OK) return s;
+    if (!dt) return TDSE_ERR_ARG;
+    const double dmin = std::min(d->dx, std::min(d->dy, d->dz));
+    *dt = d->mass / (5.0 * d->hbar) * dmin * dmin;
+    return TDSE_OK;
 }
 
 tdse_status tdse_finalize_setup(tdse_handle h, double* dt_out, double* e_max_out) {
@@ -1704,7 +1756,7 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
     out->fused_prefetch = h->fpf ? 1 : 0;
     out->graph = h->graph_on ? 1 : 0;
     out->fused_threads = h->ft;
-    out->two_step = h->two ? 1 : 0;
+    out->two_step = (h->two && out->fused) ? 1 : 0;
     out->two_step_tx = h->t2x;
     out->two_step_rows = h->t2m;
     out->two_step_zc = h->t2zc;

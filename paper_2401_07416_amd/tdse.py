@@ -35,7 +35,8 @@ EXPORTS = [
     "tdse_potential_vjp", "tdse_batch_create", "tdse_batch_member", "tdse_batch_set_tile",
     "tdse_batch_prepare", "tdse_batch_run", "tdse_batch_status", "tdse_batch_last_error",
     "tdse_batch_destroy", "tdse_hbm_probe", "tdse_interpolate_potential",
-    "tdse_dissimilarity_workspace_size", "tdse_dissimilarity",
+    "tdse_dissimilarity_workspace_size", "tdse_dissimilarity", "tdse_set_cap_paper",
+    "tdse_time_step_paper",
 ]
 
 
@@ -145,6 +146,8 @@ def load():
         "tdse_set_tile": (i32, [vp, ctypes.POINTER(Tile)]),
         "tdse_hbm_probe": (i32, [i32, ctypes.POINTER(vp), i64, i32, i32, vp, dp]),
         "tdse_interpolate_potential": (i32, [vp, vp, i32, i32, i32, dp, dp]),
+        "tdse_set_cap_paper": (i32, [vp, ctypes.c_double, ctypes.c_double]),
+        "tdse_time_step_paper": (i32, [ctypes.POINTER(Desc), dp]),
         "tdse_dissimilarity_workspace_size": (i32, [i32, i32, ctypes.POINTER(ctypes.c_size_t)]),
         "tdse_dissimilarity": (i32, [i32, vp, i32, i32, i64, vp, ctypes.c_double, vp, vp,
                                      ctypes.c_size_t, vp]),
@@ -314,6 +317,10 @@ class Sim:
         self._check(self.lib.tdse_set_cap(
             self.h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(w)))
 
+    def set_cap_paper(self, alpha: float, r_cut: float):
+        """Eq. (10) as printed: W_k = (alpha / dz) (r_cut - k dz)^2 below r_cut."""
+        self._check(self.lib.tdse_set_cap_paper(self.h, float(alpha), float(r_cut)))
+
     def set_cap_quadratic(self, n_bottom: int, n_top: int, w_max: float):
         self._check(self.lib.tdse_set_cap_quadratic(self.h, int(n_bottom), int(n_top),
                                                     float(w_max)))
@@ -455,6 +462,16 @@ def hbm_probe(kind: str = "copy", gib: float = 1.0, grid: int = 0, reps: int = 5
     return nbytes / (ms.value * 1e-3) / 1e9
 
 
+def time_step_paper(desc) -> float:
+    """Eq. (11): m min(dx, dy, dz)^2 / (5 hbar) for the description's grid."""
+    lib = load()
+    dt = ctypes.c_double()
+    st = lib.tdse_time_step_paper(ctypes.byref(desc), ctypes.byref(dt))
+    if st != OK:
+        raise TdseError(st, lib.tdse_status_string(st).decode())
+    return dt.value
+
+
 def dissimilarity(frames, weights, dA: float):
     """d_kj of eq. (16) on the GPU: frames [K][T][P] (a float32 or float64
     CUDA tensor), time-quadrature weights [T] (with the 1 / (t1 - t0)), pixel
@@ -494,16 +511,29 @@ def sim_from_workload(w, precision: Optional[str] = None, steps: Optional[int] =
     prec = precision or w.precision
     nsteps = w.steps if steps is None else steps
     nrec = w.n_records(nsteps) if max_records is None else max_records
+    flags = FLAG_PIXEL_INTEGRAL if pixel else 0
     d = make_desc(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, dt_frac=w.dt_frac,
                   bc=w.bc, precision=prec, k_det=w.k_det, record_every=w.record_every,
-                  max_records=nrec, flags=FLAG_PIXEL_INTEGRAL if pixel else 0)
+                  max_records=nrec, flags=flags)
+    if w.dt_eq11:
+        # eq. (11) exceeds the Gershgorin bound that finalize enforces
+        d = make_desc(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass,
+                      dt=time_step_paper(d), bc=w.bc, precision=prec, k_det=w.k_det,
+                      record_every=w.record_every, max_records=nrec,
+                      flags=flags | FLAG_ALLOW_UNSTABLE)
     s = Sim(d, device=device, pingpong=pingpong, stream=stream)
     if stream is not None:
         import torch
         torch.cuda.synchronize()
+    if w.cell_table is not None:
+        from .workloads import cell_table_of
+        table, spacing, origin = cell_table_of(w)
+        s.interpolate_potential(table, spacing, origin)
     if w.atoms is not None and len(w.atoms):
         s.build_potential(w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
                           screened=w.screened)
+    if w.cap_paper is not None:
+        s.set_cap_paper(*w.cap_paper)
     if w.cap is not None:
         s.set_cap_quadratic(*w.cap)
     s.finalize()

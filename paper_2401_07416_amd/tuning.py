@@ -33,23 +33,30 @@ def tile_for(w, precision: str) -> Optional[dict]:
 
 
 def candidates(nz: int):
-    """Two-pass tiles then one-pass tiles, as set_tile keyword dicts."""
+    """Two-pass tiles, one-pass tiles, then two-step sweep tiles, as set_tile
+    keyword dicts."""
     for rows in (1, 2, 4):
         for waves in (1, 2, 4):
             for zc in (8, 16, 32, 64, 128, 256):
                 if zc <= nz:
-                    yield dict(fused=0, rows=rows, waves=waves, zc=zc)
+                    yield dict(fused=0, two_step=0, rows=rows, waves=waves, zc=zc)
     for ft in (256, 128, 64):
         for fr in (2, 3, 4):
             for zc in (8, 16, 32, 64, 128):
                 if zc <= nz:
-                    yield dict(fused=1, fused_rows=fr, fused_zc=zc, fused_prefetch=0,
+                    yield dict(fused=1, two_step=0, fused_rows=fr, fused_zc=zc, fused_prefetch=0,
                                fused_threads=ft)
     for fr in (2, 3):
         for zc in (16, 64):
             if zc <= nz:
-                yield dict(fused=1, fused_rows=fr, fused_zc=zc, fused_prefetch=1,
+                yield dict(fused=1, two_step=0, fused_rows=fr, fused_zc=zc, fused_prefetch=1,
                            fused_threads=256)
+    for tx in (16, 24, 32, 40, 56, 64):
+        for zc in (32, 64, 128):
+            if zc <= nz:
+                for pf in (1, 0):
+                    yield dict(fused=1, two_step=1, two_step_tx=tx, two_step_rows=2,
+                               two_step_zc=zc, two_step_prefetch=pf)
 
 
 def autotune(sim, steps: int = 20, reps: int = 3, cands=None):

@@ -56,6 +56,11 @@ class Workload:
     kappa: float = 14.3996454784
     a0: float = 0.529177210903
     notes: str = ""
+    # potential from a unit-cell table instead of atoms: keyword arguments of
+    # unit_cell_table plus "spacing" and "origin" of its samples
+    cell_table: Optional[dict] = None
+    cap_paper: Optional[Tuple[float, float]] = None  # eq. (10) as printed: (alpha, r_cut)
+    dt_eq11: bool = False                # eq. (11) time step instead of dt_frac
 
     @property
     def cells(self) -> int:
@@ -258,16 +263,16 @@ def ragged(precision: str = "f64", seed: int = 11) -> Workload:
 
 
 def unit_cell_table(seed: int = 7, ux: int = 24, uy: int = 28, uz: int = 360,
-                    cell=(2.556, 4.427), z_top: float = 28.35, wells: int = 6):
+                    cell=(2.556, 4.427), z_top: float = 28.35, wells: int = 6, zs: float = 0.2):
     """Synthetic stand-in for a DFT potential of one surface unit cell (the
     paper's tables are DFT output, not available here): a table [uz][uy][ux]
-    in eV on a cell of cell[0] x cell[1] A and uz planes 0.2 A apart, with
+    in eV on a cell of cell[0] x cell[1] A and uz planes zs A apart, with
     a few deep periodic wells per layer below z_top and a smooth decay into
     the vacuum above it.  Seeded; no part of the method."""
     rng = np.random.default_rng(seed)
     x = np.arange(ux) * cell[0] / ux
     y = np.arange(uy) * cell[1] / uy
-    z = np.arange(uz) * 0.2
+    z = np.arange(uz) * zs
     X, Y = np.meshgrid(x, y)
     t = np.zeros((uz, uy, ux))
     for layer in range(4):
@@ -283,6 +288,49 @@ def unit_cell_table(seed: int = 7, ux: int = 24, uy: int = 28, uz: int = 360,
     return t
 
 
+def cell_table_of(w: Workload):
+    """(table, spacing, origin) of a workload whose potential comes from a
+    unit-cell table."""
+    kw = dict(w.cell_table)
+    spacing, origin = kw.pop("spacing"), kw.pop("origin", (0.0, 0.0, 0.0))
+    return unit_cell_table(**kw), spacing, origin
+
+
+def paper_cu111(reduced: bool = False, seed: int = 7) -> Workload:
+    """The paper's own set-up of section 2.1 / 2.3 (first set of runs): a
+    40.9 x 40.9 x 70 A domain on a 240 x 240 x 420 grid, the surface
+    potential of one cell repeated 15 x 15 and interpolated onto the mesh,
+    100 planes appended at the bottom for the one-sided CAP of eq. (10),
+    the eq. (11) time step, a 60 eV packet with sigma = 1.8 A at z = 42 A,
+    the detector at 37.6 A, records every 20 steps, 8000 steps.  The DFT
+    cell potential is replaced by the synthetic unit_cell_table; all z
+    positions shift up by the appended 100 dz.  reduced: a 48 x 48 x (84 +
+    20) grid over an 8.18 x 8.18 x 14 A domain (3 x 3 cells), 300 steps."""
+    L, Lz = 40.9, 70.0
+    n, nz, napp, cells = 240, 420, 100, 15
+    if reduced:
+        L, Lz, n, nz, napp, cells = 40.9 / 5, 14.0, 48, 84, 20, 3
+    dx, dz = L / n, Lz / nz
+    off = napp * dz
+    cell = L / cells
+    z_top = 28.35 if not reduced else 6.0
+    uz = nz + napp
+    table = dict(seed=seed, ux=24, uy=24, uz=uz, cell=(cell, cell), z_top=z_top + off, wells=4,
+                 spacing=(cell / 24, cell / 24, dz), origin=(0.0, 0.0, 0.0))
+    # the table's z planes sit at c * 0.2 in unit_cell_table; use the mesh spacing
+    table["zs"] = dz
+    z0 = (42.0 if not reduced else 10.5) + off
+    zdet = (37.6 if not reduced else 9.0) + off
+    alpha_rcut = 50.0 * dz / (napp * dz) ** 2  # W at the bottom plane = 50 eV
+    return Workload(name=("paper-cu111-reduced-48x48x104" if reduced else "paper-cu111-240x240x520"),
+                    nx=n, ny=n, nz=nz + napp, dx=dx, dy=dx, dz=dz, hbar=HBAR_EV_FS,
+                    mass=ME_EV_FS2_A2, atoms=None, r0=(L / 2, L / 2, z0),
+                    sigma=1.8 if not reduced else 1.2, energy=60.0, steps=8000 if not reduced else 300,
+                    k_det=int(round(zdet / dz)), record_every=20, cell_table=table,
+                    cap_paper=(alpha_rcut, napp * dz), dt_eq11=True,
+                    notes="synthetic cell potential stands in for the DFT one")
+
+
 def random_state(shape, seed: int):
     """Seeded smooth-ish random initial arrays (for pins that need generic data)."""
     rng = np.random.default_rng(seed)
@@ -296,4 +344,5 @@ ALL = {
     "headline": c3_headline,
     "ragged": ragged,
     "adjoint": c5_adjoint,
+    "paper-cu111": paper_cu111,
 }

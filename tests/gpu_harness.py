@@ -6,7 +6,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
-from paper_2401_07416_amd import tdse
+from paper_2401_07416_amd import tdse, workloads
 
 
 def oracle_grid(w):
@@ -23,13 +23,21 @@ def oracle_setup(w, V=None):
     g = oracle_grid(w)
     if V is not None:
         pass
+    elif w.cell_table is not None:
+        table, spacing, origin = workloads.cell_table_of(w)
+        V = oracle.interp_potential(g, table, spacing, origin)
     elif w.atoms is not None and len(w.atoms):
         V = oracle.potential(g, w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
                              screened=w.screened)
     else:
         V = np.zeros(g.shape)
-    dt = w.dt_frac * g.hbar / oracle.emax(g, V)
-    W = oracle.cap_quadratic(w.nz, *w.cap) if w.cap is not None else None
+    dt = oracle.dt_paper(g) if w.dt_eq11 else w.dt_frac * g.hbar / oracle.emax(g, V)
+    W = None
+    if w.cap_paper is not None:
+        W = oracle.cap_paper(w.nz, w.dz, *w.cap_paper)
+    if w.cap is not None:
+        Wq = oracle.cap_quadratic(w.nz, *w.cap)
+        W = Wq if W is None else W + Wq
     k0 = wave_vector(w, oracle.wavevector)
     R, I = oracle.init_gaussian(g, w.r0, k0, w.sigma, dt)
     return g, V, W, dt, R, I

@@ -161,3 +161,22 @@ def test_dissimilarity_rejects_bad_arguments():
         tdse.dissimilarity(f, torch.ones(2, dtype=torch.float64), 0.0)
     with pytest.raises(ValueError):
         tdse.dissimilarity(f, torch.ones(3, dtype=torch.float64), 1.0)
+
+
+# ---- the paper's own set-up (eqs. (10), (11), interpolated cell potential) ---
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_paper_literal_setup_matches_oracle(prec):
+    """Interpolated cell potential, 20 appended planes with the one-sided
+    eq. (10) CAP, the eq. (11) time step (beyond the Gershgorin bound, inside
+    the exact leapfrog limit), records every 20 steps: 300 steps against the
+    oracle's own set-up of the same description."""
+    w = workloads.paper_cu111(reduced=True)
+    say("paper-literal reduced", prec)
+    ref = H.oracle_run(w, w.steps)
+    for tile in (None, dict(fused=1, two_step=1, two_step_tx=8, two_step_rows=2, two_step_zc=32)):
+        gpu = H.gpu_run(w, w.steps, precision=prec, tile=tile)
+        assert gpu.dt == pytest.approx(oracle.dt_paper(H.oracle_grid(w)), rel=1e-15)
+        tol = (dict(tol_state=1e-11, tol_rec=1e-11, tol_scal=1e-12, tol_flux=1e-12) if prec == "f64"
+               else dict(tol_state=1e-4, tol_rec=1e-3, tol_scal=1e-4, tol_flux=1e-5))
+        say(" tile", tile, H.compare(gpu, ref, **tol))

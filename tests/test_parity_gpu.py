@@ -90,14 +90,20 @@ def test_degenerate_extents(shape, kdet, pp):
         say(H.compare(gpu, ref, **FP64))
 
 
-TILES = [dict(fused=0, rows=1, waves=1, zc=4), dict(fused=0, rows=2, waves=4, zc=16),
-         dict(fused=0, rows=4, waves=2, zc=7), dict(fused=0, rows=8, waves=1, zc=128),
-         dict(fused=0, rows=2, waves=3, zc=33), dict(fused=1, fused_rows=2, fused_zc=8),
-         dict(fused=1, fused_rows=3, fused_zc=33), dict(fused=1, fused_rows=4, fused_zc=128),
-         dict(fused=1, fused_rows=2, fused_zc=5),
-         dict(fused=1, fused_rows=3, fused_zc=16, fused_threads=64),
-         dict(fused=1, fused_rows=2, fused_zc=7, fused_threads=128),
-         dict(fused=1, fused_rows=4, fused_zc=32, fused_threads=64, fused_prefetch=1)]
+TILES = [dict(fused=0, two_step=0, rows=1, waves=1, zc=4),
+         dict(fused=0, two_step=0, rows=2, waves=4, zc=16),
+         dict(fused=0, two_step=0, rows=4, waves=2, zc=7),
+         dict(fused=0, two_step=0, rows=8, waves=1, zc=128),
+         dict(fused=0, two_step=0, rows=2, waves=3, zc=33),
+         dict(fused=1, two_step=0, fused_rows=2, fused_zc=8),
+         dict(fused=1, two_step=0, fused_rows=3, fused_zc=33),
+         dict(fused=1, two_step=0, fused_rows=4, fused_zc=128),
+         dict(fused=1, two_step=0, fused_rows=2, fused_zc=5),
+         dict(fused=1, two_step=0, fused_rows=3, fused_zc=16, fused_threads=64),
+         dict(fused=1, two_step=0, fused_rows=2, fused_zc=7, fused_threads=128),
+         dict(fused=1, two_step=0, fused_rows=4, fused_zc=32, fused_threads=64, fused_prefetch=1),
+         dict(fused=1, two_step=1, two_step_tx=56, two_step_rows=2, two_step_zc=64,
+              two_step_prefetch=1)]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -143,6 +149,7 @@ def test_graph_replay_matches_plain_launches():
     plain = H.gpu_run(w, 200, precision="f32")
     st = torch.cuda.Stream()
     g = tdse.sim_from_workload(w, precision="f32", steps=200, stream=st)
+    g.set_tile(two_step=0)   # graphs replay one-pass steps
     assert g.get_tile().graph == 1
     for n in (7, 150, 43):
         g.step(n)

@@ -55,7 +55,8 @@ def parse():
     return p.parse_args()
 
 
-KERNEL_SOURCES = ("kernels.hpp", "dispatch.hpp", "fused.hpp", "fused_f32.hip", "fused_f64.hip",
+KERNEL_SOURCES = ("kernels.hpp", "dispatch.hpp", "fused.hpp", "fused_f32.hip", "fused_f64.hip", "fused2.hpp",
+                  "fused2_f32.hip", "fused2_f64.hip",
                   "half_f32_w4.hip", "half_f32_w2.hip", "half_f32_w1.hip", "half_f64_w2.hip",
                   "half_f64_w1.hip")
 

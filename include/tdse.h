@@ -358,6 +358,16 @@ tdse_status tdse_batch_create(const tdse_desc* descs, int32_t n, void* stream, t
 tdse_status tdse_batch_member(tdse_batch b, int32_t i, tdse_handle* h);
 tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc,
                                 int32_t prefetch, int32_t threads);
+/* Two-step sweeps for the whole batch (on by default): when every member
+ * fits the sweep's tile (interior width tx, two rows per thread, z chunk
+ * zc, prefetch as for tdse_tile) and the members share the vector width,
+ * tdse_batch_prepare captures intervals of S/2 two-step launches instead of
+ * S one-pass launches; otherwise it falls back to the one-pass form.  When
+ * S/2 is odd a second graph covers intervals that start from the second
+ * state pair, and a run that ends there copies the members' state back
+ * into their bound arrays. */
+tdse_status tdse_batch_set_two_step(tdse_batch b, int32_t enable, int32_t tx, int32_t zc,
+                                    int32_t prefetch);
 tdse_status tdse_batch_prepare(tdse_batch b);
 tdse_status tdse_batch_run(tdse_batch b, int64_t n);
 tdse_status tdse_batch_status(tdse_batch b, int32_t* per_config);

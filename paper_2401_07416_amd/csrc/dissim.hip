@@ -25,7 +25,12 @@ namespace {
 
 constexpr int BK = 64;   // trajectories per block side
 constexpr int PC = 32;   // pixels per LDS chunk
-constexpr int PAD = 1;   // LDS row padding against bank conflicts
+constexpr int LS = BK + 4;  // LDS row stride (pixel-major rows of BK values)
+
+template <typename T>
+struct alignas(4 * sizeof(T)) vec_of {
+    T v[4];
+};
 
 struct DissimArgs {
     const void* frames;   // [K][T][P]
@@ -50,10 +55,13 @@ __device__ __forceinline__ void pair_block(int q, int nb, int* bi, int* bj) {
     *bj = r + q;
 }
 
+// LDS tiles are pixel-major ([PC][BK], stride LS) so that each thread reads
+// its 4 consecutive trajectories of a pixel with one vector read.
 template <typename T>
 __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
-    __shared__ T As[BK][PC + PAD];
-    __shared__ T Bs[BK][PC + PAD];
+    __shared__ __align__(16) T As[PC * LS];
+    __shared__ __align__(16) T Bs[PC * LS];
+    using V4 = vec_of<T>;
     const T* F = static_cast<const T*>(a.frames);
     const int q = blockIdx.x % a.npb;
     const int tc = blockIdx.x / a.npb;
@@ -61,7 +69,7 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
     pair_block(q, a.nb, &bi, &bj);
     const int r0 = bi * BK, c0 = bj * BK;
     const int tid = threadIdx.x;
-    const int tr = tid >> 4, tcl = tid & 15;
+    const int tr = tid >> 4, tcl = tid & 15;   // rows 4 tr .. 4 tr + 3, columns 4 tcl .. 4 tcl + 3
     const int t0 = tc * a.tpc;
     const int t1 = min(t0 + a.tpc, a.T);
     double acc[4][4];
@@ -77,13 +85,13 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
 #pragma unroll
             for (int y = 0; y < 4; ++y) s64[x][y] = 0.0;
         for (long p0 = 0; p0 < a.P; p0 += PC) {
-            // load the two 64 x 32 tiles: 2048 values each, 8 per thread
+            // 64 trajectories x 32 pixels per tile, 8 values per thread
             for (int e = tid; e < BK * PC; e += 256) {
                 const int row = e / PC, col = e - row * PC;
                 const long p = p0 + col;
                 const int ka = r0 + row, kb = c0 + row;
-                As[row][col] = (ka < a.K && p < a.P) ? F[((long)ka * a.T + t) * a.P + p] : T(0);
-                Bs[row][col] = (kb < a.K && p < a.P) ? F[((long)kb * a.T + t) * a.P + p] : T(0);
+                As[col * LS + row] = (ka < a.K && p < a.P) ? F[((long)ka * a.T + t) * a.P + p] : T(0);
+                Bs[col * LS + row] = (kb < a.K && p < a.P) ? F[((long)kb * a.T + t) * a.P + p] : T(0);
             }
             __syncthreads();
             T s[4][4];
@@ -91,18 +99,15 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
             for (int x = 0; x < 4; ++x)
 #pragma unroll
                 for (int y = 0; y < 4; ++y) s[x][y] = T(0);
-#pragma unroll 4
+#pragma unroll 8
             for (int p = 0; p < PC; ++p) {
-                T av[4], bv[4];
-#pragma unroll
-                for (int x = 0; x < 4; ++x) av[x] = As[tr + 16 * x][p];
-#pragma unroll
-                for (int y = 0; y < 4; ++y) bv[y] = Bs[tcl + 16 * y][p];
+                const V4 av = *reinterpret_cast<const V4*>(As + p * LS + 4 * tr);
+                const V4 bv = *reinterpret_cast<const V4*>(Bs + p * LS + 4 * tcl);
 #pragma unroll
                 for (int x = 0; x < 4; ++x)
 #pragma unroll
                     for (int y = 0; y < 4; ++y) {
-                        const T e = av[x] - bv[y];
+                        const T e = av.v[x] - bv.v[y];
                         s[x][y] += e * e;
                     }
             }
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
     for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
-            const int k = r0 + tr + 16 * x, j = c0 + tcl + 16 * y;
+            const int k = r0 + 4 * tr + x, j = c0 + 4 * tcl + y;
             if (k < a.K && j < a.K) {
                 out[(long)k * a.K + j] = acc[x][y];
                 out[(long)j * a.K + k] = acc[x][y];

@@ -372,4 +372,43 @@ __global__ __launch_bounds__(256) void fused2_kernel(Fused2Args<T> a) {
     fused2_body<T, W, M, REC, PF>(a, xcd_remap(blockIdx.x, a.nwg), smem_raw);
 }
 
+// Two steps of many grids in one launch (the batch form of the sweep).
+// cfg[c] describes grid c from its state pair 0 into pair 1 (parity 0) or
+// back (parity 1), with flux_a at its ring's slot 0; the launch takes ring
+// slots flux_slot and flux_slot + 1.  Workgroups wg_start[c] ..
+// wg_start[c+1]-1 of the launch (after an XCD remap over the whole launch)
+// belong to grid c.  The record slot comes from the device counter so a
+// captured graph can be replayed.
+template <typename T>
+struct Batch2Step {
+    const Fused2Args<T>* cfg;
+    const int* wg_start;
+    const long* rec_idx;
+    int n, total_wg, parity, flux_slot;
+};
+
+template <typename T, int W, int M, bool REC, bool PF>
+__global__ __launch_bounds__(256) void fused2_batch_kernel(Batch2Step<T> b) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int Lg = xcd_remap(blockIdx.x, b.total_wg);
+    int lo = 0, hi = b.n;  // wg_start[lo] <= Lg < wg_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (b.wg_start[mid] <= Lg) lo = mid; else hi = mid;
+    }
+    Fused2Args<T> a = b.cfg[lo];
+    if (b.parity) {
+        const T* r0 = a.R0;
+        const T* i0 = a.I0;
+        a.R0 = a.R1;
+        a.I0 = a.I1;
+        a.R1 = const_cast<T*>(r0);
+        a.I1 = const_cast<T*>(i0);
+    }
+    a.flux_a += (long)b.flux_slot * 2 * a.ntiles;
+    a.flux_b = a.flux_a + 2 * a.ntiles;
+    if (REC) a.rec_plane += (*b.rec_idx) * (long)a.nx * a.ny;
+    fused2_body<T, W, M, REC, PF>(a, Lg - b.wg_start[lo], smem_raw);
+}
+
 }  // namespace tdse

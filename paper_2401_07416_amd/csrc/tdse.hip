@@ -99,14 +99,22 @@ struct tdse_batch_ctx {
     int S = 0;           // steps per graph replay
     int W = 0, M = 3, zc = 64, nt = 256;
     bool pf = false;
+    // two-step sweep for the whole batch (when every member fits it)
+    bool two = true;
+    int t2x = 64, t2zc = 64;
+    bool t2pf = true;
+    bool use2 = false;  // chosen at prepare
+    int par = 0;        // state pair holding the members' current level
     size_t lds = 0;
     int total_wg = 0;
-    void* d_cfg = nullptr;     // FusedArgs<T>[n]
+    void* d_cfg = nullptr;     // FusedArgs<T>[n] or Fused2Args<T>[n]
     int* d_wg = nullptr;       // [n + 1]
     long* d_rec = nullptr;     // record counter
     void* d_fin = nullptr;     // FinArgs[n]
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph1 = nullptr;     // the interval starting from pair 1 (two-step, odd S/2)
+    hipGraphExec_t exec1 = nullptr;
     bool prepared = false;
     bool owns = true;    // members are destroyed with the batch
     int64_t step = 0;
@@ -254,6 +262,12 @@ hipError_t launch_fused2_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t 
                              const Fused2Args<float>& a, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_fused2_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
                              const Fused2Args<double>& a, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_fused2_batch_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+                                   const Batch2Step<float>& b);
+hipError_t launch_fused2_batch_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+                                   const Batch2Step<double>& b);
+hipError_t fused2_batch_allow_lds_f32(int w, int m, size_t lds);
+hipError_t fused2_batch_allow_lds_f64(int w, int m, size_t lds);
 }  // namespace tdse
 
 namespace {
@@ -862,6 +876,10 @@ static tdse_status bfail(tdse_batch_ctx* b, tdse_status s, const std::string& m)
 static void batch_free_device(tdse_batch_ctx* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->exec1) (void)hipGraphExecDestroy(b->exec1);
+    if (b->graph1) (void)hipGraphDestroy(b->graph1);
+    b->exec1 = nullptr;
+    b->graph1 = nullptr;
     if (b->d_cfg) (void)hipFree(b->d_cfg);
     if (b->d_wg) (void)hipFree(b->d_wg);
     if (b->d_rec) (void)hipFree(b->d_rec);
@@ -907,6 +925,132 @@ static hipError_t batch_enqueue_interval(tdse_batch_ctx* b) {
         e = hipGetLastError();
     }
     return e;
+}
+
+// One record interval of two-step sweeps: S / 2 launches (the last one
+// writes the record), the per-member finalisation and the counter bump.
+// par0 = the state pair the interval starts from.
+template <typename T>
+static hipError_t batch_enqueue_interval2(tdse_batch_ctx* b, int par0) {
+    const size_t n = b->members.size();
+    const int launches = b->S / 2;
+    for (int j = 0; j < launches; ++j) {
+        Batch2Step<T> st;
+        st.cfg = static_cast<const Fused2Args<T>*>(b->d_cfg);
+        st.wg_start = b->d_wg;
+        st.rec_idx = b->d_rec;
+        st.n = (int)n;
+        st.total_wg = b->total_wg;
+        st.parity = (par0 + j) & 1;
+        st.flux_slot = 2 * j;
+        const bool rec = b->h > 0 && j == launches - 1;
+        hipError_t e;
+        if constexpr (sizeof(T) == 8)
+            e = launch_fused2_batch_f64(b->W, 2, rec, b->t2pf, dim3(b->total_wg), b->lds, b->stream, st);
+        else
+            e = launch_fused2_batch_f32(b->W, 2, rec, b->t2pf, dim3(b->total_wg), b->lds, b->stream, st);
+        if (e != hipSuccess) return e;
+    }
+    BatchFin f;
+    f.cfg = static_cast<const FinArgs*>(b->d_fin);
+    f.rec_idx = b->d_rec;
+    f.n_pending = b->S;
+    f.record = b->h > 0 ? 1 : 0;
+    hipLaunchKernelGGL(finalize_batch_kernel, dim3((unsigned)n), dim3(256), 0, b->stream, f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (b->h > 0) {
+        hipLaunchKernelGGL(bump_counter_kernel, dim3(1), dim3(64), 0, b->stream, b->d_rec);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// Tables and graphs of the two-step form; false (nothing allocated) if a
+// member does not fit the sweep's tile.
+template <typename T>
+static tdse_status batch_prepare2_t(tdse_batch_ctx* b, bool* used) {
+    *used = false;
+    const size_t n = b->members.size();
+    std::vector<Fused2Args<T>> cfg(n);
+    std::vector<FinArgs> fin(n);
+    std::vector<int> wg(n + 1, 0);
+    size_t lds = 0;
+    int W = 0;
+    for (size_t i = 0; i < n; ++i) {
+        tdse_ctx* h = b->members[i];
+        const int zc = (int)std::min<int64_t>(b->t2zc, h->d.nz);
+        const Fused2Dims f = fused2_dims(h, b->t2x, 2, zc);
+        if (!f.ok) return TDSE_OK;
+        if (W == 0) W = f.W;
+        if (f.W != W) return TDSE_OK;
+        h->t2x = b->t2x;
+        h->t2m = 2;
+        h->t2zc = zc;
+        h->t2pf = b->t2pf;
+        cfg[i] = make_fused2_args<T>(h, f, b->h > 0, 0, 0);
+        cfg[i].rec_plane = static_cast<T*>(h->rec);  // record 0; the kernel adds the counter
+        lds = std::max(lds, f.lds);
+        wg[i + 1] = wg[i] + f.nwg;
+        const tdse_desc& d = h->d;
+        FinArgs& a = fin[i];
+        a.flux_ring = h->flux_ring;
+        a.n_pending = 0;
+        a.ytiles = f.ntiles;
+        a.has_up = !(d.bc[2] == TDSE_BC_ZERO && d.k_det + 1 >= d.nz);
+        a.record = 0;
+        a.rec_idx = 0;
+        a.dV = d.dx * d.dy * d.dz;
+        a.dv_cz = a.dV * h->c[2];
+        a.acc = h->acc;
+        a.part_q = h->part_q;
+        a.part_naive = h->part_naive;
+        a.n_part = (long)f.nzc * f.ntiles;
+        a.part_plane = h->part_plane;
+        a.scalars = h->scal;
+    }
+    if ((long)wg[n] >= (1L << 31)) return TDSE_OK;
+    b->W = W;
+    b->lds = lds;
+    b->total_wg = wg[n];
+    hipError_t e = sizeof(T) == 8 ? fused2_batch_allow_lds_f64(W, 2, lds) : fused2_batch_allow_lds_f32(W, 2, lds);
+    if (e != hipSuccess) return bfail(b, TDSE_ERR_DEVICE, std::string("batch LDS: ") + hipGetErrorString(e));
+    if (hipMalloc(&b->d_cfg, n * sizeof(Fused2Args<T>)) != hipSuccess ||
+        hipMalloc(&b->d_fin, n * sizeof(FinArgs)) != hipSuccess ||
+        hipMalloc(&b->d_wg, (n + 1) * sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->d_rec, sizeof(long)) != hipSuccess) {
+        batch_free_device(b);
+        return bfail(b, TDSE_ERR_OOM, "batch tables");
+    }
+    e = hipMemcpyAsync(b->d_cfg, cfg.data(), n * sizeof(Fused2Args<T>), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_fin, fin.data(), n * sizeof(FinArgs), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_wg, wg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        batch_free_device(b);
+        return bfail(b, TDSE_ERR_DEVICE, std::string("batch tables: ") + hipGetErrorString(e));
+    }
+    // one interval from pair 0 and, when an interval swaps the pairs an odd
+    // number of times, one from pair 1
+    const int ngraphs = ((b->S / 2) % 2) ? 2 : 1;
+    for (int g = 0; g < ngraphs && e == hipSuccess; ++g) {
+        hipGraph_t* gr = g ? &b->graph1 : &b->graph;
+        hipGraphExec_t* ex = g ? &b->exec1 : &b->exec;
+        e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = batch_enqueue_interval2<T>(b, g);
+            e = hipStreamEndCapture(b->stream, gr);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(ex, *gr, nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess) {
+        batch_free_device(b);
+        return bfail(b, TDSE_ERR_DEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+    }
+    b->prepared = true;
+    *used = true;
+    return TDSE_OK;
 }
 
 template <typename T>
@@ -1654,6 +1798,7 @@ tdse_status tdse_step(tdse_handle h, int64_t n) {
             if (!b) return fail(h, TDSE_ERR_OOM, "graph context");
             b->members.push_back(h);
             b->owns = false;
+            b->two = false;
             b->stream = h->stream;
             b->precision = d.precision;
             b->h = hrec;
@@ -1992,6 +2137,18 @@ tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_
     return TDSE_OK;
 }
 
+tdse_status tdse_batch_set_two_step(tdse_batch b, int32_t enable, int32_t tx, int32_t zc,
+                                    int32_t prefetch) {
+    if (!b) return TDSE_ERR_ARG;
+    if (tx < 8 || zc < 1) return bfail(b, TDSE_ERR_ARG, "two-step tile");
+    batch_free_device(b);
+    b->two = enable != 0;
+    b->t2x = tx;
+    b->t2zc = zc;
+    b->t2pf = prefetch != 0;
+    return TDSE_OK;
+}
+
 tdse_status tdse_batch_prepare(tdse_batch b) {
     if (!b) return TDSE_ERR_ARG;
     batch_free_device(b);
@@ -2004,6 +2161,18 @@ tdse_status tdse_batch_prepare(tdse_batch b) {
     }
     if (b->h > 0 && step % b->h) return bfail(b, TDSE_ERR_STATE, "members must sit on a record level");
     b->step = step;
+    b->par = 0;
+    b->use2 = false;
+    if (b->two) {
+        bool used = false;
+        tdse_status s = b->precision == TDSE_F64 ? batch_prepare2_t<double>(b, &used)
+                                                 : batch_prepare2_t<float>(b, &used);
+        if (s != TDSE_OK) return s;
+        if (used) {
+            b->use2 = true;
+            return TDSE_OK;
+        }
+    }
     return b->precision == TDSE_F64 ? batch_prepare_t<double>(b) : batch_prepare_t<float>(b);
 }
 
@@ -2020,7 +2189,20 @@ tdse_status tdse_batch_run(tdse_batch b, int64_t n) {
     const long next = b->h > 0 ? (long)(b->step / b->h + 1) : 0;
     hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, b->stream, b->d_rec, next);
     hipError_t e = hipGetLastError();
-    for (int64_t r = 0; r < n / b->S && e == hipSuccess; ++r) e = hipGraphLaunch(b->exec, b->stream);
+    const bool flips = b->use2 && (b->S / 2) % 2 == 1;
+    for (int64_t r = 0; r < n / b->S && e == hipSuccess; ++r) {
+        e = hipGraphLaunch(b->par ? b->exec1 : b->exec, b->stream);
+        if (flips) b->par ^= 1;
+    }
+    // an odd number of swaps left the levels in the second pair: copy them
+    // back so that the members' bound arrays hold the state
+    for (size_t i = 0; i < b->members.size() && e == hipSuccess && b->par; ++i) {
+        tdse_ctx* h = b->members[i];
+        const size_t bytes = (size_t)h->d.nx * h->d.ny * h->d.nz * elem_size(h->d);
+        e = hipMemcpyAsync(h->R, h->R2, bytes, hipMemcpyDeviceToDevice, b->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->I, h->I2, bytes, hipMemcpyDeviceToDevice, b->stream);
+    }
+    if (e == hipSuccess) b->par = 0;
     if (e != hipSuccess) return bfail(b, TDSE_ERR_DEVICE, std::string("batch run: ") + hipGetErrorString(e));
     b->step += n;
     for (tdse_ctx* h : b->members) h->step += n;

@@ -36,7 +36,7 @@ EXPORTS = [
     "tdse_batch_prepare", "tdse_batch_run", "tdse_batch_status", "tdse_batch_last_error",
     "tdse_batch_destroy", "tdse_hbm_probe", "tdse_interpolate_potential",
     "tdse_dissimilarity_workspace_size", "tdse_dissimilarity", "tdse_set_cap_paper",
-    "tdse_time_step_paper",
+    "tdse_time_step_paper", "tdse_batch_set_two_step",
 ]
 
 
@@ -137,6 +137,7 @@ def load():
         "tdse_batch_create": (i32, [ctypes.POINTER(Desc), i32, vp, ctypes.POINTER(vp)]),
         "tdse_batch_member": (i32, [vp, i32, ctypes.POINTER(vp)]),
         "tdse_batch_set_tile": (i32, [vp, i32, i32, i32, i32]),
+        "tdse_batch_set_two_step": (i32, [vp, i32, i32, i32, i32]),
         "tdse_batch_prepare": (i32, [vp]),
         "tdse_batch_run": (i32, [vp, i64]),
         "tdse_batch_status": (i32, [vp, ctypes.POINTER(i32)]),
@@ -579,6 +580,11 @@ class Batch:
     def set_tile(self, fused_rows=3, fused_zc=64, prefetch=False, threads=256):
         self._check(self.lib.tdse_batch_set_tile(self.b, int(fused_rows), int(fused_zc),
                                                  int(bool(prefetch)), int(threads)))
+
+    def set_two_step(self, enable=True, tx=64, zc=64, prefetch=True):
+        """Two-step sweeps for the whole batch where every member fits them."""
+        self._check(self.lib.tdse_batch_set_two_step(self.b, int(bool(enable)), int(tx), int(zc),
+                                                     int(bool(prefetch))))
 
     def prepare(self):
         self.torch.cuda.synchronize(self.device)

@@ -35,14 +35,18 @@ def small_set(steps):
     return out
 
 
-@pytest.mark.parametrize("threads", [256, 64])
+@pytest.mark.parametrize("form", ["two-step", "one-pass-256", "one-pass-64"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_batch_equals_single_runs(prec, threads):
+def test_batch_equals_single_runs(prec, form):
     steps = 60
     ws = small_set(steps)
-    say("batch of", [w.name for w in ws], prec, "threads", threads)
+    say("batch of", [w.name for w in ws], prec, form)
     b = tdse.batch_from_workloads(ws, precision=prec, steps=steps)
-    b.set_tile(fused_rows=3, fused_zc=16, prefetch=True, threads=threads)
+    if form == "two-step":
+        b.set_two_step(True, tx=24, zc=32, prefetch=True)
+    else:
+        b.set_two_step(False)
+        b.set_tile(fused_rows=3, fused_zc=16, prefetch=True, threads=int(form.split("-")[-1]))
     b.prepare()
     b.run(steps)
     assert all(s == tdse.OK for s in b.status())
@@ -98,3 +102,24 @@ def test_batch_rejects_misuse():
     with pytest.raises(tdse.TdseError) as e:
         b.run(40)  # past the record buffers
     assert e.value.status == tdse.ERR_CAPACITY
+
+
+def test_batch_two_step_odd_interval_counts():
+    """Record interval 10: an interval is five two-step launches, so the
+    state pair alternates between intervals; runs of 3 + 1 + 2 intervals
+    must end with the state in the bound arrays, equal to single runs."""
+    steps = 60
+    ws = small_set(steps)
+    b = tdse.batch_from_workloads(ws, precision="f32", steps=steps)
+    b.set_two_step(True, tx=56, zc=64, prefetch=True)
+    b.prepare()
+    for n in (30, 10, 20):
+        b.run(n)
+    assert all(s == tdse.OK for s in b.status())
+    say("odd intervals")
+    for w, m in zip(ws, b.members):
+        single = H.gpu_run(w, steps, precision="f32", tile=dict(fused=1, two_step=0))
+        assert bool((m.psi_r == single.psi_r).all()) and bool((m.psi_i == single.psi_i).all())
+        n = m.detect().n_records
+        assert bool((m.records[:n] == single.records[:n]).all())
+        assert m.detect().flux == pytest.approx(single.detect().flux, rel=1e-11, abs=1e-15)

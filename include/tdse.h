@@ -359,15 +359,16 @@ tdse_status tdse_batch_member(tdse_batch b, int32_t i, tdse_handle* h);
 tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc,
                                 int32_t prefetch, int32_t threads);
 /* Two-step sweeps for the whole batch (on by default): when every member
- * fits the sweep's tile (interior width tx, two rows per thread, z chunk
- * zc, prefetch as for tdse_tile) and the members share the vector width,
+ * fits the sweep's tile (interior width tx, rows per thread, z chunk zc,
+ * prefetch and threads per workgroup as for tdse_tile) and the members
+ * share the vector width,
  * tdse_batch_prepare captures intervals of S/2 two-step launches instead of
  * S one-pass launches; otherwise it falls back to the one-pass form.  When
  * S/2 is odd a second graph covers intervals that start from the second
  * state pair, and a run that ends there copies the members' state back
  * into their bound arrays. */
-tdse_status tdse_batch_set_two_step(tdse_batch b, int32_t enable, int32_t tx, int32_t zc,
-                                    int32_t prefetch);
+tdse_status tdse_batch_set_two_step(tdse_batch b, int32_t enable, int32_t tx, int32_t rows,
+                                    int32_t zc, int32_t prefetch, int32_t threads);
 tdse_status tdse_batch_prepare(tdse_batch b);
 tdse_status tdse_batch_run(tdse_batch b, int64_t n);
 tdse_status tdse_batch_status(tdse_batch b, int32_t* per_config);
@@ -436,10 +437,12 @@ tdse_status tdse_hbm_probe(int32_t kind, void* const* bufs, int64_t n, int32_t g
  * the one-pass kernel (which still takes single steps: a step whose level
  * is recorded first, an odd last step, the level before an adjoint
  * checkpoint).  two_step_tx = interior tile width (a multiple of the vector
- * width, >= 8), two_step_rows = rows per thread (2 or 3), so the interior
- * tile height is two_step_ty = (256 / ((tx + 8) / vector width)) * rows - 8
- * (read-only); two_step_zc = z planes per workgroup, two_step_prefetch != 0
- * loads the next plane's inputs one iteration ahead.  The sweep needs at
+ * width, >= 8), two_step_threads = threads per workgroup (256 or 512),
+ * two_step_rows = rows per thread (2 or 3 with 256 threads, 1 or 2 with
+ * 512), so the interior tile height is two_step_ty = (threads / ((tx + 8) /
+ * vector width)) * rows - 8 (read-only); two_step_zc = z planes per
+ * workgroup, two_step_prefetch != 0 loads the next plane's inputs one
+ * iteration ahead.  The sweep needs at
  * most ny tiles per plane and its LDS ((2 x 4) buffers of (ty + 10) x (tx +
  * 8) values) within the device's per-workgroup limit.
  *
@@ -448,7 +451,7 @@ tdse_status tdse_hbm_probe(int32_t kind, void* const* bufs, int64_t n, int32_t g
 typedef struct tdse_tile {
     int32_t rows, waves, zc;
     int32_t fused, fused_rows, fused_zc, fused_prefetch, graph, fused_threads;
-    int32_t two_step, two_step_tx, two_step_rows, two_step_zc, two_step_prefetch;
+    int32_t two_step, two_step_tx, two_step_rows, two_step_zc, two_step_prefetch, two_step_threads;
     int32_t vec_elems, vec_groups, lanes, band_rows, two_step_ty;
 } tdse_tile;
 

@@ -78,50 +78,77 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
 
-    for (int t = t0; t < t1; ++t) {
-        double s64[4][4];
+    // chunks of PC pixels of the workgroup's frames, in (frame, pixel) order;
+    // the next chunk's values are loaded into registers while the current
+    // one is summed from LDS
+    constexpr int PER = BK * PC / 256;   // values per thread and tile
+    const long cpt = (a.P + PC - 1) / PC;  // chunks per frame
+    const long nch = cpt * (t1 - t0);
+    T ra[PER], rb[PER];
+    // value i of a thread's tile share: row (tid / PC) + i (256 / PC), pixel tid % PC
+    constexpr int RSTEP = 256 / PC;
+    const int row0 = tid / PC, col = tid - row0 * PC;
+    const long rstride = (long)RSTEP * a.T * a.P;
+    const T* pa = F + ((long)(r0 + row0) * a.T) * a.P + col;
+    const T* pb = F + ((long)(c0 + row0) * a.T) * a.P + col;
+    auto fetch = [&](long c) {
+        const int t = t0 + (int)(c / cpt);
+        const long p0 = (c % cpt) * PC;
+        const bool pin = p0 + col < a.P;
+        const long off = (long)t * a.P + p0;
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) s64[x][y] = 0.0;
-        for (long p0 = 0; p0 < a.P; p0 += PC) {
-            // 64 trajectories x 32 pixels per tile, 8 values per thread
-            for (int e = tid; e < BK * PC; e += 256) {
-                const int row = e / PC, col = e - row * PC;
-                const long p = p0 + col;
-                const int ka = r0 + row, kb = c0 + row;
-                As[col * LS + row] = (ka < a.K && p < a.P) ? F[((long)ka * a.T + t) * a.P + p] : T(0);
-                Bs[col * LS + row] = (kb < a.K && p < a.P) ? F[((long)kb * a.T + t) * a.P + p] : T(0);
-            }
-            __syncthreads();
-            T s[4][4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) s[x][y] = T(0);
-#pragma unroll 8
-            for (int p = 0; p < PC; ++p) {
-                const V4 av = *reinterpret_cast<const V4*>(As + p * LS + 4 * tr);
-                const V4 bv = *reinterpret_cast<const V4*>(Bs + p * LS + 4 * tcl);
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) {
-                        const T e = av.v[x] - bv.v[y];
-                        s[x][y] += e * e;
-                    }
-            }
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) s64[x][y] += (double)s[x][y];
-            __syncthreads();
+        for (int i = 0; i < PER; ++i) {
+            ra[i] = (pin && r0 + row0 + RSTEP * i < a.K) ? pa[off + i * rstride] : T(0);
+            rb[i] = (pin && c0 + row0 + RSTEP * i < a.K) ? pb[off + i * rstride] : T(0);
         }
-        const double wt = a.w[t];
+    };
+    double s64[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) s64[x][y] = 0.0;
+    if (nch > 0) fetch(0);
+    for (long c = 0; c < nch; ++c) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            As[col * LS + row0 + RSTEP * i] = ra[i];
+            Bs[col * LS + row0 + RSTEP * i] = rb[i];
+        }
+        __syncthreads();
+        if (c + 1 < nch) fetch(c + 1);
+        T s[4][4];
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] += wt * sqrt(a.dA * s64[x][y]);
+            for (int y = 0; y < 4; ++y) s[x][y] = T(0);
+#pragma unroll 8
+        for (int p = 0; p < PC; ++p) {
+            const V4 av = *reinterpret_cast<const V4*>(As + p * LS + 4 * tr);
+            const V4 bv = *reinterpret_cast<const V4*>(Bs + p * LS + 4 * tcl);
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    const T e = av.v[x] - bv.v[y];
+                    s[x][y] += e * e;
+                }
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) s64[x][y] += (double)s[x][y];
+        if (c % cpt == cpt - 1) {
+            // the frame is complete
+            const double wt = a.w[t0 + (int)(c / cpt)];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    acc[x][y] += wt * sqrt(a.dA * s64[x][y]);
+                    s64[x][y] = 0.0;
+                }
+        }
+        __syncthreads();
     }
     double* out = a.part + (long)tc * a.K * a.K;
 #pragma unroll

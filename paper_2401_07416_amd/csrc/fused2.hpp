@@ -5,8 +5,9 @@
 // step moves 20 B per step.  The intermediate level (I^{n+1/2}, R^{n+1})
 // never leaves the chip.
 //
-// Mapping.  A workgroup owns an interior tile of tx x ty cells of every
-// plane of a z chunk, and works on the tile extended by four cells on each
+// Mapping.  A workgroup (NT = 256 or 512 threads) owns an interior tile of
+// tx x ty cells of every plane of a z chunk, and works on the tile extended
+// by four cells on each
 // side in x and y (ex = tx + 8, ey = ty + 8): each of the four half-steps
 // needs its input one cell further out than its output, so the region on
 // which a phase result is exact shrinks by one cell per phase, from the
@@ -65,7 +66,7 @@ struct Fused2Args {
     double pixel_w;
 };
 
-template <typename T, int W, int M, bool REC, bool PF>
+template <typename T, int W, int M, bool REC, bool PF, int NT>
 __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsigned char* smem_raw) {
     using VT = vec_t<T, W>;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -322,15 +323,15 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     }
 
     // fixed-order workgroup sums of the partials
-    __shared__ double red[256];
+    __shared__ double red[NT];
     const bool has_det = a.k_det >= k0 && a.k_det < k1;
     const bool has_up = a.k_up >= k0 && a.k_up < k1;
     auto wg_sum = [&](double v) -> double {
         __syncthreads();
         red[tid] = v;
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o && tid + o < (int)blockDim.x) red[tid] += red[tid + o];
+        for (int o = NT / 2; o > 0; o >>= 1) {
+            if (tid < o) red[tid] += red[tid + o];
             __syncthreads();
         }
         return red[0];
@@ -366,10 +367,10 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     }
 }
 
-template <typename T, int W, int M, bool REC, bool PF>
-__global__ __launch_bounds__(256) void fused2_kernel(Fused2Args<T> a) {
+template <typename T, int W, int M, bool REC, bool PF, int NT>
+__global__ __launch_bounds__(NT) void fused2_kernel(Fused2Args<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fused2_body<T, W, M, REC, PF>(a, xcd_remap(blockIdx.x, a.nwg), smem_raw);
+    fused2_body<T, W, M, REC, PF, NT>(a, xcd_remap(blockIdx.x, a.nwg), smem_raw);
 }
 
 // Two steps of many grids in one launch (the batch form of the sweep).
@@ -387,8 +388,8 @@ struct Batch2Step {
     int n, total_wg, parity, flux_slot;
 };
 
-template <typename T, int W, int M, bool REC, bool PF>
-__global__ __launch_bounds__(256) void fused2_batch_kernel(Batch2Step<T> b) {
+template <typename T, int W, int M, bool REC, bool PF, int NT>
+__global__ __launch_bounds__(NT) void fused2_batch_kernel(Batch2Step<T> b) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int Lg = xcd_remap(blockIdx.x, b.total_wg);
     int lo = 0, hi = b.n;  // wg_start[lo] <= Lg < wg_start[hi]
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(256) void fused2_batch_kernel(Batch2Step<T> b) {
     a.flux_a += (long)b.flux_slot * 2 * a.ntiles;
     a.flux_b = a.flux_a + 2 * a.ntiles;
     if (REC) a.rec_plane += (*b.rec_idx) * (long)a.nx * a.ny;
-    fused2_body<T, W, M, REC, PF>(a, Lg - b.wg_start[lo], smem_raw);
+    fused2_body<T, W, M, REC, PF, NT>(a, Lg - b.wg_start[lo], smem_raw);
 }
 
 }  // namespace tdse

@@ -43,7 +43,7 @@ struct tdse_ctx {
     bool fused = false;
     // two-step sweep: interior tile width, rows per thread, z chunk
     bool two = false;
-    int t2x = 56, t2m = 2, t2zc = 64;
+    int t2x = 56, t2m = 2, t2zc = 64, t2t = 256;
     bool t2pf = false;
     int lds_max = 65536;   // dynamic + static LDS per workgroup of the device
     // adjoint: checkpoints every adj_K steps of an adj_N-step forward run
@@ -101,7 +101,7 @@ struct tdse_batch_ctx {
     bool pf = false;
     // two-step sweep for the whole batch (when every member fits it)
     bool two = true;
-    int t2x = 64, t2zc = 64;
+    int t2x = 64, t2zc = 64, t2m = 2, t2t = 256;
     bool t2pf = true;
     bool use2 = false;  // chosen at prepare
     int par = 0;        // state pair holding the members' current level
@@ -258,16 +258,16 @@ hipError_t launch_fused_batch_f64(int w, int m, bool rec, bool pf, dim3 grid, in
                                   hipStream_t st, const BatchStep<double>& b);
 hipError_t launch_fused_f64(int w, int m, bool rec, bool pf, dim3 grid, int nt, size_t lds, hipStream_t st,
                             const FusedArgs<double>& a, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_fused2_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+hipError_t launch_fused2_f32(int w, int m, int nt, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
                              const Fused2Args<float>& a, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_fused2_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
+hipError_t launch_fused2_f64(int w, int m, int nt, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
                              const Fused2Args<double>& a, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_fused2_batch_f32(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
-                                   const Batch2Step<float>& b);
-hipError_t launch_fused2_batch_f64(int w, int m, bool rec, bool pf, dim3 grid, size_t lds, hipStream_t st,
-                                   const Batch2Step<double>& b);
-hipError_t fused2_batch_allow_lds_f32(int w, int m, size_t lds);
-hipError_t fused2_batch_allow_lds_f64(int w, int m, size_t lds);
+hipError_t launch_fused2_batch_f32(int w, int m, int nt, bool rec, bool pf, dim3 grid, size_t lds,
+                                   hipStream_t st, const Batch2Step<float>& b);
+hipError_t launch_fused2_batch_f64(int w, int m, int nt, bool rec, bool pf, dim3 grid, size_t lds,
+                                   hipStream_t st, const Batch2Step<double>& b);
+hipError_t fused2_batch_allow_lds_f32(int w, int m, int nt, size_t lds);
+hipError_t fused2_batch_allow_lds_f64(int w, int m, int nt, size_t lds);
 }  // namespace tdse
 
 namespace {
@@ -473,14 +473,15 @@ tdse_status launch_fused(tdse_ctx* h, const FusedDims& f, bool rec, long rec_idx
 }
 
 // Geometry of the two-step sweep for interior tile width tx, rows per
-// thread m and z chunk zc (256 threads per workgroup).
+// thread m, z chunk zc and nt threads per workgroup; the supported
+// (m, nt) are (2, 256), (3, 256), (1, 512) and (2, 512).
 struct Fused2Dims {
-    int W, tx, ty, ex, ey, tpr, rpp, ntx, nty, ntiles, nzc, nwg;
+    int W, tx, ty, ex, ey, tpr, rpp, ntx, nty, ntiles, nzc, nwg, nt;
     size_t lds;
     bool ok;
 };
 
-Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc) {
+Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc, int nt) {
     const tdse_desc& d = h->d;
     Fused2Dims f{};
     f.ok = false;
@@ -488,10 +489,12 @@ Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc) {
     const int wl32[3] = {4, 2, 1}, wl64[2] = {2, 1};
     const int* wl = es == 8 ? wl64 : wl32;
     const int nw = es == 8 ? 2 : 3;
-    if (tx < 8 || (m != 2 && m != 3) || zc < 1) return f;
+    const bool pair_ok = (nt == 256 && (m == 2 || m == 3)) || (nt == 512 && (m == 1 || m == 2));
+    if (tx < 8 || !pair_ok || zc < 1) return f;
+    f.nt = nt;
     f.W = 0;
     for (int i = 0; i < nw; ++i) {
-        if (d.nx % wl[i] == 0 && tx % wl[i] == 0 && (tx + 8) / wl[i] <= 256) {
+        if (d.nx % wl[i] == 0 && tx % wl[i] == 0 && (tx + 8) / wl[i] <= nt) {
             f.W = wl[i];
             break;
         }
@@ -500,7 +503,7 @@ Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc) {
     f.tx = tx;
     f.ex = tx + 8;
     f.tpr = f.ex / f.W;
-    f.rpp = 256 / f.tpr;
+    f.rpp = nt / f.tpr;
     f.ey = f.rpp * m;
     f.ty = f.ey - 8;
     if (f.ty < 1) return f;
@@ -510,9 +513,9 @@ Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc) {
     f.nzc = (int)((d.nz + zc - 1) / zc);
     f.nwg = f.ntiles * f.nzc;
     f.lds = (size_t)8 * (f.ey + 2) * f.ex * es;
-    // flux and partial slots are sized for ny per step / plane; 2 KB of
-    // static LDS for the reductions
-    f.ok = f.ntiles <= d.ny && f.lds + 2048 <= (size_t)h->lds_max &&
+    // flux and partial slots are sized for ny per step / plane; 8 B per
+    // thread of static LDS for the reductions
+    f.ok = f.ntiles <= d.ny && f.lds + 8 * (size_t)nt <= (size_t)h->lds_max &&
            (long)f.nwg < (1L << 31);
     return f;
 }
@@ -573,10 +576,10 @@ tdse_status launch_fused2(tdse_ctx* h, const Fused2Dims& f, bool rec, long rec_i
     hipError_t e;
     if (h->d.precision == TDSE_F64) {
         Fused2Args<double> a = make_fused2_args<double>(h, f, rec, rec_idx, flux_slot);
-        e = launch_fused2_f64(f.W, h->t2m, rec, h->t2pf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+        e = launch_fused2_f64(f.W, h->t2m, f.nt, rec, h->t2pf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
     } else {
         Fused2Args<float> a = make_fused2_args<float>(h, f, rec, rec_idx, flux_slot);
-        e = launch_fused2_f32(f.W, h->t2m, rec, h->t2pf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
+        e = launch_fused2_f32(f.W, h->t2m, f.nt, rec, h->t2pf, dim3(f.nwg), f.lds, h->stream, a, e0, e1);
     }
     return hip_check(h, e, "two-step sweep launch");
 }
@@ -847,7 +850,7 @@ void default_two_step(tdse_ctx* h) {
     for (int zc0 : {64, 128, 32}) {
         if (zc0 > d.nz) continue;
         for (int i = 0; i < ntx; ++i) {
-            const Fused2Dims f = fused2_dims(h, txl[i], 2, zc0);
+            const Fused2Dims f = fused2_dims(h, txl[i], 2, zc0, 256);
             if (f.ok && f.nwg >= 384) {
                 h->two = true;
                 h->t2x = txl[i];
@@ -946,9 +949,11 @@ static hipError_t batch_enqueue_interval2(tdse_batch_ctx* b, int par0) {
         const bool rec = b->h > 0 && j == launches - 1;
         hipError_t e;
         if constexpr (sizeof(T) == 8)
-            e = launch_fused2_batch_f64(b->W, 2, rec, b->t2pf, dim3(b->total_wg), b->lds, b->stream, st);
+            e = launch_fused2_batch_f64(b->W, b->t2m, b->t2t, rec, b->t2pf, dim3(b->total_wg), b->lds,
+                                        b->stream, st);
         else
-            e = launch_fused2_batch_f32(b->W, 2, rec, b->t2pf, dim3(b->total_wg), b->lds, b->stream, st);
+            e = launch_fused2_batch_f32(b->W, b->t2m, b->t2t, rec, b->t2pf, dim3(b->total_wg), b->lds,
+                                        b->stream, st);
         if (e != hipSuccess) return e;
     }
     BatchFin f;
@@ -980,14 +985,15 @@ static tdse_status batch_prepare2_t(tdse_batch_ctx* b, bool* used) {
     for (size_t i = 0; i < n; ++i) {
         tdse_ctx* h = b->members[i];
         const int zc = (int)std::min<int64_t>(b->t2zc, h->d.nz);
-        const Fused2Dims f = fused2_dims(h, b->t2x, 2, zc);
+        const Fused2Dims f = fused2_dims(h, b->t2x, b->t2m, zc, b->t2t);
         if (!f.ok) return TDSE_OK;
         if (W == 0) W = f.W;
         if (f.W != W) return TDSE_OK;
         h->t2x = b->t2x;
-        h->t2m = 2;
+        h->t2m = b->t2m;
         h->t2zc = zc;
         h->t2pf = b->t2pf;
+        h->t2t = b->t2t;
         cfg[i] = make_fused2_args<T>(h, f, b->h > 0, 0, 0);
         cfg[i].rec_plane = static_cast<T*>(h->rec);  // record 0; the kernel adds the counter
         lds = std::max(lds, f.lds);
@@ -1013,7 +1019,8 @@ static tdse_status batch_prepare2_t(tdse_batch_ctx* b, bool* used) {
     b->W = W;
     b->lds = lds;
     b->total_wg = wg[n];
-    hipError_t e = sizeof(T) == 8 ? fused2_batch_allow_lds_f64(W, 2, lds) : fused2_batch_allow_lds_f32(W, 2, lds);
+    hipError_t e = sizeof(T) == 8 ? fused2_batch_allow_lds_f64(W, b->t2m, b->t2t, lds)
+                                  : fused2_batch_allow_lds_f32(W, b->t2m, b->t2t, lds);
     if (e != hipSuccess) return bfail(b, TDSE_ERR_DEVICE, std::string("batch LDS: ") + hipGetErrorString(e));
     if (hipMalloc(&b->d_cfg, n * sizeof(Fused2Args<T>)) != hipSuccess ||
         hipMalloc(&b->d_fin, n * sizeof(FinArgs)) != hipSuccess ||
@@ -1681,7 +1688,7 @@ static tdse_status step_plain(tdse_ctx* h, int64_t n) {
     const int64_t hrec = d.record_every;
     const FusedDims fd = fused_dims(h, h->fm, h->fzc);
     const bool use_fused = h->fused && h->R2 && fd.ok;
-    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc);
+    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t);
     const bool use_f2 = use_fused && h->two && f2.ok;
     const TileDims td = tile_dims(h, h->rows, h->waves, h->zc);
     auto is_rec = [&](int64_t s) { return hrec > 0 && (s + 1) % hrec == 0; };
@@ -1781,7 +1788,7 @@ tdse_status tdse_step(tdse_handle h, int64_t n) {
     if (hrec > 0 && (h->step + n) / hrec + 1 > d.max_records)
         return fail(h, TDSE_ERR_CAPACITY, "record buffer would overflow");
     const FusedDims fd = fused_dims(h, h->fm, h->fzc);
-    const bool two = h->two && fused2_dims(h, h->t2x, h->t2m, h->t2zc).ok;
+    const bool two = h->two && fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t).ok;
     const bool graph_ok = h->fused && h->R2 && fd.ok && h->graph_on && h->stream != nullptr &&
                           !h->timing && !h->adj_ws && !two && hrec > 0 && hrec % 2 == 0 &&
                           hrec <= 256;
@@ -1906,7 +1913,8 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
     out->two_step_rows = h->t2m;
     out->two_step_zc = h->t2zc;
     out->two_step_prefetch = h->t2pf ? 1 : 0;
-    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc);
+    out->two_step_threads = h->t2t;
+    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t);
     out->two_step_ty = f2.ok ? f2.ty : 0;
     out->vec_elems = h->W;
     out->vec_groups = h->G;
@@ -1934,10 +1942,12 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
             return fail(h, TDSE_ERR_UNSUPPORTED, "one-pass tile does not fit this grid");
     }
     if (t->two_step_zc < 1) return fail(h, TDSE_ERR_ARG, "z chunks must be >= 1");
+    if (t->two_step_threads != 256 && t->two_step_threads != 512)
+        return fail(h, TDSE_ERR_ARG, "two_step_threads must be 256 or 512");
     const int t2zc = (int)std::min<int64_t>(t->two_step_zc, h->d.nz);
     if (t->two_step) {
         if (!t->fused) return fail(h, TDSE_ERR_ARG, "the two-step sweep runs with the one-pass step");
-        if (!fused2_dims(h, t->two_step_tx, t->two_step_rows, t2zc).ok)
+        if (!fused2_dims(h, t->two_step_tx, t->two_step_rows, t2zc, t->two_step_threads).ok)
             return fail(h, TDSE_ERR_UNSUPPORTED, "two-step tile does not fit this grid");
     }
     graph_invalidate(h);
@@ -1955,6 +1965,7 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
     h->t2m = t->two_step_rows;
     h->t2zc = t2zc;
     h->t2pf = t->two_step_prefetch != 0;
+    h->t2t = t->two_step_threads;
     return TDSE_OK;
 }
 
@@ -2137,15 +2148,19 @@ tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_
     return TDSE_OK;
 }
 
-tdse_status tdse_batch_set_two_step(tdse_batch b, int32_t enable, int32_t tx, int32_t zc,
-                                    int32_t prefetch) {
+tdse_status tdse_batch_set_two_step(tdse_batch b, int32_t enable, int32_t tx, int32_t rows,
+                                    int32_t zc, int32_t prefetch, int32_t threads) {
     if (!b) return TDSE_ERR_ARG;
-    if (tx < 8 || zc < 1) return bfail(b, TDSE_ERR_ARG, "two-step tile");
+    const bool pair_ok = (threads == 256 && (rows == 2 || rows == 3)) ||
+                         (threads == 512 && (rows == 1 || rows == 2));
+    if (tx < 8 || zc < 1 || !pair_ok) return bfail(b, TDSE_ERR_ARG, "two-step tile");
     batch_free_device(b);
     b->two = enable != 0;
     b->t2x = tx;
+    b->t2m = rows;
     b->t2zc = zc;
     b->t2pf = prefetch != 0;
+    b->t2t = threads;
     return TDSE_OK;
 }
 

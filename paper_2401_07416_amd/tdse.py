@@ -82,7 +82,7 @@ class Tile(ctypes.Structure):
                 ("graph", ctypes.c_int32), ("fused_threads", ctypes.c_int32),
                 ("two_step", ctypes.c_int32), ("two_step_tx", ctypes.c_int32),
                 ("two_step_rows", ctypes.c_int32), ("two_step_zc", ctypes.c_int32),
-                ("two_step_prefetch", ctypes.c_int32),
+                ("two_step_prefetch", ctypes.c_int32), ("two_step_threads", ctypes.c_int32),
                 ("vec_elems", ctypes.c_int32),
                 ("vec_groups", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("band_rows", ctypes.c_int32), ("two_step_ty", ctypes.c_int32)]
@@ -137,7 +137,7 @@ def load():
         "tdse_batch_create": (i32, [ctypes.POINTER(Desc), i32, vp, ctypes.POINTER(vp)]),
         "tdse_batch_member": (i32, [vp, i32, ctypes.POINTER(vp)]),
         "tdse_batch_set_tile": (i32, [vp, i32, i32, i32, i32]),
-        "tdse_batch_set_two_step": (i32, [vp, i32, i32, i32, i32]),
+        "tdse_batch_set_two_step": (i32, [vp, i32, i32, i32, i32, i32, i32]),
         "tdse_batch_prepare": (i32, [vp]),
         "tdse_batch_run": (i32, [vp, i64]),
         "tdse_batch_status": (i32, [vp, ctypes.POINTER(i32)]),
@@ -429,14 +429,15 @@ class Sim:
     def set_tile(self, rows=None, waves=None, zc=None, fused=None, fused_rows=None,
                  fused_zc=None, fused_prefetch=None, graph=None, fused_threads=None,
                  two_step=None, two_step_tx=None, two_step_rows=None, two_step_zc=None,
-                 two_step_prefetch=None):
+                 two_step_prefetch=None, two_step_threads=None):
         t = self.get_tile()
         for name, v in (("rows", rows), ("waves", waves), ("zc", zc), ("fused", fused),
                         ("fused_rows", fused_rows), ("fused_zc", fused_zc),
                         ("fused_prefetch", fused_prefetch), ("graph", graph),
                         ("fused_threads", fused_threads), ("two_step", two_step),
                         ("two_step_tx", two_step_tx), ("two_step_rows", two_step_rows),
-                        ("two_step_zc", two_step_zc), ("two_step_prefetch", two_step_prefetch)):
+                        ("two_step_zc", two_step_zc), ("two_step_prefetch", two_step_prefetch),
+                        ("two_step_threads", two_step_threads)):
             if v is not None:
                 setattr(t, name, int(v))
         self._check(self.lib.tdse_set_tile(self.h, ctypes.byref(t)))
@@ -581,10 +582,10 @@ class Batch:
         self._check(self.lib.tdse_batch_set_tile(self.b, int(fused_rows), int(fused_zc),
                                                  int(bool(prefetch)), int(threads)))
 
-    def set_two_step(self, enable=True, tx=64, zc=64, prefetch=True):
+    def set_two_step(self, enable=True, tx=64, zc=64, prefetch=True, rows=2, threads=256):
         """Two-step sweeps for the whole batch where every member fits them."""
-        self._check(self.lib.tdse_batch_set_two_step(self.b, int(bool(enable)), int(tx), int(zc),
-                                                     int(bool(prefetch))))
+        self._check(self.lib.tdse_batch_set_two_step(self.b, int(bool(enable)), int(tx), int(rows),
+                                                     int(zc), int(bool(prefetch)), int(threads)))
 
     def prepare(self):
         self.torch.cuda.synchronize(self.device)

@@ -35,7 +35,7 @@ def small_set(steps):
     return out
 
 
-@pytest.mark.parametrize("form", ["two-step", "one-pass-256", "one-pass-64"])
+@pytest.mark.parametrize("form", ["two-step", "two-step-512", "one-pass-256", "one-pass-64"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_batch_equals_single_runs(prec, form):
     steps = 60
@@ -44,6 +44,8 @@ def test_batch_equals_single_runs(prec, form):
     b = tdse.batch_from_workloads(ws, precision=prec, steps=steps)
     if form == "two-step":
         b.set_two_step(True, tx=24, zc=32, prefetch=True)
+    elif form == "two-step-512":
+        b.set_two_step(True, tx=32, zc=16, prefetch=True, rows=1, threads=512)
     else:
         b.set_two_step(False)
         b.set_tile(fused_rows=3, fused_zc=16, prefetch=True, threads=int(form.split("-")[-1]))

@@ -25,12 +25,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def two(tx, rows, zc, pf=0):
+def two(tx, rows, zc, pf=0, threads=256):
     return dict(fused=1, two_step=1, two_step_tx=tx, two_step_rows=rows, two_step_zc=zc,
-                two_step_prefetch=pf)
+                two_step_prefetch=pf, two_step_threads=threads)
 
 
-TILES2 = [two(56, 2, 64), two(24, 2, 16, 1), two(8, 3, 7), two(120, 3, 33, 1)]
+TILES2 = [two(56, 2, 64), two(24, 2, 16, 1), two(8, 3, 7), two(120, 3, 33, 1),
+          two(64, 1, 64, 1, 512), two(24, 2, 32, 1, 512), two(8, 1, 9, 0, 512)]
 
 
 def same_run(a, b):
@@ -64,7 +65,7 @@ def test_two_step_ragged_boundaries_vs_oracle(prec, bc):
     w = workloads.ragged(prec).with_(bc=bc)
     say("two-step ragged", prec, "bc", bc)
     ref = H.oracle_run(w, w.steps)
-    for tile in (two(8, 2, 16), two(16, 3, 53, 1)):
+    for tile in (two(8, 2, 16), two(16, 3, 53, 1), two(16, 1, 20, 1, 512)):
         gpu = H.gpu_run(w, w.steps, precision=prec, tile=tile)
         say(" tile", tile, H.compare(gpu, ref, **(FP64 if prec == "f64" else FP32)))
 
@@ -153,6 +154,7 @@ def test_two_step_timing_counts_launches():
 def test_two_step_rejects_bad_tiles():
     w = workloads.c2_reduced().with_(steps=10)
     s = tdse.sim_from_workload(w, precision="f32", steps=10)
-    for bad in (two(4, 2, 8), two(56, 4, 8), two(2040, 2, 8), dict(fused=0, two_step=1)):
+    for bad in (two(4, 2, 8), two(56, 4, 8), two(2040, 2, 8), dict(fused=0, two_step=1),
+                two(56, 3, 8, 0, 512), two(56, 2, 8, 0, 128)):
         with pytest.raises(tdse.TdseError):
             s.set_tile(**bad)

@@ -119,11 +119,25 @@ def cpu_baseline(w, seconds, planes):
     el = time.perf_counter() - t0
     threads = oracle.get_threads()
     cells = w.nx * w.ny * planes
-    return {"value": cells * steps / el / 1e9, "unit": "Gcell-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"FP64 oracle, {w.nx}x{w.ny}x{planes}-plane slab of the {w.name} grid "
-                      f"around the packet, {steps} steps, {el:.1f} s",
-            "ns_per_cell_step": el / (cells * steps) * 1e9}
+    out = {"value": cells * steps / el / 1e9, "unit": "Gcell-steps/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"FP64 oracle, {w.nx}x{w.ny}x{planes}-plane slab of the {w.name} grid "
+                     f"around the packet, {steps} steps, {el:.1f} s",
+           "ns_per_cell_step": el / (cells * steps) * 1e9}
+    # the serial analogue (one core), on the same slab for about a quarter of
+    # the time
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    s.step(1)
+    per1 = time.perf_counter() - t0
+    steps1 = max(1, int(seconds / 4 / per1))
+    t0 = time.perf_counter()
+    s.step(steps1)
+    el1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    out["single_core"] = {"value": cells * steps1 / el1 / 1e9, "cores": 1, "steps": steps1,
+                          "ns_per_cell_step": el1 / (cells * steps1) * 1e9}
+    return out
 
 
 def time_steps(sim, n):
@@ -433,6 +447,9 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, a.cpu_planes)
         out["cpu_baseline"]["speedup_gpu_over_cpu"] = round(value / out["cpu_baseline"]["value"], 1)
+        sc = out["cpu_baseline"]["single_core"]
+        sc["speedup_gpu_over_single_core"] = round(value / sc["value"], 1)
+        sc["paper_speedup_over_serial_cpu"] = 350
     print(json.dumps(out), flush=True)
 
 

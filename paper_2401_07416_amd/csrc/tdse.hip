@@ -101,7 +101,7 @@ struct tdse_batch_ctx {
     bool pf = false;
     // two-step sweep for the whole batch (when every member fits it)
     bool two = true;
-    int t2x = 64, t2zc = 64, t2m = 2, t2t = 256;
+    int t2x = 64, t2zc = 64, t2m = 1, t2t = 512;
     bool t2pf = true;
     bool use2 = false;  // chosen at prepare
     int par = 0;        // state pair holding the members' current level
@@ -839,21 +839,32 @@ void default_fused_tile(tdse_ctx* h) {
 void default_two_step(tdse_ctx* h) {
     const tdse_desc& d = h->d;
     const bool f64 = d.precision == TDSE_F64;
-    const int tx32[4] = {64, 56, 32, 24}, tx64[3] = {32, 24, 16};
-    const int* txl = f64 ? tx64 : tx32;
-    const int ntx = f64 ? 3 : 4;
+    struct Cand {
+        int tx, m, nt;
+    };
+    const Cand c32[5] = {{64, 1, 512}, {64, 2, 256}, {56, 2, 256}, {32, 1, 512}, {24, 2, 256}};
+    const Cand c64[6] = {{56, 2, 512}, {64, 2, 512}, {32, 1, 512}, {32, 2, 256}, {24, 2, 256},
+                         {16, 2, 256}};
+    const Cand* cl = f64 ? c64 : c32;
+    const int nc = f64 ? 6 : 5;
+    const int zcs32[3] = {64, 128, 32}, zcs64[3] = {128, 64, 32};
+    const int* zcs = f64 ? zcs64 : zcs32;
     h->two = false;
-    h->t2m = 2;
+    h->t2x = cl[0].tx;
+    h->t2m = cl[0].m;
+    h->t2t = cl[0].nt;
     h->t2pf = true;
-    h->t2x = txl[0];
     h->t2zc = (int)std::min<int64_t>(64, d.nz);
-    for (int zc0 : {64, 128, 32}) {
+    for (int z = 0; z < 3; ++z) {
+        const int zc0 = zcs[z];
         if (zc0 > d.nz) continue;
-        for (int i = 0; i < ntx; ++i) {
-            const Fused2Dims f = fused2_dims(h, txl[i], 2, zc0, 256);
-            if (f.ok && f.nwg >= 384) {
+        for (int i = 0; i < nc; ++i) {
+            const Fused2Dims f = fused2_dims(h, cl[i].tx, cl[i].m, zc0, cl[i].nt);
+            if (f.ok && (long)f.nwg * cl[i].nt >= 384L * 256) {
                 h->two = true;
-                h->t2x = txl[i];
+                h->t2x = cl[i].tx;
+                h->t2m = cl[i].m;
+                h->t2t = cl[i].nt;
                 h->t2zc = zc0;
                 return;
             }

@@ -43,7 +43,7 @@ def test_batch_equals_single_runs(prec, form):
     say("batch of", [w.name for w in ws], prec, form)
     b = tdse.batch_from_workloads(ws, precision=prec, steps=steps)
     if form == "two-step":
-        b.set_two_step(True, tx=24, zc=32, prefetch=True)
+        b.set_two_step(True, tx=24, zc=32, prefetch=True, rows=2, threads=256)
     elif form == "two-step-512":
         b.set_two_step(True, tx=32, zc=16, prefetch=True, rows=1, threads=512)
     else:

@@ -456,6 +456,17 @@ typedef struct tdse_tile {
 } tdse_tile;
 
 tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out);
+
+/* Tile autotuner: times a built-in list of candidate tiles on the handle's
+ * own grid and state (flags: bit 0 two-pass, bit 1 one-pass, bit 2 two-step
+ * sweep; 0 = all; the one-pass and two-step candidates need
+ * tdse_bind_pingpong), each for 2 warm-up and `steps` timed steps with HIP
+ * events on the handle's stream, without records; keeps the fastest, sets
+ * it and returns it in *out.  The state is spent: afterwards the handle
+ * needs tdse_init_gaussian or tdse_set_state before tdse_step
+ * (TDSE_ERR_STATE until then).  TDSE_ERR_STATE without a state, with
+ * pending sums or with an adjoint bound. */
+tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile* out);
 tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t);
 
 #ifdef __cplusplus

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void adjoint_half_kernel(AdjArgs<T> a) {
                 for (int e = 0; e < W; ++e) out[g].v[e] = T(0);
             return;
         }
-        const T s = a.cb[kk];
+        const T s = ld_uniform(a.cb, kk);
         const T* p = base + (long)kk * plane + (long)jj * nx + (long)lc * W;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -107,8 +107,8 @@ __global__ __launch_bounds__(256) void adjoint_half_kernel(AdjArgs<T> a) {
         for (int r = 0; r < RY; ++r) load_scaled(a.S, jrow[r], kwrap(k + 1), sn[r]);
         load_scaled(a.S, jlo, k, hl);
         load_scaled(a.S, jhi, k, hh);
-        const T cak = a.ca[k];
-        const T cbk = a.cb[k];
+        const T cak = ld_uniform(a.ca, k);
+        const T cbk = ld_uniform(a.cb, k);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             if (!real[r]) continue;

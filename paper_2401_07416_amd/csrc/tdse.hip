@@ -1980,6 +1980,89 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
     return TDSE_OK;
 }
 
+tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile* out) {
+    if (!h || !out || steps < 1) return TDSE_ERR_ARG;
+    if (!h->ready) return fail(h, TDSE_ERR_STATE, "no state: init_gaussian or set_state first");
+    if (h->pending != 0) return fail(h, TDSE_ERR_STATE, "pending flux partials");
+    if (h->adj_ws) return fail(h, TDSE_ERR_STATE, "unbind the adjoint before tuning");
+    const bool want2p = flags == 0 || (flags & 1), want1p = flags == 0 || (flags & 2),
+               want2s = flags == 0 || (flags & 4);
+    tdse_tile base;
+    tdse_get_tile(h, &base);
+    std::vector<tdse_tile> cands;
+    if (want2p) {
+        const int c[4][3] = {{2, 4, 64}, {4, 4, 64}, {2, 4, 16}, {1, 4, 32}};
+        for (const auto& x : c) {
+            tdse_tile t = base;
+            t.fused = 0;
+            t.two_step = 0;
+            t.rows = x[0];
+            t.waves = x[1];
+            t.zc = x[2];
+            cands.push_back(t);
+        }
+    }
+    if (want1p && h->R2) {
+        const int c[5][3] = {{3, 64, 256}, {2, 32, 256}, {4, 64, 256}, {2, 8, 128}, {3, 16, 256}};
+        for (const auto& x : c) {
+            tdse_tile t = base;
+            t.fused = 1;
+            t.two_step = 0;
+            t.fused_rows = x[0];
+            t.fused_zc = x[1];
+            t.fused_threads = x[2];
+            t.fused_prefetch = 0;
+            cands.push_back(t);
+        }
+    }
+    if (want2s && h->R2) {
+        const int c[6][4] = {{64, 1, 512, 64}, {56, 1, 512, 64}, {56, 2, 512, 128},
+                             {64, 2, 256, 64}, {32, 1, 512, 32}, {32, 2, 256, 128}};
+        for (const auto& x : c) {
+            tdse_tile t = base;
+            t.fused = 1;
+            t.two_step = 1;
+            t.two_step_tx = x[0];
+            t.two_step_rows = x[1];
+            t.two_step_threads = x[2];
+            t.two_step_zc = x[3];
+            t.two_step_prefetch = 1;
+            cands.push_back(t);
+        }
+    }
+    // no records while tuning (the state is given up anyway)
+    const int64_t hrec = h->d.record_every;
+    h->d.record_every = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    tdse_status st = hip_check(h, hipEventCreate(&e0), "event");
+    if (st == TDSE_OK) st = hip_check(h, hipEventCreate(&e1), "event");
+    float best = -1.f;
+    tdse_tile win = base;
+    for (const tdse_tile& t : cands) {
+        if (st != TDSE_OK) break;
+        if (tdse_set_tile(h, &t) != TDSE_OK) continue;  // does not fit this grid
+        st = step_plain(h, 2);
+        if (st == TDSE_OK) st = hip_check(h, hipEventRecord(e0, h->stream), "event");
+        if (st == TDSE_OK) st = step_plain(h, steps);
+        if (st == TDSE_OK) st = hip_check(h, hipEventRecord(e1, h->stream), "event");
+        if (st == TDSE_OK) st = hip_check(h, hipEventSynchronize(e1), "event");
+        float ms = 0.f;
+        if (st == TDSE_OK) st = hip_check(h, hipEventElapsedTime(&ms, e0, e1), "event");
+        if (st == TDSE_OK && (best < 0 || ms < best)) {
+            best = ms;
+            win = t;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    h->d.record_every = hrec;
+    h->ready = false;
+    if (st != TDSE_OK) return st;
+    st = tdse_set_tile(h, &win);
+    if (st != TDSE_OK) return st;
+    return tdse_get_tile(h, out);
+}
+
 tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2) {
     if (!h) return TDSE_ERR_ARG;
     if (!h->bound) return fail(h, TDSE_ERR_STATE, "bind before bind_pingpong");

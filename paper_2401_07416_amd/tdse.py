@@ -36,7 +36,7 @@ EXPORTS = [
     "tdse_batch_prepare", "tdse_batch_run", "tdse_batch_status", "tdse_batch_last_error",
     "tdse_batch_destroy", "tdse_hbm_probe", "tdse_interpolate_potential",
     "tdse_dissimilarity_workspace_size", "tdse_dissimilarity", "tdse_set_cap_paper",
-    "tdse_time_step_paper", "tdse_batch_set_two_step",
+    "tdse_time_step_paper", "tdse_batch_set_two_step", "tdse_autotune",
 ]
 
 
@@ -145,6 +145,7 @@ def load():
         "tdse_batch_destroy": (i32, [vp]),
         "tdse_get_tile": (i32, [vp, ctypes.POINTER(Tile)]),
         "tdse_set_tile": (i32, [vp, ctypes.POINTER(Tile)]),
+        "tdse_autotune": (i32, [vp, i32, i32, ctypes.POINTER(Tile)]),
         "tdse_hbm_probe": (i32, [i32, ctypes.POINTER(vp), i64, i32, i32, vp, dp]),
         "tdse_interpolate_potential": (i32, [vp, vp, i32, i32, i32, dp, dp]),
         "tdse_set_cap_paper": (i32, [vp, ctypes.c_double, ctypes.c_double]),
@@ -420,6 +421,13 @@ class Sim:
         n = (ctypes.c_int64 * 4)()
         self._check(self.lib.tdse_timing_read(self.h, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(("half_i", "half_r", "fused", "two_step"))}
+
+    def autotune(self, steps: int = 10, flags: int = 0) -> Tile:
+        """Library autotuner: times its candidate tiles on this grid, keeps the
+        fastest.  The state is spent (set a new one before stepping)."""
+        t = Tile()
+        self._check(self.lib.tdse_autotune(self.h, int(steps), int(flags), ctypes.byref(t)))
+        return t
 
     def get_tile(self) -> Tile:
         t = Tile()

@@ -158,3 +158,20 @@ def test_two_step_rejects_bad_tiles():
                 two(56, 3, 8, 0, 512), two(56, 2, 8, 0, 128)):
         with pytest.raises(tdse.TdseError):
             s.set_tile(**bad)
+
+
+def test_library_autotuner_picks_a_tile_and_spends_the_state():
+    w = workloads.c2_reduced().with_(steps=100)
+    s = tdse.sim_from_workload(w, precision="f32", steps=100)
+    t = s.autotune(steps=6)
+    say("autotuned", t.as_dict())
+    assert t.fused in (0, 1) and (t.two_step == 0 or t.two_step_ty > 0)
+    with pytest.raises(tdse.TdseError) as e:
+        s.step(2)
+    assert e.value.status == tdse.ERR_STATE
+    # a fresh state on the tuned tile gives the bits of the default run
+    ref = H.gpu_run(w, 100, precision="f32")
+    r0 = tdse.sim_from_workload(w, precision="f32", steps=100)
+    s.set_state(r0.psi_r, r0.psi_i, step=0)
+    s.step(100)
+    assert bool((s.psi_r == ref.psi_r).all()) and bool((s.psi_i == ref.psi_i).all())

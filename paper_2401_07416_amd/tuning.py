@@ -51,12 +51,12 @@ def candidates(nz: int):
             if zc <= nz:
                 yield dict(fused=1, two_step=0, fused_rows=fr, fused_zc=zc, fused_prefetch=1,
                            fused_threads=256)
-    for tx in (16, 24, 32, 40, 56, 64):
-        for zc in (32, 64, 128):
-            if zc <= nz:
-                for pf in (1, 0):
-                    yield dict(fused=1, two_step=1, two_step_tx=tx, two_step_rows=2,
-                               two_step_zc=zc, two_step_prefetch=pf)
+    for tx in (16, 24, 32, 40, 56, 64, 120):
+        for rows, threads in ((2, 256), (1, 512), (2, 512)):
+            for zc in (32, 64, 128):
+                if zc <= nz:
+                    yield dict(fused=1, two_step=1, two_step_tx=tx, two_step_rows=rows,
+                               two_step_zc=zc, two_step_prefetch=1, two_step_threads=threads)
 
 
 def autotune(sim, steps: int = 20, reps: int = 3, cands=None):

@@ -21,6 +21,7 @@
 #include "fused.hpp"
 #include "fused2.hpp"
 #include "adjoint.hpp"
+#include "adjoint_fused.hpp"
 
 using namespace tdse;
 
@@ -267,6 +268,10 @@ hipError_t launch_fused2_batch_f32(int w, int m, int nt, bool rec, bool pf, dim3
 hipError_t launch_fused2_batch_f64(int w, int m, int nt, bool rec, bool pf, dim3 grid, size_t lds,
                                    hipStream_t st, const Batch2Step<double>& b);
 hipError_t fused2_batch_allow_lds_f32(int w, int m, int nt, size_t lds);
+hipError_t launch_adjoint_fused_f32(int w, int m, dim3 grid, size_t lds, hipStream_t st,
+                                    const AdjFusedArgs<float>& a);
+hipError_t launch_adjoint_fused_f64(int w, int m, dim3 grid, size_t lds, hipStream_t st,
+                                    const AdjFusedArgs<double>& a);
 hipError_t fused2_batch_allow_lds_f64(int w, int m, int nt, size_t lds);
 }  // namespace tdse
 
@@ -379,6 +384,7 @@ tdse_status launch_half(tdse_ctx* h, int mode, int rows, int waves, int zc, long
 // rpp rows per pass of a 256-thread workgroup, band of ty = rpp*m - 2 rows.
 struct FusedDims {
     int W, tpr, rpp, ty, nbands, nzc, nwg, threads;
+    int zcu;  // the z chunk the geometry was made for
     size_t lds;
     bool ok;
 };
@@ -404,6 +410,7 @@ FusedDims fused_dims(const tdse_ctx* h, int m, int zc, int threads = 0) {
     f.rpp = f.threads / f.tpr;
     f.ty = f.rpp * m - 2;
     f.nbands = f.ty > 0 ? (int)((d.ny + f.ty - 1) / f.ty) : 0;
+    f.zcu = zc;
     f.nzc = (int)((d.nz + zc - 1) / zc);
     f.nwg = f.nbands * f.nzc;
     f.lds = (size_t)(3 * f.ty + 8) * d.nx * es;
@@ -627,10 +634,11 @@ tdse_status begin_records(tdse_ctx* h) {
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % ALIGN) == 0; }
 
 // Adjoint workspace: checkpoints of levels 0, K, 2K, ... < N, the K + 1
-// states of one recomputed segment, and r, i, A i_t and (FP32) the segment
-// accumulator of dL/dV.  Each array is [nz][ny][nx] in the state precision.
+// states of one recomputed segment, r and its second buffer, i and A i_t,
+// and (FP32) the segment accumulator of dL/dV.  Each array is [nz][ny][nx]
+// in the state precision.
 struct AdjLayout {
-    size_t arr, nck, ckpt, seg, rb, ia, ib, gv, total;
+    size_t arr, nck, ckpt, seg, rb, rc, ia, ib, gv, total;
 };
 
 AdjLayout adj_layout(const tdse_desc& d, int64_t N, int K) {
@@ -641,6 +649,7 @@ AdjLayout adj_layout(const tdse_desc& d, int64_t N, int K) {
     L.ckpt = o; o += 2 * L.nck * L.arr;
     L.seg = o; o += 2 * ((size_t)K + 1) * L.arr;
     L.rb = o; o += L.arr;
+    L.rc = o; o += L.arr;
     L.ia = o; o += L.arr;
     L.ib = o; o += L.arr;
     L.gv = o; o += L.arr;
@@ -725,6 +734,63 @@ tdse_status forward_step_explicit(tdse_ctx* h, void* Rs, void* Is, void* Rd, voi
     return st;
 }
 
+// Geometry of the one-pass reverse step (the forward band mapping with 256
+// threads); not ok where the one-pass forward step is off.
+FusedDims adj_fused_dims(const tdse_ctx* h) {
+    FusedDims best{};
+    best.ok = false;
+    if (!h->fused) return best;
+    for (int zc0 : {64, 32, 16, 8}) {
+        const int zc = (int)std::min<int64_t>(zc0, h->d.nz);
+        const FusedDims f = fused_dims(h, 2, zc, 256);
+        if (!f.ok) return best;
+        best = f;
+        best.zcu = zc;
+        if ((long)f.nwg >= 1024) break;
+    }
+    return best;
+}
+
+template <typename T>
+tdse_status launch_adj_fused(tdse_ctx* h, const FusedDims& f, const T* r, const T* i, T* r_out,
+                             T* i_out, const T* Rn, const T* Ih, T* gv) {
+    const tdse_desc& d = h->d;
+    AdjFusedArgs<T> a;
+    a.r = r;
+    a.i = i;
+    a.r_out = r_out;
+    a.i_out = i_out;
+    a.V = static_cast<const T*>(h->V);
+    a.Rn = Rn;
+    a.Ih = Ih;
+    a.gv = gv;
+    a.ca = static_cast<const T*>(h->ca);
+    a.cb = static_cast<const T*>(h->cb);
+    a.cx = (T)h->c[0];
+    a.cy = (T)h->c[1];
+    a.cz = (T)h->c[2];
+    a.cv = (T)h->c[3];
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    a.tpr = f.tpr;
+    a.rpp = f.rpp;
+    a.ty = f.ty;
+    a.nbands = f.nbands;
+    a.zc = f.zcu;
+    a.nzc = f.nzc;
+    a.nwg = f.nwg;
+    a.bcx = d.bc[0] == TDSE_BC_ZERO;
+    a.bcy = d.bc[1] == TDSE_BC_ZERO;
+    a.bcz = d.bc[2] == TDSE_BC_ZERO;
+    hipError_t e;
+    if constexpr (sizeof(T) == 8)
+        e = launch_adjoint_fused_f64(f.W, 2, dim3(f.nwg), f.lds, h->stream, a);
+    else
+        e = launch_adjoint_fused_f32(f.W, 2, dim3(f.nwg), f.lds, h->stream, a);
+    return hip_check(h, e, "one-pass adjoint launch");
+}
+
 template <typename T>
 tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* gI0) {
     const tdse_desc& d = h->d;
@@ -737,6 +803,7 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
     auto ck = [&](size_t c, int which) { return reinterpret_cast<T*>(w + L.ckpt + (2 * c + which) * L.arr); };
     auto sg = [&](size_t m, int which) { return reinterpret_cast<T*>(w + L.seg + (2 * m + which) * L.arr); };
     T* rb = reinterpret_cast<T*>(w + L.rb);
+    T* rc = reinterpret_cast<T*>(w + L.rc);
     T* ia = reinterpret_cast<T*>(w + L.ia);
     T* ib = reinterpret_cast<T*>(w + L.ib);
     T* gv = sizeof(T) == 8 ? reinterpret_cast<T*>(gV64) : reinterpret_cast<T*>(w + L.gv);
@@ -754,6 +821,8 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
                            Im, rho_bar + (lev / hrec) * nxy, poff, nxy);
         return hip_check(h, hipGetLastError(), "inject launch");
     };
+    // the one-pass reverse step where the one-pass forward step is on
+    const FusedDims af = adj_fused_dims(h);
     bool first = true;
     for (int64_t c = (int64_t)L.nck - 1; c >= 0; --c) {
         const int64_t s0 = c * K;
@@ -773,10 +842,17 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
         for (int64_t m = s1 - 1; m >= s0; --m) {
             const T* Rn = sg(m - s0, 0);
             const T* Ih = sg(m - s0 + 1, 1);
-            tdse_status st = launch_adj<T>(h, 0, make_adj_args<T>(h, rb, ia, nullptr, nullptr, nullptr, nullptr));
-            if (st != TDSE_OK) return st;
-            st = launch_adj<T>(h, 1, make_adj_args<T>(h, ia, rb, ib, Rn, Ih, gv));
-            if (st != TDSE_OK) return st;
+            tdse_status st;
+            if (af.ok) {
+                st = launch_adj_fused<T>(h, af, rb, ia, rc, ib, Rn, Ih, gv);
+                if (st != TDSE_OK) return st;
+                std::swap(rb, rc);
+            } else {
+                st = launch_adj<T>(h, 0, make_adj_args<T>(h, rb, ia, nullptr, nullptr, nullptr, nullptr));
+                if (st != TDSE_OK) return st;
+                st = launch_adj<T>(h, 1, make_adj_args<T>(h, ia, rb, ib, Rn, Ih, gv));
+                if (st != TDSE_OK) return st;
+            }
             std::swap(ia, ib);
             st = inject(m, sg(m - s0, 0), sg(m - s0, 1));
             if (st != TDSE_OK) return st;

@@ -193,3 +193,16 @@ def test_full_adjoint_workload_fp32_against_fp64():
             fd = (lp - lm) / (2 * hh)
             say("pos", a, c, g64[0][a, c], fd)
             assert g64[0][a, c] == pytest.approx(fd, rel=1e-4, abs=1e-6 * np.max(np.abs(g64[0])))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_one_pass_reverse_step_equals_the_two_phase_form(prec):
+    """The one-pass reverse step (with the one-pass forward) and the two
+    phase kernels (two-pass forward) form the same products in the same
+    order: identical gradients."""
+    p = small_problem(seed=3)
+    say("one-pass vs two-phase adjoint", prec)
+    a, _ = gpu_adjoint(p, prec, pingpong=True)
+    b, _ = gpu_adjoint(p, prec, pingpong=False)
+    for x, y, name in zip(a, b, ("dL/dV", "dL/dR0", "dL/dI0")):
+        assert np.array_equal(x, y), name

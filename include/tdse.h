@@ -437,14 +437,14 @@ tdse_status tdse_hbm_probe(int32_t kind, void* const* bufs, int64_t n, int32_t g
  * the one-pass kernel (which still takes single steps: a step whose level
  * is recorded first, an odd last step, the level before an adjoint
  * checkpoint).  two_step_tx = interior tile width (a multiple of the vector
- * width, >= 8), two_step_threads = threads per workgroup (256 or 512),
+ * width, >= 8), two_step_threads = threads per workgroup (256, 512 or 1024),
  * two_step_rows = rows per thread (2 or 3 with 256 threads, 1 or 2 with
- * 512), so the interior tile height is two_step_ty = (threads / ((tx + 8) /
- * vector width)) * rows - 8 (read-only); two_step_zc = z planes per
- * workgroup, two_step_prefetch != 0 loads the next plane's inputs one
- * iteration ahead.  The sweep needs at
- * most ny tiles per plane and its LDS ((2 x 4) buffers of (ty + 10) x (tx +
- * 8) values) within the device's per-workgroup limit.
+ * 512, 1 with 1024), so the interior tile height is two_step_ty = (threads
+ * / ((tx + 8) / vector width)) * rows - 8 (read-only); two_step_zc = z
+ * planes per workgroup, two_step_prefetch != 0 loads the next plane's
+ * inputs one iteration ahead.  The sweep needs at most ny tiles per plane
+ * and its LDS ((2 x 4) buffers of (ty + 10) x (tx + 8) values, plus 8 bytes
+ * per thread) within the device's per-workgroup limit.
  *
  * tdse_create picks defaults; tdse_set_tile checks and replaces them.  The
  * last five fields are read-only. */

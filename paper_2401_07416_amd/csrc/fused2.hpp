@@ -5,26 +5,27 @@
 // step moves 20 B per step.  The intermediate level (I^{n+1/2}, R^{n+1})
 // never leaves the chip.
 //
-// Mapping.  A workgroup (NT = 256 or 512 threads) owns an interior tile of
-// tx x ty cells of every plane of a z chunk, and works on the tile extended
-// by four cells on each
-// side in x and y (ex = tx + 8, ey = ty + 8): each of the four half-steps
-// needs its input one cell further out than its output, so the region on
-// which a phase result is exact shrinks by one cell per phase, from the
-// whole extension for the loaded R^n to the interior for R^{n+2}.  Results
-// on the shrinking rim are computed and discarded.
+// Mapping.  A workgroup (NT = 256, 512 or 1024 threads) owns an interior
+// tile of tx x ty cells of every plane of a z chunk, and works on the tile
+// extended by four cells on each side in x and y (ex = tx + 8, ey = ty + 8,
+// ey = M rows per thread x the rows one pass of NT threads covers): each of
+// the four half-steps needs its input one cell further out than its output,
+// so the region on which a phase result is exact shrinks by one cell per
+// phase, from the whole extension for the loaded R^n to the interior for
+// R^{n+2}.  Results on the shrinking rim are computed and discarded.
 //
 // Per iteration k of the z march the four phases run one plane apart:
 //   A1  I^{n+1/2}(k+3)  from R^n(k+2..k+4)
 //   B1  R^{n+1}(k+2)    from I^{n+1/2}(k+1..k+3)
 //   A2  I^{n+3/2}(k+1)  from R^{n+1}(k..k+2)
 //   B2  R^{n+2}(k)      from I^{n+3/2}(k-1..k+1)
-// Each thread keeps the three-plane z windows of the four fields and four
-// planes of V in registers (its W-wide x vectors of M extended rows).  The x
-// and y neighbours of each phase's centre plane come from LDS, where the
-// previous iteration left them: every phase reads the LDS buffers of parity
-// k and writes those of parity k + 1, so one barrier per iteration orders
-// all reads and writes.  The march starts six planes before the chunk so
+// Each thread keeps the z windows of the four fields (the new plane of each
+// plus the two below it that the next phases read) and four planes of V in
+// registers (its W-wide x vectors of M extended rows).  The x and y
+// neighbours of each phase's centre plane come from LDS, where the previous
+// iteration left them: every phase reads the LDS buffers of parity k and
+// writes those of parity k + 1, so one barrier per iteration orders all
+// reads and writes.  The march starts six planes before the chunk so
 // that every stored plane is exact.
 //
 // The cell arithmetic is lap7 / update_I / update_R of kernels.hpp, so the

@@ -1,5 +1,5 @@
 // Two-step (temporally blocked) sweep kernel instances for double state:
-// (rows per thread, threads per workgroup) in {(2, 256), (3, 256), (1, 512), (2, 512)}.
+// (rows per thread, threads per workgroup) in {(2, 256), (3, 256), (1, 512), (2, 512), (1, 1024)}.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -37,6 +37,7 @@ hipError_t go2_m(int m, int nt, bool rec, bool pf, dim3 grid, size_t lds, hipStr
     if (m == 3 && nt == 256) return go2<W, 3, 256>(rec, pf, grid, lds, st, a, e0, e1);
     if (m == 1 && nt == 512) return go2<W, 1, 512>(rec, pf, grid, lds, st, a, e0, e1);
     if (m == 2 && nt == 512) return go2<W, 2, 512>(rec, pf, grid, lds, st, a, e0, e1);
+    if (m == 1 && nt == 1024) return go2<W, 1, 1024>(rec, pf, grid, lds, st, a, e0, e1);
     return hipErrorInvalidValue;
 }
 
@@ -59,6 +60,7 @@ hipError_t gob2_m(int m, int nt, bool rec, bool pf, dim3 grid, size_t lds, hipSt
     if (m == 3 && nt == 256) return gob2<W, 3, 256>(rec, pf, grid, lds, st, b);
     if (m == 1 && nt == 512) return gob2<W, 1, 512>(rec, pf, grid, lds, st, b);
     if (m == 2 && nt == 512) return gob2<W, 2, 512>(rec, pf, grid, lds, st, b);
+    if (m == 1 && nt == 1024) return gob2<W, 1, 1024>(rec, pf, grid, lds, st, b);
     return hipErrorInvalidValue;
 }
 
@@ -81,6 +83,7 @@ hipError_t allow2_m(int m, int nt, size_t lds) {
     if (m == 3 && nt == 256) return allow2<W, 3, 256>(lds);
     if (m == 1 && nt == 512) return allow2<W, 1, 512>(lds);
     if (m == 2 && nt == 512) return allow2<W, 2, 512>(lds);
+    if (m == 1 && nt == 1024) return allow2<W, 1, 1024>(lds);
     return hipErrorInvalidValue;
 }
 

@@ -481,7 +481,7 @@ tdse_status launch_fused(tdse_ctx* h, const FusedDims& f, bool rec, long rec_idx
 
 // Geometry of the two-step sweep for interior tile width tx, rows per
 // thread m, z chunk zc and nt threads per workgroup; the supported
-// (m, nt) are (2, 256), (3, 256), (1, 512) and (2, 512).
+// (m, nt) are (2, 256), (3, 256), (1, 512), (2, 512) and (1, 1024).
 struct Fused2Dims {
     int W, tx, ty, ex, ey, tpr, rpp, ntx, nty, ntiles, nzc, nwg, nt;
     size_t lds;
@@ -496,7 +496,8 @@ Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc, int nt) {
     const int wl32[3] = {4, 2, 1}, wl64[2] = {2, 1};
     const int* wl = es == 8 ? wl64 : wl32;
     const int nw = es == 8 ? 2 : 3;
-    const bool pair_ok = (nt == 256 && (m == 2 || m == 3)) || (nt == 512 && (m == 1 || m == 2));
+    const bool pair_ok = (nt == 256 && (m == 2 || m == 3)) || (nt == 512 && (m == 1 || m == 2)) ||
+                         (nt == 1024 && m == 1);
     if (tx < 8 || !pair_ok || zc < 1) return f;
     f.nt = nt;
     f.W = 0;
@@ -919,7 +920,7 @@ void default_two_step(tdse_ctx* h) {
         int tx, m, nt;
     };
     const Cand c32[5] = {{64, 1, 512}, {64, 2, 256}, {56, 2, 256}, {32, 1, 512}, {24, 2, 256}};
-    const Cand c64[6] = {{56, 2, 512}, {64, 2, 512}, {32, 1, 512}, {32, 2, 256}, {24, 2, 256},
+    const Cand c64[6] = {{64, 1, 1024}, {32, 1, 1024}, {56, 2, 512}, {32, 1, 512}, {32, 2, 256},
                          {16, 2, 256}};
     const Cand* cl = f64 ? c64 : c32;
     const int nc = f64 ? 6 : 5;
@@ -2029,8 +2030,8 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
             return fail(h, TDSE_ERR_UNSUPPORTED, "one-pass tile does not fit this grid");
     }
     if (t->two_step_zc < 1) return fail(h, TDSE_ERR_ARG, "z chunks must be >= 1");
-    if (t->two_step_threads != 256 && t->two_step_threads != 512)
-        return fail(h, TDSE_ERR_ARG, "two_step_threads must be 256 or 512");
+    if (t->two_step_threads != 256 && t->two_step_threads != 512 && t->two_step_threads != 1024)
+        return fail(h, TDSE_ERR_ARG, "two_step_threads must be 256, 512 or 1024");
     const int t2zc = (int)std::min<int64_t>(t->two_step_zc, h->d.nz);
     if (t->two_step) {
         if (!t->fused) return fail(h, TDSE_ERR_ARG, "the two-step sweep runs with the one-pass step");
@@ -2322,7 +2323,7 @@ tdse_status tdse_batch_set_two_step(tdse_batch b, int32_t enable, int32_t tx, in
                                     int32_t zc, int32_t prefetch, int32_t threads) {
     if (!b) return TDSE_ERR_ARG;
     const bool pair_ok = (threads == 256 && (rows == 2 || rows == 3)) ||
-                         (threads == 512 && (rows == 1 || rows == 2));
+                         (threads == 512 && (rows == 1 || rows == 2)) || (threads == 1024 && rows == 1);
     if (tx < 8 || zc < 1 || !pair_ok) return bfail(b, TDSE_ERR_ARG, "two-step tile");
     batch_free_device(b);
     b->two = enable != 0;

@@ -89,19 +89,32 @@ def autotune(sim, steps: int = 20, reps: int = 3, cands=None):
 
 
 def autotune_batch(batch, intervals: int = 2, cands=None):
-    """Time one-pass tiles on a batch (the members advance; use a scratch
-    batch).  Each candidate is (fused_rows, fused_zc, prefetch); returns
-    [(ms_per_step, tile)] sorted, and leaves the batch prepared with the best."""
+    """Time batch tiles (the members advance; use a scratch batch).  A
+    candidate is ("one-pass", fused_rows, fused_zc, prefetch, threads) or
+    ("two-step", tx, rows, zc, threads); returns [(ms_per_step, candidate)]
+    sorted, and leaves the batch prepared with the best."""
     import torch
 
     from .tdse import TdseError
+
+    def apply(c):
+        if c[0] == "two-step":
+            _, tx, rows, zc, threads = c
+            batch.set_two_step(True, tx=tx, zc=zc, prefetch=True, rows=rows, threads=threads)
+        else:
+            _, m, zc, pf, ft = c
+            batch.set_two_step(False)
+            batch.set_tile(m, zc, pf, ft)
+
+    if cands is None:
+        cands = [("two-step", tx, rows, zc, nt) for tx in (32, 56, 64)
+                 for rows, nt in ((1, 512), (2, 256), (1, 1024)) for zc in (32, 64)]
+        cands += [("one-pass", m, zc, 0, 256) for m in (2, 3) for zc in (16, 32, 64)]
     res = []
-    step = batch.members[0].detect().step
     interval = None
-    for tile in (cands or [(m, zc, 0, ft) for ft in (256, 128, 64) for m in (2, 3, 4)
-                           for zc in (16, 32, 64)]):
+    for c in cands:
         try:
-            batch.set_tile(*tile)
+            apply(c)
             batch.prepare()
         except TdseError:
             continue
@@ -114,10 +127,9 @@ def autotune_batch(batch, intervals: int = 2, cands=None):
         batch.run(intervals * interval)
         e1.record(batch.stream)
         e1.synchronize()
-        step += intervals * interval
-        res.append((e0.elapsed_time(e1) / (intervals * interval), tile))
+        res.append((e0.elapsed_time(e1) / (intervals * interval), c))
     res.sort()
     if res:
-        batch.set_tile(*res[0][1])
+        apply(res[0][1])
         batch.prepare()
     return res

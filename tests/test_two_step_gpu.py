@@ -31,7 +31,8 @@ def two(tx, rows, zc, pf=0, threads=256):
 
 
 TILES2 = [two(56, 2, 64), two(24, 2, 16, 1), two(8, 3, 7), two(120, 3, 33, 1),
-          two(64, 1, 64, 1, 512), two(24, 2, 32, 1, 512), two(8, 1, 9, 0, 512)]
+          two(64, 1, 64, 1, 512), two(24, 2, 32, 1, 512), two(8, 1, 9, 0, 512),
+          two(64, 1, 32, 1, 1024), two(16, 1, 11, 0, 1024)]
 
 
 def same_run(a, b):

@@ -236,10 +236,42 @@ def secondary_paper(steps=400):
     ms = time_steps(sim, steps)
     v = w.cells * steps / (ms * 1e-3) / 1e9
     k620_s_per_step = 0.16
-    return {"workload": w.name + " FP32", "value": round(v, 2), "unit": "Gcell-steps/s",
-            "ms_per_step": round(ms / steps, 4), "steps": steps,
-            "paper_k620_s_per_step": k620_s_per_step,
-            "speedup_over_paper_gpu": round(k620_s_per_step / (ms / steps * 1e-3), 1)}
+    out = {"workload": w.name + " FP32", "value": round(v, 2), "unit": "Gcell-steps/s",
+           "ms_per_step": round(ms / steps, 4), "steps": steps,
+           "paper_k620_s_per_step": k620_s_per_step,
+           "speedup_over_paper_gpu": round(k620_s_per_step / (ms / steps * 1e-3), 1)}
+    out["paper_design"] = paper_design(sim, w, v)
+    return out
+
+
+def paper_design(sim, w, ours, steps=100):
+    """The section 2.2 design on this device (z-fastest arrays, eq. (12)
+    blocks, one launch per half-step, no LDS), for the block shapes of the
+    paper's Table 1: Gcell-steps/s and the HBM rate at its algorithmic 32 B
+    per FP32 cell-step (each half-step reads S, V, U and writes U)."""
+    import torch
+    R = sim.psi_r.permute(2, 1, 0).contiguous()
+    I = sim.psi_i.permute(2, 1, 0).contiguous()
+    V = sim.v.permute(2, 1, 0).contiguous()
+    res = {}
+    for block in ((16, 4, 2), (16, 4, 4), (16, 8, 4), (16, 8, 8), (64, 4, 1), (64, 1, 4)):
+        sim.paper_layout_run(R, I, V, 10, block)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        sim.paper_layout_run(R, I, V, steps, block)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        g = w.cells * steps / (ms * 1e-3) / 1e9
+        res["x".join(map(str, block))] = {"gcell_steps_s": round(g, 2),
+                                          "ms_per_step": round(ms / steps, 4),
+                                          "hbm_gbs_alg": round(g * 32, 1)}
+    best = max(res, key=lambda k: res[k]["gcell_steps_s"])
+    return {"blocks": res, "best_block": best,
+            "library_over_paper_design": round(ours / res[best]["gcell_steps_s"], 2),
+            "library_over_paper_block_16x4x4": round(ours / res["16x4x4"]["gcell_steps_s"], 2)}
 
 
 def secondary_adjoint():

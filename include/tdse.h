@@ -469,6 +469,25 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out);
 tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile* out);
 tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t);
 
+/* The GPU design of section 2.2 as a baseline: n leapfrog steps (eq. (9),
+ * then eq. (8), each a launch that updates its array in place) on arrays
+ * stored z fastest and x slowest, [nx][ny][nz], with one thread per grid
+ * point in blocks of bx x by x bz points (bx along z, by along x, bz along
+ * y) laid out on a two-dimensional grid by eq. (12), every neighbour read
+ * from global memory and periodic neighbours taken modulo N (eqs.
+ * (13)-(14)).  Grid, boundaries, coefficients and CAP tables are the
+ * handle's (tdse_finalize_setup first); psi_r, psi_i and v are device
+ * arrays of the handle's precision owned by the caller, distinct from each
+ * other; psi_r and psi_i are overwritten.  The cell arithmetic is the
+ * library's, so the result is bitwise the transpose of n tdse_step steps
+ * from the transposed state.  No records, sums or step count: the handle's
+ * own state is not touched.  Asynchronous on the handle's stream.
+ * TDSE_ERR_ARG for null or aliased arrays, n < 0 or a block of more than
+ * 1024 threads; TDSE_ERR_STATE before finalize; TDSE_ERR_UNSUPPORTED when
+ * the block grid exceeds the device's grid dimensions. */
+tdse_status tdse_paper_layout_run(tdse_handle h, void* psi_r, void* psi_i, const void* v, int64_t n,
+                                  int32_t bx, int32_t by, int32_t bz);
+
 #ifdef __cplusplus
 }
 #endif

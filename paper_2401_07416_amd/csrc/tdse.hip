@@ -22,6 +22,7 @@
 #include "fused2.hpp"
 #include "adjoint.hpp"
 #include "adjoint_fused.hpp"
+#include "paper_layout.hpp"
 
 using namespace tdse;
 
@@ -1985,6 +1986,60 @@ tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count) {
     return TDSE_OK;
 }
 
+tdse_status tdse_paper_layout_run(tdse_handle h, void* psi_r, void* psi_i, const void* v, int64_t n,
+                                  int32_t bx, int32_t by, int32_t bz) {
+    if (!h || !psi_r || !psi_i || !v || n < 0) return TDSE_ERR_ARG;
+    if (!h->finalized) return fail(h, TDSE_ERR_STATE, "finalize_setup before paper_layout_run");
+    if (bx < 1 || by < 1 || bz < 1 || (long)bx * by * bz > 1024)
+        return fail(h, TDSE_ERR_ARG, "block Bx x By x Bz must hold 1..1024 threads");
+    if (psi_r == psi_i || psi_r == v || psi_i == v)
+        return fail(h, TDSE_ERR_ARG, "psi_r, psi_i and v must be distinct");
+    const tdse_desc& d = h->d;
+    const long nyb = (d.ny + bz - 1) / bz;
+    const long gy = ((long)d.nx * nyb + by - 1) / by;
+    const long gx = (d.nz + bx - 1) / bx;
+    int maxy = 0, maxx = 0;
+    HIPCHK(h, hipDeviceGetAttribute(&maxy, hipDeviceAttributeMaxGridDimY, h->device));
+    HIPCHK(h, hipDeviceGetAttribute(&maxx, hipDeviceAttributeMaxGridDimX, h->device));
+    if (gy > maxy || gx > maxx)
+        return fail(h, TDSE_ERR_UNSUPPORTED, "grid of blocks exceeds the device's grid dimensions");
+    const dim3 grid((unsigned)gx, (unsigned)gy), block((unsigned)bx, (unsigned)by, (unsigned)bz);
+    auto run = [&](auto* tag) -> tdse_status {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        tdse::ZArgs<T> a;
+        a.V = static_cast<const T*>(v);
+        a.ca = static_cast<const T*>(h->ca);
+        a.cb = static_cast<const T*>(h->cb);
+        a.cx = (T)h->c[0];
+        a.cy = (T)h->c[1];
+        a.cz = (T)h->c[2];
+        a.cv = (T)h->c[3];
+        a.nx = (int)d.nx;
+        a.ny = (int)d.ny;
+        a.nz = (int)d.nz;
+        a.bcx = d.bc[0] == TDSE_BC_ZERO;
+        a.bcy = d.bc[1] == TDSE_BC_ZERO;
+        a.bcz = d.bc[2] == TDSE_BC_ZERO;
+        a.nyb = (int)nyb;
+        for (int64_t s = 0; s < n; ++s) {
+            for (int half = 0; half < 2; ++half) {
+                const bool is_r = half == 1;   // eq. (9), then eq. (8)
+                a.U = static_cast<T*>(is_r ? psi_r : psi_i);
+                a.S = static_cast<const T*>(is_r ? psi_i : psi_r);
+                hipError_t e;
+                if constexpr (sizeof(T) == 8)
+                    e = tdse::launch_zfast_f64(is_r, grid, block, h->stream, a);
+                else
+                    e = tdse::launch_zfast_f32(is_r, grid, block, h->stream, a);
+                HIPCHK(h, e);
+            }
+        }
+        return TDSE_OK;
+    };
+    if (d.precision == TDSE_F64) return run((double*)nullptr);
+    return run((float*)nullptr);
+}
+
 tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
     if (!h || !out) return TDSE_ERR_ARG;
     out->rows = h->rows;
@@ -2035,6 +2090,11 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
     const int t2zc = (int)std::min<int64_t>(t->two_step_zc, h->d.nz);
     if (t->two_step) {
         if (!t->fused) return fail(h, TDSE_ERR_ARG, "the two-step sweep runs with the one-pass step");
+        const int pm = t->two_step_rows, pt = t->two_step_threads;
+        if (!((pt == 256 && (pm == 2 || pm == 3)) || (pt == 512 && (pm == 1 || pm == 2)) ||
+              (pt == 1024 && pm == 1)))
+            return fail(h, TDSE_ERR_UNSUPPORTED,
+                        "two-step (rows, threads) must be (2,256), (3,256), (1,512), (2,512) or (1,1024)");
         if (!fused2_dims(h, t->two_step_tx, t->two_step_rows, t2zc, t->two_step_threads).ok)
             return fail(h, TDSE_ERR_UNSUPPORTED, "two-step tile does not fit this grid");
     }

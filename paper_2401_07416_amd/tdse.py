@@ -36,7 +36,7 @@ EXPORTS = [
     "tdse_batch_prepare", "tdse_batch_run", "tdse_batch_status", "tdse_batch_last_error",
     "tdse_batch_destroy", "tdse_hbm_probe", "tdse_interpolate_potential",
     "tdse_dissimilarity_workspace_size", "tdse_dissimilarity", "tdse_set_cap_paper",
-    "tdse_time_step_paper", "tdse_batch_set_two_step", "tdse_autotune",
+    "tdse_time_step_paper", "tdse_batch_set_two_step", "tdse_autotune", "tdse_paper_layout_run",
 ]
 
 
@@ -95,13 +95,20 @@ _lib = None
 
 
 def load():
-    """Load libtdse.so (raises if it has not been built)."""
+    """Load libtdse.so (raises if it has not been built).
+
+    torch is imported first: the PyTorch wheel carries its own HIP runtime,
+    and the library must resolve its HIP symbols to that one, the runtime
+    that owns the device memory and streams it is handed.  Loaded before
+    torch, the library would pull in a second HIP runtime whose calls fail
+    in a process where torch has initialised the device."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_2401_07416_amd.build` (no CPU fallback exists)")
+    import torch  # noqa: F401  (one HIP runtime per process, torch's)
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     dp = ctypes.POINTER(ctypes.c_double)
@@ -146,6 +153,7 @@ def load():
         "tdse_get_tile": (i32, [vp, ctypes.POINTER(Tile)]),
         "tdse_set_tile": (i32, [vp, ctypes.POINTER(Tile)]),
         "tdse_autotune": (i32, [vp, i32, i32, ctypes.POINTER(Tile)]),
+        "tdse_paper_layout_run": (i32, [vp, vp, vp, vp, i64, i32, i32, i32]),
         "tdse_hbm_probe": (i32, [i32, ctypes.POINTER(vp), i64, i32, i32, vp, dp]),
         "tdse_interpolate_potential": (i32, [vp, vp, i32, i32, i32, dp, dp]),
         "tdse_set_cap_paper": (i32, [vp, ctypes.c_double, ctypes.c_double]),
@@ -428,6 +436,19 @@ class Sim:
         t = Tile()
         self._check(self.lib.tdse_autotune(self.h, int(steps), int(flags), ctypes.byref(t)))
         return t
+
+    def paper_layout_run(self, psi_r, psi_i, v, n: int, block=(16, 4, 4)):
+        """n steps of the section 2.2 design on z-fastest arrays [nx][ny][nz]
+        (this handle's grid, coefficients and CAP; its own state untouched);
+        block = (Bx, By, Bz) with Bx along z."""
+        for a in (psi_r, psi_i, v):
+            if (a.dtype != self.dtype or a.device != self.psi_r.device or not a.is_contiguous()
+                    or tuple(a.shape) != (self.desc.nx, self.desc.ny, self.desc.nz)):
+                raise ValueError("arrays must be contiguous [nx][ny][nz] of the handle's dtype "
+                                 "and device")
+        bx, by, bz = (int(b) for b in block)
+        self._check(self.lib.tdse_paper_layout_run(self.h, psi_r.data_ptr(), psi_i.data_ptr(),
+                                                   v.data_ptr(), int(n), bx, by, bz))
 
     def get_tile(self) -> Tile:
         t = Tile()

@@ -1,6 +1,7 @@
 """Host-side tests of the C ABI (no GPU): the library loads, exports every
 symbol include/tdse.h declares, and its host-only calls (description
 checks, the Gershgorin time-step bound, workspace sizing) behave."""
+import ast
 import ctypes
 import os
 import re
@@ -27,6 +28,20 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert sorted(tdse.EXPORTS) == names
+
+
+def test_binding_leaves_one_hip_runtime_in_the_process():
+    """The binding loads the library after torch, so its HIP symbols bind to
+    the runtime that owns torch's device memory (a second runtime in the
+    process fails its first device call)."""
+    import subprocess
+    import sys
+    code = ("from paper_2401_07416_amd import tdse; tdse.load(); "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300, check=True).stdout
+    libs = ast.literal_eval(out.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
 
 
 def test_abi_version_and_status_strings():

@@ -174,7 +174,8 @@ def test_paper_literal_setup_matches_oracle(prec):
     w = workloads.paper_cu111(reduced=True)
     say("paper-literal reduced", prec)
     ref = H.oracle_run(w, w.steps)
-    for tile in (None, dict(fused=1, two_step=1, two_step_tx=8, two_step_rows=2, two_step_zc=32)):
+    for tile in (None, dict(fused=1, two_step=1, two_step_tx=8, two_step_rows=2, two_step_zc=32,
+                            two_step_threads=256)):
         gpu = H.gpu_run(w, w.steps, precision=prec, tile=tile)
         assert gpu.dt == pytest.approx(oracle.dt_paper(H.oracle_grid(w)), rel=1e-15)
         tol = (dict(tol_state=1e-11, tol_rec=1e-11, tol_scal=1e-12, tol_flux=1e-12) if prec == "f64"

@@ -232,6 +232,9 @@ def secondary_paper(steps=400):
     from paper_2401_07416_amd import tdse, tuning, workloads
     w = workloads.paper_cu111()
     sim = tdse.sim_from_workload(w, precision="f32", steps=steps + 20)
+    t = tuning.tile_for(w, "f32")
+    if t:
+        sim.set_tile(**t)
     sim.step(20)
     ms = time_steps(sim, steps)
     v = w.cells * steps / (ms * 1e-3) / 1e9

@@ -411,7 +411,9 @@ tdse_status tdse_dissimilarity(int32_t precision, const void* frames, int32_t K,
  * and two written streams bufs[3..4] (d = a + b c, e = b - a c, elementwise).
  * Each buffer is n floats (n a multiple of 4) of device memory, 16-byte
  * aligned, all distinct, owned by the caller; the written buffers are
- * overwritten.  grid = workgroups of 256 threads (0: 4096).  Runs one warm-up
+ * overwritten.  All accesses carry the non-temporal hint.  grid = workgroups
+ * of 256 threads in a grid-stride loop (0: one 16-byte vector per thread,
+ * the fastest form measured).  Runs one warm-up
  * pass and reps timed passes on stream (a hipStream_t, may be null),
  * synchronises it and returns the average milliseconds per pass in
  * *ms_per_pass.  TDSE_ERR_ARG for bad arguments, TDSE_ERR_DEVICE for HIP

@@ -45,6 +45,7 @@ struct FusedArgs {
     double* part_plane;    // [nbands]
     double* pixel;
     double pixel_w;
+    int nt_out;           // non-temporal hint on the R^{n+1}, I^{n+1/2} stores
 };
 
 // PF: issue the loads of the next plane (R three planes ahead, I^{n-1/2}
@@ -195,7 +196,7 @@ __device__ __forceinline__ void fused_step_body(const FusedArgs<T>& a, int L,
                     out.v[e] = zero ? T(0) : update_I(lap, vv[i].v[e], c, io[i].v[e], a.cv, cap, cbp);
                 }
                 *reinterpret_cast<VT*>(li_row(buf, b) + x0) = out;
-                if (store) bstore<T, W>(prs(a.I1, gp), voffB[i], out);
+                if (store) bstore_out<T, W>(prs(a.I1, gp), voffB[i], out, a.nt_out);
             } else {
 #pragma unroll
                 for (int e = 0; e < W; ++e) out.v[e] = T(0);
@@ -289,7 +290,7 @@ __device__ __forceinline__ void fused_step_body(const FusedArgs<T>& a, int L,
                     nv += dn * dn + dc * dc;
                 }
             }
-            bstore<T, W>(prs(a.R1, k), voffB[i], out);
+            bstore_out<T, W>(prs(a.R1, k), voffB[i], out, a.nt_out);
             if (REC && at_det) {
                 VT rv;
                 const long poff = (long)rowj[i] * nx + x0;

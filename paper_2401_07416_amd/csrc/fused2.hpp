@@ -65,6 +65,7 @@ struct Fused2Args {
     double* part_plane;   // [ntiles]
     double* pixel;
     double pixel_w;
+    int nt_out;           // non-temporal hint on the R^{n+2}, I^{n+3/2} stores
 };
 
 template <typename T, int W, int M, bool REC, bool PF, int NT>
@@ -243,12 +244,12 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
         if (pC >= k0 && pC < k1) {
             const auto rI = prs(a.I1, pC);
 #pragma unroll
-            for (int i = 0; i < M; ++i) bstore<T, W>(rI, soff[i], nC[i]);
+            for (int i = 0; i < M; ++i) bstore_out<T, W>(rI, soff[i], nC[i], a.nt_out);
         }
         if (pD >= k0) {
             const auto rR = prs(a.R1, pD);
 #pragma unroll
-            for (int i = 0; i < M; ++i) bstore<T, W>(rR, soff[i], nD[i]);
+            for (int i = 0; i < M; ++i) bstore_out<T, W>(rR, soff[i], nD[i], a.nt_out);
         }
         // flux partials of both steps over the stored cells
         const bool inB = pB >= k0 && pB < k1;

@@ -115,18 +115,34 @@ __device__ __forceinline__ vec_t<T, W> bload(__amdgpu_buffer_rsrc_t r, int off) 
     }
 }
 
-template <typename T, int W>
+// AUX is the cache-policy immediate: 0, or CPOL_NT, the non-temporal hint
+// of gfx950 (bit 1).
+constexpr int CPOL_NT = 2;
+
+template <typename T, int W, int AUX = 0>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, const vec_t<T, W>& v) {
     constexpr int B = (int)sizeof(T) * W;
     if constexpr (B == 16) {
         using U = __attribute__((ext_vector_type(4))) unsigned int;
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, off, 0, AUX);
     } else if constexpr (B == 8) {
         using U = __attribute__((ext_vector_type(2))) unsigned int;
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, off, 0, AUX);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, AUX);
     }
+}
+
+// Store of a result that no other workgroup of the launch reads: with nt
+// set (grids whose arrays are far larger than the 256 MB memory-side cache)
+// it carries the non-temporal hint, so the written lines do not displace
+// inputs that neighbouring tiles are still to re-read.
+template <typename T, int W>
+__device__ __forceinline__ void bstore_out(__amdgpu_buffer_rsrc_t r, int off, const vec_t<T, W>& v, bool nt) {
+    if (nt)
+        bstore<T, W, CPOL_NT>(r, off, v);
+    else
+        bstore<T, W>(r, off, v);
 }
 
 // Load of a read-only table entry at a wave-uniform index through the

@@ -148,6 +148,18 @@ tdse_status hip_check(tdse_ctx* h, hipError_t e, const char* what) {
         if (s_ != TDSE_OK) return s_;                             \
     } while (0)
 
+// Step outputs carry the non-temporal hint when the five state-sized arrays
+// a step touches exceed the 256 MB memory-side cache (MALL): they are
+// evicted before the next step reads them in any case, and without the
+// hint they displace input lines that neighbouring tiles re-read.
+constexpr size_t MALL_BYTES = (size_t)256 << 20;
+
+bool stream_outputs(size_t state_bytes_total) { return 5 * state_bytes_total > MALL_BYTES; }
+
+size_t state_bytes(const tdse_desc& d) {
+    return (size_t)d.nx * d.ny * d.nz * (d.precision == TDSE_F64 ? 8 : 4);
+}
+
 struct Layout {
     size_t ca, cb, acc, flux, part_q, part_n, part_p, red, gfac, total;
     int F;
@@ -461,6 +473,7 @@ FusedArgs<T> make_fused_args(tdse_ctx* h, const FusedDims& f, bool rec, long rec
     a.part_plane = h->part_plane;
     a.pixel = (rec && (d.flags & TDSE_FLAG_PIXEL_INTEGRAL)) ? h->pix : nullptr;
     a.pixel_w = (double)d.record_every * h->dt;
+    a.nt_out = stream_outputs(state_bytes(d));
     return a;
 }
 
@@ -573,6 +586,7 @@ Fused2Args<T> make_fused2_args(tdse_ctx* h, const Fused2Dims& f, bool rec, long 
     a.part_plane = h->part_plane;
     a.pixel = (rec && (d.flags & TDSE_FLAG_PIXEL_INTEGRAL)) ? h->pix : nullptr;
     a.pixel_w = (double)d.record_every * h->dt;
+    a.nt_out = stream_outputs(state_bytes(d));
     return a;
 }
 
@@ -984,6 +998,13 @@ static void batch_free_device(tdse_batch_ctx* b) {
     b->prepared = false;
 }
 
+// the members run together, so their summed footprint decides the hint
+static int batch_streams(const tdse_batch_ctx* b) {
+    size_t tot = 0;
+    for (const tdse_ctx* m : b->members) tot += state_bytes(m->d);
+    return stream_outputs(tot) ? 1 : 0;
+}
+
 template <typename T>
 static hipError_t batch_enqueue_interval(tdse_batch_ctx* b) {
     const size_t n = b->members.size();
@@ -1084,6 +1105,7 @@ static tdse_status batch_prepare2_t(tdse_batch_ctx* b, bool* used) {
         h->t2pf = b->t2pf;
         h->t2t = b->t2t;
         cfg[i] = make_fused2_args<T>(h, f, b->h > 0, 0, 0);
+        cfg[i].nt_out = batch_streams(b);
         cfg[i].rec_plane = static_cast<T*>(h->rec);  // record 0; the kernel adds the counter
         lds = std::max(lds, f.lds);
         wg[i + 1] = wg[i] + f.nwg;
@@ -1167,6 +1189,7 @@ static tdse_status batch_prepare_t(tdse_batch_ctx* b) {
         if (W == 0) W = fd.W;
         if (fd.W != W) return bfail(b, TDSE_ERR_UNSUPPORTED, "members need the same vector width");
         cfg[i] = make_fused_args<T>(h, fd, b->h > 0, 0, 0);
+        cfg[i].nt_out = batch_streams(b);
         cfg[i].rec_plane = static_cast<T*>(h->rec);  // record 0; the kernel adds the counter
         lds = std::max(lds, fd.lds);
         wg[i + 1] = wg[i] + fd.nwg;

@@ -20,7 +20,7 @@
 //   A2  I^{n+3/2}(k+1)  from R^{n+1}(k..k+2)
 //   B2  R^{n+2}(k)      from I^{n+3/2}(k-1..k+1)
 // Each thread keeps the z windows of the four fields (the new plane of each
-// plus the two below it that the next phases read) and four planes of V in
+// plus the two below it that the next phases read) and four planes of cv V in
 // registers (its W-wide x vectors of M extended rows).  The x and y
 // neighbours of each phase's centre plane come from LDS, where the previous
 // iteration left them: every phase reads the LDS buffers of parity k and
@@ -150,35 +150,69 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     }
 
     // one phase on plane p: centre c, z neighbours zl / zr, x / y neighbours
-    // from LDS buffer src (the centre plane), old value uo, potential v;
+    // from LDS buffer src (the centre plane), old value uo, cv V in cvv;
     // IS_R selects eq. (8), else eq. (9).  The result goes to out and, from
-    // live threads, to LDS buffer dst (if not null).
+    // live threads, to LDS buffer dst (if not null).  A plane outside a zero
+    // z boundary is zero.  The 1024-thread workgroups (one per CU, where
+    // the VALU work is least hidden) also take two uniform shortcuts: no
+    // zero-boundary select without zero x / y boundaries (idle threads'
+    // results are never stored or read), and no CAP factors on planes
+    // without absorption (ca = cb = 1); the bits are the same.
+    const bool sel_xy = NT != 1024 || a.bcx || a.bcy;
     auto phase = [&](auto is_r, int p, const VT(&zl)[M], const VT(&c)[M], const VT(&zr)[M],
-                     const T* src, const VT(&uo)[M], const VT(&v)[M], VT(&out)[M], T* dst) {
+                     const T* src, const VT(&uo)[M], const VT(&cvv)[M], VT(&out)[M], T* dst) {
         constexpr bool IS_R = decltype(is_r)::value;
         const int gp = gplane(p);
-        const T cap = gp >= 0 ? ld_uniform(a.ca, gp) : T(1);
-        const T cbp = gp >= 0 ? ld_uniform(a.cb, gp) : T(1);
+        if (gp < 0) {
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-            const T* row = src + rowb[i] * ex + c0;
-            const VT yl = *reinterpret_cast<const VT*>(row - ex);
-            const VT yr = *reinterpret_cast<const VT*>(row + ex);
-            const T xle = row[-1], xre = row[W];
-            const bool zero = zc_cell[i] || gp < 0;
-            VT o;
-#pragma unroll
-            for (int e = 0; e < W; ++e) {
-                const T cc = c[i].v[e];
-                const T xl = e > 0 ? c[i].v[e - 1] : xle;
-                const T xr = e < W - 1 ? c[i].v[e + 1] : xre;
-                const T lap = lap7(cc, xl, xr, yl.v[e], yr.v[e], zl[i].v[e], zr[i].v[e], a.cx, a.cy, a.cz);
-                const T u = IS_R ? update_R(lap, v[i].v[e], cc, uo[i].v[e], a.cv, cap, cbp)
-                                 : update_I(lap, v[i].v[e], cc, uo[i].v[e], a.cv, cap, cbp);
-                o.v[e] = zero ? T(0) : u;
+            for (int i = 0; i < M; ++i) {
+                out[i] = zero_vec();
+                if (dst && live) *reinterpret_cast<VT*>(dst + rowb[i] * ex + c0) = out[i];
             }
-            out[i] = o;
-            if (dst && live) *reinterpret_cast<VT*>(dst + rowb[i] * ex + c0) = o;
+            return;
+        }
+        const T cap = ld_uniform(a.ca, gp);
+        const T cbp = ld_uniform(a.cb, gp);
+        auto cells = [&](auto sel, auto unit) {
+            constexpr bool SEL = decltype(sel)::value, UNIT = decltype(unit)::value;
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const T* row = src + rowb[i] * ex + c0;
+                const VT yl = *reinterpret_cast<const VT*>(row - ex);
+                const VT yr = *reinterpret_cast<const VT*>(row + ex);
+                const T xle = row[-1], xre = row[W];
+                VT o;
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    const T cc = c[i].v[e];
+                    const T xl = e > 0 ? c[i].v[e - 1] : xle;
+                    const T xr = e < W - 1 ? c[i].v[e + 1] : xre;
+                    const T lap = lap7(cc, xl, xr, yl.v[e], yr.v[e], zl[i].v[e], zr[i].v[e], a.cx, a.cy, a.cz);
+                    T u;
+                    if constexpr (UNIT)
+                        u = IS_R ? update_R_unit(lap, cvv[i].v[e], cc, uo[i].v[e])
+                                 : update_I_unit(lap, cvv[i].v[e], cc, uo[i].v[e]);
+                    else
+                        u = IS_R ? update_R_cvv(lap, cvv[i].v[e], cc, uo[i].v[e], cap, cbp)
+                                 : update_I_cvv(lap, cvv[i].v[e], cc, uo[i].v[e], cap, cbp);
+                    if constexpr (SEL)
+                        o.v[e] = zc_cell[i] ? T(0) : u;
+                    else
+                        o.v[e] = u;
+                }
+                out[i] = o;
+                if (dst && live) *reinterpret_cast<VT*>(dst + rowb[i] * ex + c0) = o;
+            }
+        };
+        using Yes = std::true_type;
+        using No = std::false_type;
+        const bool unit = NT == 1024 && cap == T(1) && cbp == T(1);
+        if (sel_xy) {
+            if (unit) cells(Yes{}, Yes{});
+            else cells(Yes{}, No{});
+        } else {
+            if (unit) cells(No{}, Yes{});
+            else cells(No{}, No{});
         }
     };
     using IsR = std::integral_constant<bool, true>;
@@ -226,6 +260,11 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
         } else {
             load3(k + 4, k + 3, Rn[2], io, Vw[3]);
         }
+        // the window keeps cv V, formed once per plane instead of per phase
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int e = 0; e < W; ++e) Vw[3][i].v[e] = a.cv * Vw[3][i].v[e];
         // stage R^n(k+4) for the next iteration's A1
         if (live) {
 #pragma unroll

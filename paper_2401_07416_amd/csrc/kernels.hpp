@@ -175,6 +175,29 @@ __device__ __forceinline__ T update_R(T lap, T v, T c, T uo, T cv, T ca, T cb) {
     return ca * uo - cb * (lap - cv * v * c);
 }
 
+// The same updates with the product cv V formed beforehand (the expressions
+// above evaluate cv * v first, so the bits agree), and their forms on
+// planes without absorption (ca = cb = 1, where 1 * x = x exactly).
+template <typename T>
+__device__ __forceinline__ T update_I_cvv(T lap, T cvv, T c, T uo, T ca, T cb) {
+    return ca * uo + cb * (lap - cvv * c);
+}
+
+template <typename T>
+__device__ __forceinline__ T update_R_cvv(T lap, T cvv, T c, T uo, T ca, T cb) {
+    return ca * uo - cb * (lap - cvv * c);
+}
+
+template <typename T>
+__device__ __forceinline__ T update_I_unit(T lap, T cvv, T c, T uo) {
+    return uo + (lap - cvv * c);
+}
+
+template <typename T>
+__device__ __forceinline__ T update_R_unit(T lap, T cvv, T c, T uo) {
+    return uo - (lap - cvv * c);
+}
+
 template <typename T, int W, int G, int RY, int MODE>
 __global__ __launch_bounds__(256) void half_step_kernel(HalfArgs<T> a) {
     using VT = vec_t<T, W>;

@@ -10,8 +10,8 @@
 // FP32 cross term.  So the contraction runs on the vector ALU, register
 // tiled like a GEMM: a workgroup owns a 64 x 64 block of pairs, each thread a
 // 4 x 4 sub-block, and pixels stream through LDS in chunks of 32; per chunk
-// the squared differences are summed in the frame precision and then added
-// to an FP64 accumulator.  Each workgroup covers a range of frames and
+// the squared differences are summed in the frame precision (fused
+// multiply-adds) and then added to an FP64 accumulator.  Each workgroup covers a range of frames and
 // writes its partial time sum; a second kernel adds the partials in a fixed
 // order, so the result is bitwise reproducible and exactly symmetric.
 #include <hip/hip_runtime.h>
@@ -43,6 +43,12 @@ struct DissimArgs {
     int tpc;              // frames per workgroup
     double* part;         // [ntc][K][K]
 };
+
+// e * e + s with one rounding (a fused multiply-add): two instructions per
+// pair and pixel with the subtraction, and a sum at least as accurate as
+// the separately rounded product and add.
+__device__ __forceinline__ float fma_of(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_of(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // pair block index -> (row block, column block), column >= row
 __device__ __forceinline__ void pair_block(int q, int nb, int* bi, int* bj) {
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
 #pragma unroll
                 for (int y = 0; y < 4; ++y) {
                     const T e = av.v[x] - bv.v[y];
-                    s[x][y] += e * e;
+                    s[x][y] = fma_of(e, e, s[x][y]);
                 }
         }
 #pragma unroll

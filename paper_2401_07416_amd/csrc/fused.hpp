@@ -314,19 +314,10 @@ __device__ __forceinline__ void fused_step_body(const FusedArgs<T>& a, int L,
     }
 
     // fixed-order workgroup sums of the partials
-    __shared__ double red[256];
+    __shared__ double red[4];
     const bool has_det = (a.k_det >= k0 && a.k_det < k1);
     const bool has_up = (a.k_up >= k0 && a.k_up < k1);
-    auto wg_sum = [&](double v) -> double {
-        __syncthreads();
-        red[tid] = v;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o && tid + o < (int)blockDim.x) red[tid] += red[tid + o];
-            __syncthreads();
-        }
-        return red[0];
-    };
+    auto wg_sum = [&](double v) -> double { return block_sum(v, red, (int)blockDim.x >> 6); };
     if (has_det) {
         const double s = wg_sum(f0);
         if (tid == 0) a.flux_slots[band] = s;

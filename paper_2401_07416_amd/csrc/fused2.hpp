@@ -364,19 +364,10 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     }
 
     // fixed-order workgroup sums of the partials
-    __shared__ double red[NT];
+    __shared__ double red[NT / 64];
     const bool has_det = a.k_det >= k0 && a.k_det < k1;
     const bool has_up = a.k_up >= k0 && a.k_up < k1;
-    auto wg_sum = [&](double v) -> double {
-        __syncthreads();
-        red[tid] = v;
-        __syncthreads();
-        for (int o = NT / 2; o > 0; o >>= 1) {
-            if (tid < o) red[tid] += red[tid + o];
-            __syncthreads();
-        }
-        return red[0];
-    };
+    auto wg_sum = [&](double v) -> double { return block_sum(v, red, NT / 64); };
     if (has_det) {
         const double sa = wg_sum(fa0);
         const double sb = wg_sum(fb0);

@@ -81,6 +81,21 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Fixed-order workgroup sum for 1D workgroups of whole wavefronts: the
+// butterfly above within each wavefront (every lane ends with the same bits,
+// since each level adds x_i + x_(i^o) and addition commutes), then the
+// wavefront totals in wavefront order.  red holds one double per
+// wavefront; every thread of the workgroup calls this and gets the sum.
+__device__ __forceinline__ double block_sum(double v, double* red, int nwaves) {
+    v = wave_sum(v);
+    __syncthreads();  // the previous call's reads of red are done
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += red[w];
+    return s;
+}
+
 template <typename T, int W>
 __device__ __forceinline__ vec_t<T, W> ldv(const T* p) {
     return *reinterpret_cast<const vec_t<T, W>*>(p);

@@ -536,8 +536,8 @@ Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc, int nt) {
     f.nwg = f.ntiles * f.nzc;
     f.lds = (size_t)8 * (f.ey + 2) * f.ex * es;
     // flux and partial slots are sized for ny per step / plane; 8 B per
-    // thread of static LDS for the reductions
-    f.ok = f.ntiles <= d.ny && f.lds + 8 * (size_t)nt <= (size_t)h->lds_max &&
+    // wavefront of static LDS for the reductions
+    f.ok = f.ntiles <= d.ny && f.lds + 8 * (size_t)(nt / 64) <= (size_t)h->lds_max &&
            (long)f.nwg < (1L << 31);
     return f;
 }

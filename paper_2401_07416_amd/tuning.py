@@ -108,7 +108,7 @@ def autotune_batch(batch, intervals: int = 2, cands=None):
 
     if cands is None:
         cands = [("two-step", tx, rows, zc, nt) for tx in (32, 56, 64)
-                 for rows, nt in ((1, 512), (2, 256), (1, 1024)) for zc in (32, 64)]
+                 for rows, nt in ((1, 512), (2, 256), (1, 1024)) for zc in (32, 64, 128)]
         cands += [("one-pass", m, zc, 0, 256) for m in (2, 3) for zc in (16, 32, 64)]
     res = []
     interval = None

@@ -4,17 +4,23 @@ MI355X: Gcell-steps/s of the whole step (both half-steps with the fused
 detection records, FP64 flux and norm sums) on the 512x512x1024 synthetic
 surface-diffraction grid, FP32 state.  Prints one JSON line.
 
-A step is one pass of the hot path over the grid: eq. (9) then eq. (8) (fused
-into one sweep over ping-pong buffers), with the flux partials, every 50
-steps the record plane with Q, naive norm and plane sums, and the
-fixed-order FP64 finalisation.  Inputs are resident in HBM before the timed region starts.
+A step is eq. (9) then eq. (8) over the whole grid, with the flux partials,
+every 50 steps the record plane with Q, naive norm and plane sums, and the
+fixed-order FP64 finalisation; the step driver runs them as two-step sweeps
+(two steps per pass over ping-pong buffers) where the grid fits one, else
+as one-pass steps or in-place half-steps.  Inputs are resident in HBM
+before the timed region starts.
 
-roofline: the dominant kernel is the one-pass step kernel (or the half-step
-kernel on the two-pass path); its algorithmic bytes per launch are 20 B per
-cell in FP32 (read R, I, V once, write R, I once; 16 B for a half-step),
-divided by its average launch time measured with HIP events around each
-launch inside the timed region.  cpu_baseline: the FP64 oracle timed on this host's cores on a
-bounded slab of the same workload.
+roofline: the dominant kernel is the launch kind that takes most of the
+timed region (the two-step sweep by default; the one-pass step or the
+half-step kernels when selected); its algorithmic bytes per launch are 20 B
+per cell in FP32 (read R, I, V once, write R, I once: two steps for the
+sweep, one for the one-pass step; 16 B for a half-step), divided by its
+average launch time measured with HIP events around each launch inside the
+timed region, on the stream the kernels run on.  traffic: calibrated
+rocprofv3 FETCH_SIZE + WRITE_SIZE per launch from profiles/, while the
+kernel sources and tile match.  cpu_baseline: the FP64 oracle timed on this
+host's cores on a bounded slab of the same workload.
 """
 from __future__ import annotations
 

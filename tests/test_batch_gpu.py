@@ -125,3 +125,31 @@ def test_batch_two_step_odd_interval_counts():
         n = m.detect().n_records
         assert bool((m.records[:n] == single.records[:n]).all())
         assert m.detect().flux == pytest.approx(single.detect().flux, rel=1e-11, abs=1e-15)
+
+
+def test_full_batch_workload_members_equal_single_runs():
+    """The 64-configuration film workload at full size (128^2 x 256 to
+    256^2 x 512, 1.04 G cells) in the library's default batch tile, two
+    record intervals: every member finishes, and the first, last, smallest
+    and largest grids are bitwise the grids run alone."""
+    ws = workloads.c4_batch(64, steps=100)
+    steps = 2 * ws[0].record_every
+    say("full batch", len(ws), "configs", sum(w.cells for w in ws), "cells", steps, "steps")
+    b = tdse.batch_from_workloads(ws, precision="f32", steps=steps)
+    b.prepare()
+    b.run(steps)
+    assert all(s == tdse.OK for s in b.status())
+    cells = [w.cells for w in ws]
+    for i in sorted({0, len(ws) - 1, int(np.argmin(cells)), int(np.argmax(cells))}):
+        w, m = ws[i], b.members[i]
+        say(" member", i, w.name)
+        single = H.gpu_run(w, steps, precision="f32")
+        assert bool((m.psi_r == single.psi_r).all()) and bool((m.psi_i == single.psi_i).all())
+        n = m.detect().n_records
+        assert n == steps // w.record_every + 1
+        assert bool((m.records[:n] == single.records[:n]).all())
+        np.testing.assert_allclose(m.scalars[:n].cpu().numpy(), single.scalars[:n].cpu().numpy(),
+                                   rtol=1e-12, atol=1e-15)
+        del single
+    del b
+    torch.cuda.empty_cache()

@@ -187,11 +187,13 @@ def test_chunked_steps_and_resume_are_exact():
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_full_surface_grid(prec):
-    """256x256x512 surface workload at full size, 50 steps (one record)."""
+    """256x256x512 surface workload at full size, 50 steps (one record), in
+    the tile the benchmark uses for this grid."""
+    from paper_2401_07416_amd import tuning
     w = workloads.c2_surface()
     say("surface 256x256x512", prec, "50 steps")
     ref = H.oracle_run(w, 50)
-    gpu = H.gpu_run(w, 50, precision=prec)
+    gpu = H.gpu_run(w, 50, precision=prec, tile=tuning.tile_for(w, prec))
     say(H.compare(gpu, ref, **(FP64 if prec == "f64" else FP32)))
 
 

@@ -386,8 +386,8 @@ def main():
         copy_probe()
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md but not implemented",
+        print(json.dumps({"error": "libtdse runs on one GPU; a sharded multi-GPU path is not "
+                                   "implemented, so only --gpus 1 is measured",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch

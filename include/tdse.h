@@ -75,7 +75,7 @@ enum {
     TDSE_ERR_NONFINITE = 4,   /* a NaN or Inf reached the FP64 sums */
     TDSE_ERR_DEVICE = 5,      /* HIP runtime error; message kept */
     TDSE_ERR_OOM = 6,         /* device allocation failed (setup temporaries) */
-    TDSE_ERR_UNSUPPORTED = 7, /* shape or option this build does not handle */
+    TDSE_ERR_UNSUPPORTED = 7, /* shape or option the library does not handle */
     TDSE_ERR_CAPACITY = 8     /* the record buffer would overflow */
 };
 

@@ -64,6 +64,7 @@ struct HalfArgs {
     double* part_plane; // [ytiles]
     double* pixel;      // [ny][nx] or null
     double pixel_w;     // h * dt
+    int nt_in;          // non-temporal hint on the U and V loads
 };
 
 // Workgroup id -> logical tile index such that the workgroups the hardware
@@ -99,6 +100,21 @@ __device__ __forceinline__ double block_sum(double v, double* red, int nwaves) {
 template <typename T, int W>
 __device__ __forceinline__ vec_t<T, W> ldv(const T* p) {
     return *reinterpret_cast<const vec_t<T, W>*>(p);
+}
+
+// Load with the non-temporal hint, for streams read once per launch.
+template <typename T, int W>
+__device__ __forceinline__ vec_t<T, W> ldv_nt(const T* p) {
+    constexpr int B = (int)sizeof(T) * W;
+    if constexpr (B == 16) {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        return __builtin_bit_cast(vec_t<T, W>, __builtin_nontemporal_load(reinterpret_cast<const u4*>(p)));
+    } else if constexpr (B == 8) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(vec_t<T, W>, __builtin_nontemporal_load(reinterpret_cast<const u2*>(p)));
+    } else {
+        return __builtin_bit_cast(vec_t<T, W>, __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p)));
+    }
 }
 
 template <typename T, int W>
@@ -262,6 +278,18 @@ __global__ __launch_bounds__(256) void half_step_kernel(HalfArgs<T> a) {
 #pragma unroll
         for (int g = 0; g < G; ++g) out[g] = ldv<T, W>(p + (long)g * a.nl * W);
     };
+    // U and V are read once per launch (no neighbour reads them): with nt_in
+    // (grids far beyond the memory-side cache) they stream past it
+    auto load_own = [&](const T* base, int jj, int kk, VT(&out)[G]) {
+        const T* p = base + (long)kk * plane + (long)jj * nx + (long)lc * W;
+        if (a.nt_in) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) out[g] = ldv_nt<T, W>(p + (long)g * a.nl * W);
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; ++g) out[g] = ldv<T, W>(p + (long)g * a.nl * W);
+        }
+    };
 
     VT sp[RY][G], sc[RY][G], sn[RY][G];
 #pragma unroll
@@ -285,8 +313,8 @@ __global__ __launch_bounds__(256) void half_step_kernel(HalfArgs<T> a) {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             if (real[r]) {
-                load_row(a.U, jrow[r], k, u[r]);
-                load_row(a.V, jrow[r], k, vv[r]);
+                load_own(a.U, jrow[r], k, u[r]);
+                load_own(a.V, jrow[r], k, vv[r]);
             }
         }
         const T cak = ld_uniform(a.ca, k);

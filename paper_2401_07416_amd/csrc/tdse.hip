@@ -148,10 +148,11 @@ tdse_status hip_check(tdse_ctx* h, hipError_t e, const char* what) {
         if (s_ != TDSE_OK) return s_;                             \
     } while (0)
 
-// Step outputs carry the non-temporal hint when the five state-sized arrays
-// a step touches exceed the 256 MB memory-side cache (MALL): they are
-// evicted before the next step reads them in any case, and without the
-// hint they displace input lines that neighbouring tiles re-read.
+// Step outputs (and the half-step's own-cell inputs) carry the
+// non-temporal hint when the five state-sized arrays a step touches exceed
+// the 256 MB memory-side cache (MALL): they are evicted before the next
+// step reads them in any case, and without the hint they displace input
+// lines that neighbouring tiles re-read.
 constexpr size_t MALL_BYTES = (size_t)256 << 20;
 
 bool stream_outputs(size_t state_bytes_total) { return 5 * state_bytes_total > MALL_BYTES; }
@@ -351,6 +352,7 @@ HalfArgs<T> make_args(tdse_ctx* h, int mode, int rows, int waves, int zc, long r
     a.part_plane = h->part_plane;
     a.pixel = (d.flags & TDSE_FLAG_PIXEL_INTEGRAL) ? h->pix : nullptr;
     a.pixel_w = (double)d.record_every * h->dt;
+    a.nt_in = stream_outputs(state_bytes(d));
     if (mode == MODE_I || mode == MODE_R) a.pixel = nullptr;
     return a;
 }

@@ -159,9 +159,27 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     // results are never stored or read), and no CAP factors on planes
     // without absorption (ca = cb = 1); the bits are the same.
     const bool sel_xy = NT != 1024 || a.bcx || a.bcy;
-    auto phase = [&](auto is_r, int p, const VT(&zl)[M], const VT(&c)[M], const VT(&zr)[M],
+    // Phase d (1..4) is exact on extended rows [d, ey - d); with one row per
+    // thread, a wavefront none of whose rows lie there skips it (its rows
+    // are all discarded rim, and no needed cell of the next phase reads
+    // them): two of 16 wavefronts in the last phase of a 1024-thread tile.
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+    const int wlo = wbase / a.tpr;
+    const int whi = min((wbase + 63) / a.tpr, a.rpp - 1);
+    auto wave_needed = [&](int d) -> bool {
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+            if (whi + i * a.rpp >= d && wlo + i * a.rpp < ey - d) return true;
+        return false;
+    };
+    auto phase = [&](auto is_r, int depth, int p, const VT(&zl)[M], const VT(&c)[M], const VT(&zr)[M],
                      const T* src, const VT(&uo)[M], const VT(&cvv)[M], VT(&out)[M], T* dst) {
         constexpr bool IS_R = decltype(is_r)::value;
+        if (M == 1 && !wave_needed(depth)) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) out[i] = zero_vec();
+            return;
+        }
         const int gp = gplane(p);
         if (gp < 0) {
 #pragma unroll
@@ -272,13 +290,13 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
         }
         VT nA[M], nB[M], nC[M], nD[M];
         // A1: I^{n+1/2}(k+3)
-        phase(IsI{}, k + 3, Rn[0], Rn[1], Rn[2], buf(0, par), io, Vw[3], nA, buf(1, par ^ 1));
+        phase(IsI{}, 1, k + 3, Rn[0], Rn[1], Rn[2], buf(0, par), io, Vw[3], nA, buf(1, par ^ 1));
         // B1: R^{n+1}(k+2)
-        phase(IsR{}, k + 2, Ia[0], Ia[1], nA, buf(1, par), Rn[0], Vw[2], nB, buf(2, par ^ 1));
+        phase(IsR{}, 2, k + 2, Ia[0], Ia[1], nA, buf(1, par), Rn[0], Vw[2], nB, buf(2, par ^ 1));
         // A2: I^{n+3/2}(k+1)
-        phase(IsI{}, k + 1, Rb[0], Rb[1], nB, buf(2, par), Ia[0], Vw[1], nC, buf(3, par ^ 1));
+        phase(IsI{}, 3, k + 1, Rb[0], Rb[1], nB, buf(2, par), Ia[0], Vw[1], nC, buf(3, par ^ 1));
         // B2: R^{n+2}(k)
-        phase(IsR{}, k, Ib[0], Ib[1], nC, buf(3, par), Rb[0], Vw[0], nD, nullptr);
+        phase(IsR{}, 4, k, Ib[0], Ib[1], nC, buf(3, par), Rb[0], Vw[0], nD, nullptr);
         const int pB = k + 2, pC = k + 1, pD = k;
         if (pC >= k0 && pC < k1) {
             const auto rI = prs(a.I1, pC);

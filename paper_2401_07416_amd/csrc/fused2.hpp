@@ -175,7 +175,9 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     auto phase = [&](auto is_r, int depth, int p, const VT(&zl)[M], const VT(&c)[M], const VT(&zr)[M],
                      const T* src, const VT(&uo)[M], const VT(&cvv)[M], VT(&out)[M], T* dst) {
         constexpr bool IS_R = decltype(is_r)::value;
-        if (M == 1 && !wave_needed(depth)) {
+        // the march's first iterations reach planes below those the stored
+        // planes [k0, k1) depend on: phase d needs planes >= k0 - (4 - d)
+        if (p < k0 - (4 - depth) || (M == 1 && !wave_needed(depth))) {
 #pragma unroll
             for (int i = 0; i < M; ++i) out[i] = zero_vec();
             return;

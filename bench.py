@@ -283,6 +283,35 @@ def paper_design(sim, w, ours, steps=100):
             "library_over_paper_block_16x4x4": round(ours / res["16x4x4"]["gcell_steps_s"], 2)}
 
 
+def secondary_shard(steps=400):
+    """One GPU's z-slab of the headline grid split over 8 GPUs (512x512x128,
+    periodic z in place of the halo planes), with the halo traffic the
+    sharded sweep would exchange per two-step pass: R^n on 4 planes below
+    and 3 above the slab, I^{n-1/2} on 3 below and 2 above (the planes the
+    sweep's first and last stored planes depend on), over one xGMI link to
+    each z neighbour at the 153 GB/s per link of the MI355X's
+    specification (an estimate; nothing here uses a second GPU)."""
+    from paper_2401_07416_amd import tdse, tuning, workloads
+    w = workloads.c3_shard(8, 1)
+    sim = tdse.sim_from_workload(w, precision="f32", steps=steps + 20)
+    t = tuning.tile_for(w, "f32")
+    if t:
+        sim.set_tile(**t)
+    sim.step(20)
+    ms = time_steps(sim, steps)
+    v = w.cells * steps / (ms * 1e-3) / 1e9
+    plane = w.nx * w.ny * 4
+    up, down = (3 + 2) * plane, (4 + 3) * plane
+    link_us = max(up, down) / 153e9 * 1e6
+    pass_us = 2 * ms / steps * 1e3
+    tile = sim.get_tile()
+    return {"workload": w.name + " FP32 (one of 8 z-slabs of surface-512x512x1024)",
+            "value": round(v, 2), "unit": "Gcell-steps/s", "ms_per_step": round(ms / steps, 4),
+            "two_step": int(tile.two_step), "halo_bytes_per_pass": up + down,
+            "halo_link_us_per_pass_est": round(link_us, 1), "compute_us_per_pass": round(pass_us, 1),
+            "eight_gpu_gcell_steps_s_if_hidden": round(8 * v, 1)}
+
+
 def secondary_adjoint():
     """Plain forward, checkpointed forward and adjoint of the 128x128x256,
     4000-step gradient workload in FP32, timed with HIP events."""
@@ -479,7 +508,8 @@ def main():
         sec = {}
         for name, fn in (("fp64", secondary_fp64), ("adjoint", secondary_adjoint),
                          ("batched", secondary_batch), ("interpolation", secondary_interp),
-                         ("dissimilarity", secondary_dissim), ("paper_setup", secondary_paper)):
+                         ("dissimilarity", secondary_dissim), ("paper_setup", secondary_paper),
+                         ("shard_share", secondary_shard)):
             try:
                 sec[name] = fn()
             except Exception as ex:  # reported, never hidden

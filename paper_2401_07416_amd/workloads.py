@@ -156,6 +156,20 @@ def c3_headline(seed: int = 2401) -> Workload:
                     dt_frac=0.9, steps=10000, k_det=250, record_every=50)
 
 
+def c3_shard(gpus: int = 8, index: int = 1, seed: int = 2401) -> Workload:
+    """One GPU's share of the 512x512x1024 headline grid split into z-slabs
+    over `gpus` GPUs: slab `index` of 1024 / gpus planes, the same tiled
+    surface atoms shifted into the slab's frame, periodic z standing in for
+    the halo planes the neighbouring GPUs would send, no absorbing planes (an
+    interior slab has none), the packet in the middle of the slab."""
+    w = c3_headline(seed)
+    nz = w.nz // gpus
+    atoms = w.atoms.copy()
+    atoms[:, 2] -= index * nz * w.dz
+    return w.with_(name=f"shard{index}of{gpus}-512x512x{nz}", nz=nz, atoms=atoms, cap=None,
+                   r0=(51.2, 51.2, 0.5 * nz * w.dz), k_det=nz // 2)
+
+
 def c5_adjoint(seed: int = 5, nxy: int = 128, nz: int = 256, steps: int = 4000) -> Workload:
     """Adjoint-gradient workload: 128x128x256 (25.6 x 25.6 x 51.2 A), FP32
     forward, a 3 x 8 x 8 slab at a = 3.2 A (top layer z = 18 A, layers 2.5 A
@@ -342,6 +356,7 @@ ALL = {
     "surface": c2_surface,
     "surface-reduced": c2_reduced,
     "headline": c3_headline,
+    "headline-shard8": c3_shard,
     "ragged": ragged,
     "adjoint": c5_adjoint,
     "paper-cu111": paper_cu111,

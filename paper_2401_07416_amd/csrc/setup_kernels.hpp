@@ -7,22 +7,13 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "kernels.hpp"
+
 namespace tdse {
 
-// Fixed-order FP64 sum over a workgroup of 256 threads.
-__device__ __forceinline__ double block_sum256(double v, double* red) {
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-#pragma unroll
-    for (int o = 128; o > 0; o >>= 1) {
-        if (t < o) red[t] += red[t + o];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
-}
+// Fixed-order FP64 sum over a workgroup of 256 threads (wavefront
+// butterflies, then the four wavefront totals in order).
+__device__ __forceinline__ double block_sum256(double v, double* red) { return block_sum(v, red, 4); }
 
 struct FinArgs {
     const double* flux_ring;  // [n_pending][2][ytiles]
@@ -40,7 +31,7 @@ struct FinArgs {
 // Folds the pending per-step flux partials into the accumulator in step
 // order and, on record steps, writes {plane_sum, naive_norm, Q, flux_acc}.
 __device__ __forceinline__ void finalize_body(const FinArgs& a) {
-    __shared__ double red[256];
+    __shared__ double red[4];
     const int t = threadIdx.x;
     double acc = a.acc[0];
     for (int s = 0; s < a.n_pending; ++s) {

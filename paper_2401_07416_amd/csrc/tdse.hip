@@ -48,6 +48,7 @@ struct tdse_ctx {
     int t2x = 56, t2m = 2, t2zc = 64, t2t = 256;
     bool t2pf = false;
     int lds_max = 65536;   // dynamic + static LDS per workgroup of the device
+    int cus = 256;         // compute units of the device
     // adjoint: checkpoints every adj_K steps of an adj_N-step forward run
     void* adj_ws = nullptr;
     int64_t adj_N = 0;
@@ -949,6 +950,19 @@ void default_two_step(tdse_ctx* h) {
     h->t2t = cl[0].nt;
     h->t2pf = true;
     h->t2zc = (int)std::min<int64_t>(64, d.nz);
+    // FP32 grids large enough for 2.5 waves of one 1024-thread workgroup
+    // per CU in 128-plane chunks take that tile (its rim is the smallest)
+    if (!f64 && d.nz >= 128) {
+        const Fused2Dims f = fused2_dims(h, 64, 1, 128, 1024);
+        if (f.ok && 2 * (long)f.nwg >= 5L * h->cus) {
+            h->two = true;
+            h->t2x = 64;
+            h->t2m = 1;
+            h->t2t = 1024;
+            h->t2zc = 128;
+            return;
+        }
+    }
     for (int z = 0; z < 3; ++z) {
         const int zc0 = zcs[z];
         if (zc0 > d.nz) continue;
@@ -1349,6 +1363,10 @@ tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out) {
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess &&
         lds > 0)
         h->lds_max = lds;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess &&
+        cus > 0)
+        h->cus = cus;
     default_tile(h);
     default_fused_tile(h);
     default_two_step(h);

@@ -66,7 +66,7 @@ def test_two_step_ragged_boundaries_vs_oracle(prec, bc):
     w = workloads.ragged(prec).with_(bc=bc)
     say("two-step ragged", prec, "bc", bc)
     ref = H.oracle_run(w, w.steps)
-    for tile in (two(8, 2, 16), two(16, 3, 53, 1), two(16, 1, 20, 1, 512)):
+    for tile in (two(8, 2, 16), two(16, 3, 53, 1), two(16, 1, 20, 1, 512), two(16, 1, 20, 1, 1024)):
         gpu = H.gpu_run(w, w.steps, precision=prec, tile=tile)
         say(" tile", tile, H.compare(gpu, ref, **(FP64 if prec == "f64" else FP32)))
 
@@ -82,8 +82,9 @@ def test_two_step_degenerate_extents(shape, kdet):
         ww = w.with_(bc=bc)
         say("two-step degenerate", shape, "bc", bc)
         ref = H.oracle_run(ww, ww.steps)
-        gpu = H.gpu_run(ww, ww.steps, precision="f64", tile=two(8, 2, 8))
-        say(H.compare(gpu, ref, **FP64))
+        for tile in (two(8, 2, 8), two(8, 1, 8, 0, 1024)):
+            gpu = H.gpu_run(ww, ww.steps, precision="f64", tile=tile)
+            say(" tile", tile, H.compare(gpu, ref, **FP64))
 
 
 def test_two_step_odd_chunks_and_resume():

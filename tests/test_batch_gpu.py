@@ -35,7 +35,8 @@ def small_set(steps):
     return out
 
 
-@pytest.mark.parametrize("form", ["two-step", "two-step-512", "one-pass-256", "one-pass-64"])
+@pytest.mark.parametrize("form", ["two-step", "two-step-512", "two-step-1024", "one-pass-256",
+                                  "one-pass-64"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_batch_equals_single_runs(prec, form):
     steps = 60
@@ -46,6 +47,8 @@ def test_batch_equals_single_runs(prec, form):
         b.set_two_step(True, tx=24, zc=32, prefetch=True, rows=2, threads=256)
     elif form == "two-step-512":
         b.set_two_step(True, tx=32, zc=16, prefetch=True, rows=1, threads=512)
+    elif form == "two-step-1024":
+        b.set_two_step(True, tx=16, zc=16, prefetch=True, rows=1, threads=1024)
     else:
         b.set_two_step(False)
         b.set_tile(fused_rows=3, fused_zc=16, prefetch=True, threads=int(form.split("-")[-1]))

@@ -2196,8 +2196,9 @@ tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile
         }
     }
     if (want2s && h->R2) {
-        const int c[6][4] = {{64, 1, 512, 64}, {56, 1, 512, 64}, {56, 2, 512, 128},
-                             {64, 2, 256, 64}, {32, 1, 512, 32}, {32, 2, 256, 128}};
+        const int c[9][4] = {{64, 1, 512, 64}, {56, 1, 512, 64}, {56, 2, 512, 128},
+                             {64, 2, 256, 64}, {32, 1, 512, 32}, {32, 2, 256, 128},
+                             {64, 1, 1024, 128}, {32, 1, 1024, 32}, {120, 1, 1024, 64}};
         for (const auto& x : c) {
             tdse_tile t = base;
             t.fused = 1;

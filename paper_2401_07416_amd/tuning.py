@@ -52,7 +52,7 @@ def candidates(nz: int):
                 yield dict(fused=1, two_step=0, fused_rows=fr, fused_zc=zc, fused_prefetch=1,
                            fused_threads=256)
     for tx in (16, 24, 32, 40, 56, 64, 120):
-        for rows, threads in ((2, 256), (1, 512), (2, 512)):
+        for rows, threads in ((2, 256), (1, 512), (2, 512), (1, 1024)):
             for zc in (32, 64, 128):
                 if zc <= nz:
                     yield dict(fused=1, two_step=1, two_step_tx=tx, two_step_rows=rows,

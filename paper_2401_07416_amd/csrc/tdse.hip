@@ -950,6 +950,23 @@ void default_two_step(tdse_ctx* h) {
     h->t2t = cl[0].nt;
     h->t2pf = true;
     h->t2zc = (int)std::min<int64_t>(64, d.nz);
+    // FP64: the 1024-thread tile 32 wide (W = 2) in the longest z chunk that
+    // still gives 2.5 waves of one workgroup per CU
+    if (f64) {
+        const int zcs1[3] = {128, 64, 32};
+        for (int zc0 : zcs1) {
+            if (zc0 > d.nz) continue;
+            const Fused2Dims f = fused2_dims(h, 32, 1, zc0, 1024);
+            if (f.ok && 2 * (long)f.nwg >= 5L * h->cus) {
+                h->two = true;
+                h->t2x = 32;
+                h->t2m = 1;
+                h->t2t = 1024;
+                h->t2zc = zc0;
+                return;
+            }
+        }
+    }
     // FP32 grids large enough for 2.5 waves of one 1024-thread workgroup
     // per CU in 128-plane chunks take that tile (its rim is the smallest)
     if (!f64 && d.nz >= 128) {

@@ -157,9 +157,16 @@ def test_two_step_rejects_bad_tiles():
     w = workloads.c2_reduced().with_(steps=10)
     s = tdse.sim_from_workload(w, precision="f32", steps=10)
     for bad in (two(4, 2, 8), two(56, 4, 8), two(2040, 2, 8), dict(fused=0, two_step=1),
-                two(56, 3, 8, 0, 512), two(56, 2, 8, 0, 128)):
+                two(56, 3, 8, 0, 512), two(56, 2, 8, 0, 128), two(56, 2, 8, 0, 1024)):
         with pytest.raises(tdse.TdseError):
             s.set_tile(**bad)
+    # a (rows, threads) pair that has no kernel names the pairs that do
+    with pytest.raises(tdse.TdseError, match=r"\(1,1024\)") as e:
+        s.set_tile(**two(56, 2, 8, 0, 1024))
+    assert e.value.status == tdse.ERR_UNSUPPORTED
+    # the handle still steps with its previous tile
+    s.step(2)
+    assert s.detect().n_records >= 1
 
 
 def test_library_autotuner_picks_a_tile_and_spends_the_state():

@@ -446,7 +446,9 @@ tdse_status tdse_hbm_probe(int32_t kind, void* const* bufs, int64_t n, int32_t g
  * planes per workgroup, two_step_prefetch != 0 loads the next plane's
  * inputs one iteration ahead.  The sweep needs at most ny tiles per plane
  * and its LDS ((2 x 4) buffers of (ty + 10) x (tx + 8) values, plus 8 bytes
- * per thread) within the device's per-workgroup limit.
+ * per wavefront) within the device's per-workgroup limit.  TDSE_ERR_ARG for
+ * a thread count other than 256, 512 or 1024; TDSE_ERR_UNSUPPORTED for a
+ * (rows, threads) pair without a kernel or a tile that does not fit.
  *
  * tdse_create picks defaults; tdse_set_tile checks and replaces them.  The
  * last five fields are read-only. */

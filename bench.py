@@ -474,6 +474,11 @@ def main():
                 "alg_bytes_per_launch": alg_bytes,
                 "launches": {k: v[1] for k, v in kt.items()},
                 "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()}}
+        if traffic is not None:
+            # the memory-side rate: counted bytes per launch over this run's
+            # average launch time
+            roof["traffic_gbs"] = round(traffic / (avg * 1e-3) / 1e9, 1)
+            roof["traffic_frac"] = round(traffic / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     # algorithmic bytes per cell-step of the launches the timed steps ran
     alg_words = sum(words[k] * kt[k][1] for k in kt)
     bytes_per_cell_step = es * alg_words / max(1, a.steps)

@@ -927,71 +927,70 @@ void default_fused_tile(tdse_ctx* h) {
     h->fzc = bzc;
 }
 
-// The two-step sweep pays a six-plane start per z chunk and a four-cell rim
-// per tile, so it is the default only where chunks of >= 32 planes still
-// give a few hundred workgroups; the first fitting (tile width, z chunk) in
-// order of preference is taken.
+// Workgroups of a two-step tile one CU holds at once: LDS, and the
+// wavefronts per SIMD the kernel's registers allow (one row per thread:
+// <= 128 VGPRs, 4 per SIMD; two rows: 2 per SIMD; three rows: 1).
+int fused2_wg_per_cu(const tdse_ctx* h, const Fused2Dims& f, int m) {
+    const int waves = f.nt / 64;
+    const int per_simd = m == 1 ? 4 : (m == 2 ? 2 : 1);
+    const int by_regs = std::max(1, 4 * per_simd / waves);
+    const size_t lds = f.lds + 8 * (size_t)(f.nt / 64);
+    const int by_lds = std::max(1, (int)((size_t)h->lds_max / lds));
+    return std::min(by_regs, by_lds);
+}
+
+// Modelled time of a two-step tile: the workgroups run in ceil(nwg / slots)
+// waves, slots = CUs x workgroups per CU; each takes (zc + 6) planes of its
+// extended tile, at a rate shared by the workgroups of a CU.  On the grids
+// measured this ranks the tiles and chunks as the timings do (the chunk
+// that makes the last wave full matters most on mid-size grids).
+double fused2_cost(const tdse_ctx* h, const Fused2Dims& f, int m, int zc) {
+    const int k = fused2_wg_per_cu(h, f, m);
+    const long slots = (long)k * h->cus;
+    const long waves = (f.nwg + slots - 1) / slots;
+    return (double)waves * k * (zc + 6) * (double)f.ex * f.ey;
+}
+
+// The default two-step tile: the lowest modelled time over the built
+// (rows, threads) pairs, a few tile widths and z chunks of 32 .. 256 planes
+// (shorter chunks spend too much on the six-plane start), where the tile
+// fits and its workgroups fill at least three quarters of the CUs' slots.
 void default_two_step(tdse_ctx* h) {
     const tdse_desc& d = h->d;
     const bool f64 = d.precision == TDSE_F64;
     struct Cand {
         int tx, m, nt;
     };
-    const Cand c32[5] = {{64, 1, 512}, {64, 2, 256}, {56, 2, 256}, {32, 1, 512}, {24, 2, 256}};
-    const Cand c64[6] = {{64, 1, 1024}, {32, 1, 1024}, {56, 2, 512}, {32, 1, 512}, {32, 2, 256},
-                         {16, 2, 256}};
+    // on a tie of the model the earlier candidate stays (512 threads first:
+    // two workgroups per CU hide more latency than one)
+    const Cand c32[10] = {{64, 1, 512}, {56, 1, 512}, {48, 1, 512}, {32, 1, 512}, {64, 1, 1024},
+                          {120, 1, 1024}, {32, 1, 1024}, {64, 2, 256}, {56, 2, 256}, {24, 2, 256}};
+    const Cand c64[8] = {{32, 1, 512}, {64, 1, 512}, {32, 1, 1024}, {64, 1, 1024}, {16, 1, 1024},
+                         {56, 2, 512}, {32, 2, 256}, {16, 2, 256}};
     const Cand* cl = f64 ? c64 : c32;
-    const int nc = f64 ? 6 : 5;
-    const int zcs32[3] = {64, 128, 32}, zcs64[3] = {128, 64, 32};
-    const int* zcs = f64 ? zcs64 : zcs32;
+    const int nc = f64 ? 8 : 10;
     h->two = false;
     h->t2x = cl[0].tx;
     h->t2m = cl[0].m;
     h->t2t = cl[0].nt;
     h->t2pf = true;
     h->t2zc = (int)std::min<int64_t>(64, d.nz);
-    // FP64: the 1024-thread tile 32 wide (W = 2) in the longest z chunk that
-    // still gives 2.5 waves of one workgroup per CU
-    if (f64) {
-        const int zcs1[3] = {128, 64, 32};
-        for (int zc0 : zcs1) {
-            if (zc0 > d.nz) continue;
-            const Fused2Dims f = fused2_dims(h, 32, 1, zc0, 1024);
-            if (f.ok && 2 * (long)f.nwg >= 5L * h->cus) {
-                h->two = true;
-                h->t2x = 32;
-                h->t2m = 1;
-                h->t2t = 1024;
-                h->t2zc = zc0;
-                return;
-            }
-        }
-    }
-    // FP32 grids large enough for 2.5 waves of one 1024-thread workgroup
-    // per CU in 128-plane chunks take that tile (its rim is the smallest)
-    if (!f64 && d.nz >= 128) {
-        const Fused2Dims f = fused2_dims(h, 64, 1, 128, 1024);
-        if (f.ok && 2 * (long)f.nwg >= 5L * h->cus) {
-            h->two = true;
-            h->t2x = 64;
-            h->t2m = 1;
-            h->t2t = 1024;
-            h->t2zc = 128;
-            return;
-        }
-    }
-    for (int z = 0; z < 3; ++z) {
-        const int zc0 = zcs[z];
-        if (zc0 > d.nz) continue;
-        for (int i = 0; i < nc; ++i) {
+    double best = 0.0;
+    for (int i = 0; i < nc; ++i) {
+        for (int zc0 = 32; zc0 <= 256; zc0 += 4) {
+            if (zc0 > d.nz) break;
             const Fused2Dims f = fused2_dims(h, cl[i].tx, cl[i].m, zc0, cl[i].nt);
-            if (f.ok && (long)f.nwg * cl[i].nt >= 384L * 256) {
+            // at least three quarters of one wave of workgroups, else the
+            // one-pass step (more, smaller workgroups) keeps the CUs busier
+            if (!f.ok || 4L * f.nwg < 3L * fused2_wg_per_cu(h, f, cl[i].m) * h->cus) continue;
+            const double c = fused2_cost(h, f, cl[i].m, zc0);
+            if (!h->two || c < best) {
+                best = c;
                 h->two = true;
                 h->t2x = cl[i].tx;
                 h->t2m = cl[i].m;
                 h->t2t = cl[i].nt;
                 h->t2zc = zc0;
-                return;
             }
         }
     }
@@ -2227,6 +2226,29 @@ tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile
             t.two_step_prefetch = 1;
             cands.push_back(t);
         }
+        // and the cost model's choice for this grid (its z chunk fills the
+        // last wave of workgroups)
+        const bool two0 = h->two;
+        const bool pf0 = h->t2pf;
+        const int x0 = h->t2x, m0 = h->t2m, t0 = h->t2t, z0 = h->t2zc;
+        default_two_step(h);
+        if (h->two) {
+            tdse_tile t = base;
+            t.fused = 1;
+            t.two_step = 1;
+            t.two_step_tx = h->t2x;
+            t.two_step_rows = h->t2m;
+            t.two_step_threads = h->t2t;
+            t.two_step_zc = h->t2zc;
+            t.two_step_prefetch = 1;
+            cands.push_back(t);
+        }
+        h->two = two0;
+        h->t2pf = pf0;
+        h->t2x = x0;
+        h->t2m = m0;
+        h->t2t = t0;
+        h->t2zc = z0;
     }
     // no records while tuning (the state is given up anyway)
     const int64_t hrec = h->d.record_every;

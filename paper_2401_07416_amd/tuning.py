@@ -67,7 +67,21 @@ def autotune(sim, steps: int = 20, reps: int = 3, cands=None):
 
     from .tdse import TdseError
     res = []
-    for tile in (cands or candidates(sim.desc.nz)):
+    if cands is None:
+        # the library's own default for this grid (its cost-model choice of
+        # the two-step tile) is timed with the list
+        t = sim.get_tile()
+        cur = dict(fused=t.fused, two_step=t.two_step)
+        if t.two_step:
+            cur.update(two_step_tx=t.two_step_tx, two_step_rows=t.two_step_rows,
+                       two_step_zc=t.two_step_zc, two_step_prefetch=t.two_step_prefetch,
+                       two_step_threads=t.two_step_threads)
+        cands = list(candidates(sim.desc.nz)) + [cur]
+    # one-time costs (first launches, code loading) land here, not on the
+    # first candidate
+    sim.step(4)
+    torch.cuda.synchronize()
+    for tile in cands:
         try:
             sim.set_tile(**tile)
         except TdseError:

@@ -358,7 +358,8 @@ tdse_status tdse_batch_create(const tdse_desc* descs, int32_t n, void* stream, t
 tdse_status tdse_batch_member(tdse_batch b, int32_t i, tdse_handle* h);
 tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc,
                                 int32_t prefetch, int32_t threads);
-/* Two-step sweeps for the whole batch (on by default): when every member
+/* Two-step sweeps for the whole batch (on by default, with tx 64, one row,
+ * z chunk 48, prefetch, 1024 threads): when every member
  * fits the sweep's tile (interior width tx, rows per thread, z chunk zc,
  * prefetch and threads per workgroup as for tdse_tile) and the members
  * share the vector width,

@@ -104,7 +104,7 @@ struct tdse_batch_ctx {
     bool pf = false;
     // two-step sweep for the whole batch (when every member fits it)
     bool two = true;
-    int t2x = 64, t2zc = 64, t2m = 1, t2t = 512;
+    int t2x = 64, t2zc = 48, t2m = 1, t2t = 1024;
     bool t2pf = true;
     bool use2 = false;  // chosen at prepare
     int par = 0;        // state pair holding the members' current level
@@ -1131,12 +1131,20 @@ static tdse_status batch_prepare2_t(tdse_batch_ctx* b, bool* used) {
         if (!f.ok) return TDSE_OK;
         if (W == 0) W = f.W;
         if (f.W != W) return TDSE_OK;
+        // the member's own tile is kept for its single-grid steps
+        const int sx = h->t2x, sm = h->t2m, sz = h->t2zc, st = h->t2t;
+        const bool spf = h->t2pf;
         h->t2x = b->t2x;
         h->t2m = b->t2m;
         h->t2zc = zc;
         h->t2pf = b->t2pf;
         h->t2t = b->t2t;
         cfg[i] = make_fused2_args<T>(h, f, b->h > 0, 0, 0);
+        h->t2x = sx;
+        h->t2m = sm;
+        h->t2zc = sz;
+        h->t2pf = spf;
+        h->t2t = st;
         cfg[i].nt_out = batch_streams(b);
         cfg[i].rec_plane = static_cast<T*>(h->rec);  // record 0; the kernel adds the counter
         lds = std::max(lds, f.lds);
@@ -1213,10 +1221,21 @@ static tdse_status batch_prepare_t(tdse_batch_ctx* b) {
     int W = 0;
     for (size_t i = 0; i < n; ++i) {
         tdse_ctx* h = b->members[i];
+        // the member's own tile is kept for its single-grid steps
+        const int sm = h->fm, sz = h->fzc, st = h->ft;
         h->fm = b->M;
         h->fzc = (int)std::min<int64_t>(b->zc, h->d.nz);
         h->ft = b->nt;
         const FusedDims fd = fused_dims(h, b->M, h->fzc, b->nt);
+        struct Restore {
+            tdse_ctx* h;
+            int m, z, t;
+            ~Restore() {
+                h->fm = m;
+                h->fzc = z;
+                h->ft = t;
+            }
+        } restore{h, sm, sz, st};
         if (!fd.ok) return bfail(b, TDSE_ERR_UNSUPPORTED, "member grid does not fit the one-pass tile");
         if (W == 0) W = fd.W;
         if (fd.W != W) return bfail(b, TDSE_ERR_UNSUPPORTED, "members need the same vector width");

@@ -396,9 +396,13 @@ tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count);
  * times (records of configurations with equal grids and time steps);
  * weights: device double [T]; out: device double [K][K] (symmetric, zero
  * diagonal); workspace: device, >= tdse_dissimilarity_workspace_size bytes.
- * All caller-owned.  The sums are formed from the differences (no
- * cancellation), FP32 frames in FP32 over chunks of 32 pixels and FP64
- * beyond; the result is bitwise reproducible.  Asynchronous on stream (a
+ * All caller-owned.  FP64 frames: the sums are formed from the
+ * differences on the vector ALU.  FP32 frames: on the FP64 matrix cores as
+ * |x_k|^2 + |x_j|^2 - 2 x_k . x_j with x = frame - (the frame of trajectory
+ * 0 at the same time), exact in FP64 (the shift leaves every distance
+ * unchanged and keeps the cancellation to a few FP64 ulps of |x|^2); a
+ * negative rounding residue counts as zero.  The result is bitwise
+ * reproducible and exactly symmetric.  Asynchronous on stream (a
  * hipStream_t, may be null).  TDSE_ERR_ARG for null pointers, sizes < 1,
  * dA <= 0 or a short workspace; TDSE_ERR_DEVICE for launch errors. */
 tdse_status tdse_dissimilarity_workspace_size(int32_t K, int32_t T, size_t* bytes);

@@ -4,16 +4,16 @@
 //   d_kj = sum_t w_t sqrt(dA sum_p (rho_k,t,p - rho_j,t,p)^2),
 // with the quadrature weights w_t carrying 1 / (t1 - t0).
 //
-// The pixel sum is formed directly from the differences, not from the Gram
-// expansion |a|^2 + |b|^2 - 2 a.b: trajectories that are close (the pairs a
-// dissimilarity is for) would lose their distance to cancellation in the
-// FP32 cross term.  So the contraction runs on the vector ALU, register
-// tiled like a GEMM: a workgroup owns a 64 x 64 block of pairs, each thread a
-// 4 x 4 sub-block, and pixels stream through LDS in chunks of 32; per chunk
-// the squared differences are summed in the frame precision (fused
-// multiply-adds) and then added to an FP64 accumulator.  Each workgroup covers a range of frames and
-// writes its partial time sum; a second kernel adds the partials in a fixed
-// order, so the result is bitwise reproducible and exactly symmetric.
+// FP32 frames (the records) go to the FP64 matrix cores as a Gram
+// contraction of shifted frames (dissim_gram_kernel, below).  FP64 frames
+// keep the direct form on the vector ALU, where an FP64 Gram expansion
+// would lose close pairs to cancellation: register tiled like a GEMM, a
+// workgroup owns a 64 x 64 block of pairs, each thread a 4 x 4 sub-block,
+// pixels stream through LDS in chunks of 32, and the squared differences of
+// a chunk are summed with fused multiply-adds.  Each workgroup covers a
+// range of frames and writes its partial time sums; a second kernel adds
+// the partials in a fixed order, so the result is bitwise reproducible and
+// exactly symmetric.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -169,6 +169,213 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
         }
 }
 
+// FP32 frames on the matrix cores.  The distance does not change when every
+// frame of a time t is shifted by the same image c_t, and with x_k = rho_k - c
+//   sum_p (rho_k - rho_j)^2 = |x_k|^2 + |x_j|^2 - 2 x_k . x_j,
+// a Gram contraction.  Formed in FP64 from FP32 frames: x = rho - c is exact
+// in FP64, and the shift c_t = the frame of trajectory 0 keeps |x|^2 of the
+// order of the distances themselves for trajectories that are close to one
+// another (the case a dissimilarity has to resolve), so the cancellation in
+// the expansion costs a few FP64 ulps of |x|^2, not the FP32 cross term's
+// 1e-7.  The Gram block of a workgroup (GB x GB pairs, eight wavefronts of
+// 32 x 64 pairs) accumulates on v_mfma_f64_16x16x4_f64 over chunks of GPC
+// pixels staged in LDS as FP64 rows; the squared norms come from the same
+// FP64 values as they are staged.
+constexpr int GB = 128;           // trajectories per block side
+constexpr int GPC = 64;           // pixels per LDS chunk
+constexpr int GLS = GPC + 2;      // LDS row stride in doubles (16-byte rows, spread banks)
+constexpr int GTHREADS = 512;
+static_assert(GPC % 4 == 0 && GB % (GTHREADS / (GPC / 4)) == 0 && GPC / 4 <= 64, "staging map");
+constexpr int GQ = GPC / 4;            // 4-pixel vectors per row and chunk
+constexpr int GRP = GTHREADS / GQ;     // rows staged per pass
+constexpr int GNP = GB / GRP;          // passes per side
+constexpr int GKU = 4;                 // MFMA steps unrolled per loop trip
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct GramArgs {
+    const float* frames;  // [K][T][P]
+    const double* w;      // [T]
+    double dA;
+    int K, T;
+    long P;
+    int nb, npb, tpc;
+    double* part;         // [ntc][K][K]
+};
+
+// four consecutive pixels p0 .. p0 + 3 of a row (zero past P)
+template <bool VEC>
+__device__ __forceinline__ float4 load4(const float* row, long p0, long P) {
+    if (VEC) {
+        if (p0 < P) return *reinterpret_cast<const float4*>(row + p0);
+        return make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float4 r;
+    r.x = p0 < P ? row[p0] : 0.f;
+    r.y = p0 + 1 < P ? row[p0 + 1] : 0.f;
+    r.z = p0 + 2 < P ? row[p0 + 2] : 0.f;
+    r.w = p0 + 3 < P ? row[p0 + 3] : 0.f;
+    return r;
+}
+
+// VEC: P is a multiple of 4 (whole float4 loads)
+template <bool VEC>
+__global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
+    __shared__ __align__(16) double As[GB * GLS];
+    __shared__ __align__(16) double Bs[GB * GLS];
+    __shared__ double nrm[2 * GB];
+    const int q = blockIdx.x % a.npb;
+    const int tc = blockIdx.x / a.npb;
+    int bi, bj;
+    pair_block(q, a.nb, &bi, &bj);
+    const int r0 = bi * GB, c0 = bj * GB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 64;  // the wavefront's 32 x 64 pairs
+    const int li = lane & 15, lk = lane >> 4;
+    const int t0 = tc * a.tpc;
+    const int t1 = min(t0 + a.tpc, a.T);
+    const long TP = (long)a.T * a.P;
+    const long cpt = (a.P + GPC - 1) / GPC;
+    const long nch = cpt * (t1 - t0);
+
+    // staging: rows srow + GRP i of each side, pixels 4 quad .. 4 quad + 3
+    const int quad = tid % GQ, srow = tid / GQ;
+    float4 ra[GNP], rb[GNP], rc;
+    bool va[GNP], vb[GNP];
+#pragma unroll
+    for (int i = 0; i < GNP; ++i) {
+        va[i] = r0 + srow + GRP * i < a.K;
+        vb[i] = c0 + srow + GRP * i < a.K;
+    }
+    auto fetch = [&](long c) {
+        const int t = t0 + (int)(c / cpt);
+        const long p0 = (c % cpt) * GPC + 4 * quad;
+        const long off = (long)t * a.P;
+#pragma unroll
+        for (int i = 0; i < GNP; ++i) {
+            ra[i] = va[i] ? load4<VEC>(a.frames + (long)(r0 + srow + GRP * i) * TP + off, p0, a.P)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+            rb[i] = vb[i] ? load4<VEC>(a.frames + (long)(c0 + srow + GRP * i) * TP + off, p0, a.P)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        rc = load4<VEC>(a.frames + off, p0, a.P);   // the shift: trajectory 0
+    };
+
+    dbl4 g[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) g[m][n] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // the time sums live in this workgroup's own slab of the partials (the
+    // pairs k <= j of its block), one read-modify-write per frame
+    double* out = a.part + (long)tc * a.K * a.K;
+    double na[GNP], nbv[GNP];
+#pragma unroll
+    for (int i = 0; i < GNP; ++i) na[i] = nbv[i] = 0.0;
+
+    // one row's four staged values as FP64 x = rho - c (exact), into LDS,
+    // with their squares added to the row's partial norm
+    auto stage = [&](double* L, int row, const float4& v, bool valid, double& nacc) {
+        double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+        if (valid) {
+            x0 = (double)v.x - (double)rc.x;
+            x1 = (double)v.y - (double)rc.y;
+            x2 = (double)v.z - (double)rc.z;
+            x3 = (double)v.w - (double)rc.w;
+        }
+        nacc = __builtin_fma(x0, x0, nacc);
+        nacc = __builtin_fma(x1, x1, nacc);
+        nacc = __builtin_fma(x2, x2, nacc);
+        nacc = __builtin_fma(x3, x3, nacc);
+        double2* d = reinterpret_cast<double2*>(L + row * GLS + 4 * quad);
+        d[0] = make_double2(x0, x1);
+        d[1] = make_double2(x2, x3);
+    };
+
+    if (nch > 0) fetch(0);
+    for (long c = 0; c < nch; ++c) {
+#pragma unroll
+        for (int i = 0; i < GNP; ++i) {
+            stage(As, srow + GRP * i, ra[i], va[i], na[i]);
+            stage(Bs, srow + GRP * i, rb[i], vb[i], nbv[i]);
+        }
+        __syncthreads();
+        if (c + 1 < nch) fetch(c + 1);
+#pragma unroll GKU
+        for (int kk = 0; kk < GPC / 4; ++kk) {
+            double av[2], bv[4];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) av[m] = As[(wr + 16 * m + li) * GLS + 4 * kk + lk];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) bv[n] = Bs[(wc + 16 * n + li) * GLS + 4 * kk + lk];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    g[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], g[m][n], 0, 0, 0);
+        }
+        const bool frame_done = c % cpt == cpt - 1;
+        if (frame_done) {
+            // a row's norm: its GQ quad lanes (adjacent lanes) combined
+            // by a butterfly, the same bits in each
+#pragma unroll
+            for (int i = 0; i < GNP; ++i) {
+                double x = na[i], y = nbv[i];
+#pragma unroll
+                for (int s = 1; s < GQ; s <<= 1) {
+                    x += __shfl_xor(x, s);
+                    y += __shfl_xor(y, s);
+                }
+                if (quad == 0) {
+                    nrm[srow + GRP * i] = x;
+                    nrm[GB + srow + GRP * i] = y;
+                }
+                na[i] = 0.0;
+                nbv[i] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (frame_done) {
+            const int f = (int)(c / cpt);
+            const double wt = a.w[t0 + f];
+            // element r of a lane's accumulator is pair (4 r + lk, li) of the 16 x 16 tile
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wr + 16 * m + 4 * r + lk, col = wc + 16 * n + li;
+                        const double d2 = (nrm[row] + nrm[GB + col]) - 2.0 * g[m][n][r];
+                        const double v = wt * sqrt(a.dA * fmax(d2, 0.0));
+                        g[m][n][r] = 0.0;
+                        const int k = r0 + row, j = c0 + col;
+                        if (k < a.K && j < a.K && k <= j) {
+                            double* o = out + (long)k * a.K + j;
+                            *o = f == 0 ? v : *o + v;
+                        }
+                    }
+        }
+    }
+    // a diagonal block holds both (k, j) and (j, k): the pair with k < j
+    // writes both, so the result is exactly symmetric; d_kk = 0
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = r0 + wr + 16 * m + 4 * r + lk, j = c0 + wc + 16 * n + li;
+                if (k < a.K && j < a.K && k <= j) {
+                    if (k == j)
+                        out[(long)k * a.K + k] = 0.0;
+                    else
+                        out[(long)j * a.K + k] = out[(long)k * a.K + j];
+                }
+            }
+}
+
 __global__ __launch_bounds__(256) void dissim_reduce_kernel(const double* part, int ntc, long kk,
                                                             double* out) {
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < kk; i += (long)gridDim.x * 256) {
@@ -181,6 +388,29 @@ __global__ __launch_bounds__(256) void dissim_reduce_kernel(const double* part, 
 struct Plan {
     int nb, npb, tpc, ntc;
 };
+
+// Gram kernel: frames per workgroup chosen so that the last round of
+// workgroups over the compute units is as full as possible (cost = rounds x
+// frames per workgroup, for 256 compute units; ties to more frames, less
+// workspace)
+Plan plan_gram(int K, int T) {
+    Plan p;
+    p.nb = (K + GB - 1) / GB;
+    p.npb = p.nb * (p.nb + 1) / 2;
+    constexpr long CUS = 256;
+    long best = -1;
+    p.tpc = 1;
+    for (int tpc = 1; tpc <= T; ++tpc) {
+        const long ntc = (T + tpc - 1) / tpc;
+        const long cost = (p.npb * ntc + CUS - 1) / CUS * tpc;
+        if (best < 0 || cost <= best) {
+            best = cost;
+            p.tpc = tpc;
+        }
+    }
+    p.ntc = (T + p.tpc - 1) / p.tpc;
+    return p;
+}
 
 Plan plan_of(int K, int T) {
     Plan p;
@@ -198,8 +428,9 @@ Plan plan_of(int K, int T) {
 
 extern "C" tdse_status tdse_dissimilarity_workspace_size(int32_t K, int32_t T, size_t* bytes) {
     if (!bytes || K < 1 || T < 1) return TDSE_ERR_ARG;
-    const Plan p = plan_of(K, T);
-    *bytes = (size_t)p.ntc * K * K * sizeof(double);
+    // the larger of the two kernels' partial sums (FP64 and FP32 frames)
+    const int ntc = std::max(plan_of(K, T).ntc, plan_gram(K, T).ntc);
+    *bytes = (size_t)ntc * K * K * sizeof(double);
     return TDSE_OK;
 }
 
@@ -209,26 +440,42 @@ extern "C" tdse_status tdse_dissimilarity(int32_t precision, const void* frames,
     if (!frames || !weights || !out || !workspace || K < 1 || T < 1 || P < 1) return TDSE_ERR_ARG;
     if (precision != TDSE_F32 && precision != TDSE_F64) return TDSE_ERR_ARG;
     if (!(dA > 0)) return TDSE_ERR_ARG;
-    const Plan p = plan_of(K, T);
+    const Plan p = precision == TDSE_F32 ? plan_gram(K, T) : plan_of(K, T);
     if (workspace_bytes < (size_t)p.ntc * K * K * sizeof(double)) return TDSE_ERR_ARG;
     if ((long)p.npb * p.ntc > (1L << 31) - 1) return TDSE_ERR_ARG;
-    DissimArgs a;
-    a.frames = frames;
-    a.w = weights;
-    a.dA = dA;
-    a.K = K;
-    a.T = T;
-    a.P = P;
-    a.nb = p.nb;
-    a.npb = p.npb;
-    a.tpc = p.tpc;
-    a.part = static_cast<double*>(workspace);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const dim3 grid((unsigned)(p.npb * p.ntc));
-    if (precision == TDSE_F64)
+    if (precision == TDSE_F32) {
+        GramArgs g;
+        g.frames = static_cast<const float*>(frames);
+        g.w = weights;
+        g.dA = dA;
+        g.K = K;
+        g.T = T;
+        g.P = P;
+        g.nb = p.nb;
+        g.npb = p.npb;
+        g.tpc = p.tpc;
+        g.part = static_cast<double*>(workspace);
+        const bool vec = P % 4 == 0 && (reinterpret_cast<uintptr_t>(frames) & 15) == 0;
+        if (vec)
+            hipLaunchKernelGGL(dissim_gram_kernel<true>, grid, dim3(GTHREADS), 0, st, g);
+        else
+            hipLaunchKernelGGL(dissim_gram_kernel<false>, grid, dim3(GTHREADS), 0, st, g);
+    } else {
+        DissimArgs a;
+        a.frames = frames;
+        a.w = weights;
+        a.dA = dA;
+        a.K = K;
+        a.T = T;
+        a.P = P;
+        a.nb = p.nb;
+        a.npb = p.npb;
+        a.tpc = p.tpc;
+        a.part = static_cast<double*>(workspace);
         hipLaunchKernelGGL(dissim_kernel<double>, grid, dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(dissim_kernel<float>, grid, dim3(256), 0, st, a);
+    }
     if (hipGetLastError() != hipSuccess) return TDSE_ERR_DEVICE;
     const long kk = (long)K * K;
     const unsigned g = (unsigned)std::min<long>((kk + 255) / 256, 4096);

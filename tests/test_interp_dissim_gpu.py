@@ -109,9 +109,9 @@ def test_dissimilarity_matches_oracle(prec):
 
 
 def test_dissimilarity_keeps_close_pairs_accurate():
-    """Pairs that differ by 1e-4 of the signal: the sums of squared
-    differences keep their relative accuracy in FP32 (a Gram expansion in
-    FP32 would lose it to cancellation)."""
+    """Pairs that differ by 1e-4 of the signal keep their relative
+    accuracy (an FP32 Gram expansion would lose it to cancellation; the
+    library's FP64 expansion of shifted frames does not)."""
     K, T, P = 8, 3, 65536
     rng = np.random.default_rng(22)
     base = np.abs(rng.standard_normal((1, T, P)))
@@ -125,6 +125,47 @@ def test_dissimilarity_keeps_close_pairs_accurate():
     err = float(np.max(np.abs(d[off] - ref[off]) / ref[off]))
     say("close pairs max rel", err)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("K,T,P", [(300, 5, 999), (260, 4, 1024), (129, 2, 33), (1, 3, 7), (2, 1, 1)])
+def test_dissimilarity_blocks_and_tails(K, T, P):
+    """FP32 frames over several 128-trajectory blocks (off-diagonal and
+    ragged ones), pixel counts off the 4-pixel vectors and 32-pixel chunks,
+    and the degenerate single trajectory, frame and pixel."""
+    rng = np.random.default_rng(K * 1000 + P)
+    f = rng.uniform(0.0, 2.0, (K, T, P)).astype(np.float32).astype(np.float64)
+    w = rng.uniform(0.05, 0.2, T)
+    ref = oracle.dissimilarity(f, w, 0.25)
+    d = tdse.dissimilarity(torch.from_numpy(f).to("cuda", torch.float32), torch.from_numpy(w),
+                           0.25).cpu().numpy()
+    assert np.all(np.diag(d) == 0.0)
+    np.testing.assert_array_equal(d, d.T)
+    off = ~np.eye(K, dtype=bool)
+    if off.any():
+        say("blocks", K, T, P, "max rel", float(np.max(np.abs(d[off] - ref[off]) / ref[off])))
+    np.testing.assert_allclose(d, ref, rtol=1e-6, atol=0)
+
+
+def test_dissimilarity_of_repeated_and_shifted_trajectories():
+    """A trajectory repeated under another index is at distance ~0 (to
+    FP64 rounding of the norms, far below the FP32 resolution of the
+    frames), and a common offset of every frame leaves d unchanged."""
+    K, T, P = 40, 3, 4096
+    rng = np.random.default_rng(23)
+    # values on a 2^-20 grid, so that adding 4 below is exact in FP32
+    f = (np.floor(rng.uniform(0.0, 1.0, (K, T, P)) * 2.0**20) / 2.0**20).astype(np.float32)
+    f[17] = f[5]
+    w = np.full(T, 1.0 / T)
+    d = tdse.dissimilarity(torch.from_numpy(f).cuda(), torch.from_numpy(w), 1.0).cpu().numpy()
+    typical = float(np.median(d[~np.eye(K, dtype=bool)]))
+    say("repeated pair", d[5, 17], "typical", typical)
+    assert d[5, 17] <= 1e-6 * typical
+    # the offset is exact in FP32, so the differences are unchanged bit for bit
+    g = (f.astype(np.float64) + 4.0).astype(np.float32)
+    assert np.array_equal(g.astype(np.float64) - 4.0, f.astype(np.float64))
+    d2 = tdse.dissimilarity(torch.from_numpy(g).cuda(), torch.from_numpy(w), 1.0).cpu().numpy()
+    off = ~np.eye(K, dtype=bool)
+    np.testing.assert_allclose(d2[off], d[off], rtol=1e-12, atol=0)
 
 
 def test_dissimilarity_of_batch_records():

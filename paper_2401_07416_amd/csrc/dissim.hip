@@ -182,14 +182,13 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
 // pixels staged in LDS as FP64 rows; the squared norms come from the same
 // FP64 values as they are staged.
 constexpr int GB = 128;           // trajectories per block side
-constexpr int GPC = 64;           // pixels per LDS chunk
+constexpr int GPC = 32;           // pixels per LDS chunk
 constexpr int GLS = GPC + 2;      // LDS row stride in doubles (16-byte rows, spread banks)
 constexpr int GTHREADS = 512;
 static_assert(GPC % 4 == 0 && GB % (GTHREADS / (GPC / 4)) == 0 && GPC / 4 <= 64, "staging map");
 constexpr int GQ = GPC / 4;            // 4-pixel vectors per row and chunk
 constexpr int GRP = GTHREADS / GQ;     // rows staged per pass
 constexpr int GNP = GB / GRP;          // passes per side
-constexpr int GKU = 4;                 // MFMA steps unrolled per loop trip
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -221,9 +220,9 @@ __device__ __forceinline__ float4 load4(const float* row, long p0, long P) {
 // VEC: P is a multiple of 4 (whole float4 loads)
 template <bool VEC>
 __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
-    __shared__ __align__(16) double As[GB * GLS];
-    __shared__ __align__(16) double Bs[GB * GLS];
-    __shared__ double nrm[2 * GB];
+    __shared__ __align__(16) double As[2 * GB * GLS];
+    __shared__ __align__(16) double Bs[2 * GB * GLS];
+    __shared__ double nrm[2 * 2 * GB];
     const int q = blockIdx.x % a.npb;
     const int tc = blockIdx.x / a.npb;
     int bi, bj;
@@ -293,52 +292,76 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
         d[1] = make_double2(x2, x3);
     };
 
-    if (nch > 0) fetch(0);
-    for (long c = 0; c < nch; ++c) {
+    // a row's norm over the frame: its GQ quad lanes (adjacent lanes)
+    // combined by a butterfly, the same bits in each, into the frame's half
+    // of nrm (halves alternate with the frame, so that a wavefront still in
+    // the previous frame's end reads its own half)
+    auto frame_norms = [&](int f) {
+        double* nf = nrm + (f & 1) * 2 * GB;
 #pragma unroll
         for (int i = 0; i < GNP; ++i) {
-            stage(As, srow + GRP * i, ra[i], va[i], na[i]);
-            stage(Bs, srow + GRP * i, rb[i], vb[i], nbv[i]);
+            double x = na[i], y = nbv[i];
+#pragma unroll
+            for (int s = 1; s < GQ; s <<= 1) {
+                x += __shfl_xor(x, s);
+                y += __shfl_xor(y, s);
+            }
+            if (quad == 0) {
+                nf[srow + GRP * i] = x;
+                nf[GB + srow + GRP * i] = y;
+            }
+            na[i] = 0.0;
+            nbv[i] = 0.0;
         }
-        __syncthreads();
-        if (c + 1 < nch) fetch(c + 1);
-#pragma unroll GKU
+    };
+    auto stage_chunk = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < GNP; ++i) {
+            stage(As + buf * GB * GLS, srow + GRP * i, ra[i], va[i], na[i]);
+            stage(Bs + buf * GB * GLS, srow + GRP * i, rb[i], vb[i], nbv[i]);
+        }
+    };
+
+    // two LDS buffers: chunk c + 1 is staged into the other buffer while
+    // chunk c is contracted (late in it: its loads, issued a chunk ahead,
+    // have landed), one barrier per chunk
+    if (nch > 0) {
+        fetch(0);
+        stage_chunk(0);
+        if (nch > 1) fetch(1);
+    }
+    __syncthreads();
+    for (long c = 0; c < nch; ++c) {
+        const int cur = (int)(c & 1);
+        const double* Ac = As + cur * GB * GLS;
+        const double* Bc = Bs + cur * GB * GLS;
+        const bool frame_done = c % cpt == cpt - 1;
+#pragma unroll
         for (int kk = 0; kk < GPC / 4; ++kk) {
             double av[2], bv[4];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) av[m] = As[(wr + 16 * m + li) * GLS + 4 * kk + lk];
+            for (int m = 0; m < 2; ++m) av[m] = Ac[(wr + 16 * m + li) * GLS + 4 * kk + lk];
 #pragma unroll
-            for (int n = 0; n < 4; ++n) bv[n] = Bs[(wc + 16 * n + li) * GLS + 4 * kk + lk];
+            for (int n = 0; n < 4; ++n) bv[n] = Bc[(wc + 16 * n + li) * GLS + 4 * kk + lk];
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
                 for (int n = 0; n < 4; ++n)
                     g[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], g[m][n], 0, 0, 0);
-        }
-        const bool frame_done = c % cpt == cpt - 1;
-        if (frame_done) {
-            // a row's norm: its GQ quad lanes (adjacent lanes) combined
-            // by a butterfly, the same bits in each
-#pragma unroll
-            for (int i = 0; i < GNP; ++i) {
-                double x = na[i], y = nbv[i];
-#pragma unroll
-                for (int s = 1; s < GQ; s <<= 1) {
-                    x += __shfl_xor(x, s);
-                    y += __shfl_xor(y, s);
+            if (kk == GPC * 3 / 16) {
+                // the staged norms so far cover the frame's chunks up to c
+                if (frame_done) frame_norms((int)(c / cpt));
+                if (c + 1 < nch) {
+                    stage_chunk(cur ^ 1);
+                    if (c + 2 < nch) fetch(c + 2);
                 }
-                if (quad == 0) {
-                    nrm[srow + GRP * i] = x;
-                    nrm[GB + srow + GRP * i] = y;
-                }
-                na[i] = 0.0;
-                nbv[i] = 0.0;
             }
         }
         __syncthreads();
         if (frame_done) {
             const int f = (int)(c / cpt);
             const double wt = a.w[t0 + f];
+            const double* nf = nrm + (f & 1) * 2 * GB;
             // element r of a lane's accumulator is pair (4 r + lk, li) of the 16 x 16 tile
 #pragma unroll
             for (int m = 0; m < 2; ++m)
@@ -347,7 +370,7 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = wr + 16 * m + 4 * r + lk, col = wc + 16 * n + li;
-                        const double d2 = (nrm[row] + nrm[GB + col]) - 2.0 * g[m][n][r];
+                        const double d2 = (nf[row] + nf[GB + col]) - 2.0 * g[m][n][r];
                         const double v = wt * sqrt(a.dA * fmax(d2, 0.0));
                         g[m][n][r] = 0.0;
                         const int k = r0 + row, j = c0 + col;

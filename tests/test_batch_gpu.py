@@ -66,6 +66,25 @@ def test_batch_equals_single_runs(prec, form):
         assert m.detect().flux == pytest.approx(single.detect().flux, rel=1e-11, abs=1e-15)
 
 
+@pytest.mark.parametrize("form", ["two-step", "one-pass"])
+def test_preparing_a_batch_keeps_members_tiles(form):
+    """A batch's tile is the batch's: after prepare() each member still
+    reports (and steps alone with) the tile it had before."""
+    steps = 20
+    ws = small_set(steps)
+    b = tdse.batch_from_workloads(ws, precision="f32", steps=steps)
+    before = [m.get_tile() for m in b.members]
+    if form == "two-step":
+        b.set_two_step(True, tx=16, zc=16, prefetch=True, rows=1, threads=1024)
+    else:
+        b.set_two_step(False)
+        b.set_tile(fused_rows=2, fused_zc=8, prefetch=False, threads=64)
+    b.prepare()
+    after = [m.get_tile() for m in b.members]
+    for x, y in zip(before, after):
+        assert {f: getattr(x, f) for f, _ in x._fields_} == {f: getattr(y, f) for f, _ in y._fields_}
+
+
 def test_batch_member_matches_oracle():
     steps = 40
     ws = small_set(steps)

@@ -146,6 +146,29 @@ def test_dissimilarity_blocks_and_tails(K, T, P):
     np.testing.assert_allclose(d, ref, rtol=1e-6, atol=0)
 
 
+def test_dissimilarity_full_size_sampled():
+    """The benchmark's size (879 trajectories x 77 frames x 128^2 pixels,
+    seeded uniform FP32 frames, the launch the benchmark times): sampled
+    trajectories across the 128-trajectory blocks (first, last, both sides
+    of block edges) against the oracle run on those trajectories alone."""
+    K, T, P = 879, 77, 128 * 128
+    g = torch.Generator(device="cuda")
+    g.manual_seed(16)
+    frames = torch.rand((K, T, P), generator=g, device="cuda", dtype=torch.float32)
+    w = np.full(T, 1.0 / T)
+    d = tdse.dissimilarity(frames, torch.from_numpy(w), 0.04).cpu().numpy()
+    assert np.all(np.diag(d) == 0.0)
+    np.testing.assert_array_equal(d, d.T)
+    pick = [0, 1, 127, 128, 255, 256, 500, 639, 640, 767, 768, 877, 878]
+    sub = frames[pick].double().cpu().numpy()
+    del frames
+    ref = oracle.dissimilarity(sub, w, 0.04)
+    got = d[np.ix_(pick, pick)]
+    off = ~np.eye(len(pick), dtype=bool)
+    say("full size sampled max rel", float(np.max(np.abs(got[off] - ref[off]) / ref[off])))
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=0)
+
+
 def test_dissimilarity_of_repeated_and_shifted_trajectories():
     """A trajectory repeated under another index is at distance ~0 (to
     FP64 rounding of the norms, far below the FP32 resolution of the

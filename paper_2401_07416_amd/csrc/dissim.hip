@@ -177,14 +177,17 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
 // order of the distances themselves for trajectories that are close to one
 // another (the case a dissimilarity has to resolve), so the cancellation in
 // the expansion costs a few FP64 ulps of |x|^2, not the FP32 cross term's
-// 1e-7.  The Gram block of a workgroup (GB x GB pairs, eight wavefronts of
-// 32 x 64 pairs) accumulates on v_mfma_f64_16x16x4_f64 over chunks of GPC
-// pixels staged in LDS as FP64 rows; the squared norms come from the same
-// FP64 values as they are staged.
+// 1e-7.  The Gram block of a workgroup (GB x GB pairs, sixteen wavefronts
+// of 32 x 32 pairs: four per SIMD) accumulates on v_mfma_f64_16x16x4_f64
+// over chunks of GPC pixels staged in LDS as FP64 rows; the squared norms
+// come from the same FP64 values as they are staged.
 constexpr int GB = 128;           // trajectories per block side
 constexpr int GPC = 32;           // pixels per LDS chunk
 constexpr int GLS = GPC + 2;      // LDS row stride in doubles (16-byte rows, spread banks)
-constexpr int GTHREADS = 512;
+constexpr int GTHREADS = 1024;
+constexpr int GWN = GTHREADS == 1024 ? 2 : 4;  // 16-column tiles per wavefront (2 row tiles)
+constexpr int GWC = GB / (16 * GWN);            // wavefronts across a block's columns
+static_assert((GB / 32) * GWC * 64 == GTHREADS, "wavefront grid");
 static_assert(GPC % 4 == 0 && GB % (GTHREADS / (GPC / 4)) == 0 && GPC / 4 <= 64, "staging map");
 constexpr int GQ = GPC / 4;            // 4-pixel vectors per row and chunk
 constexpr int GRP = GTHREADS / GQ;     // rows staged per pass
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
     const int r0 = bi * GB, c0 = bj * GB;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
-    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 64;  // the wavefront's 32 x 64 pairs
+    const int wr = (wv / GWC) * 32, wc = (wv % GWC) * 16 * GWN;  // the wavefront's 32 x 16 GWN pairs
     const int li = lane & 15, lk = lane >> 4;
     const int t0 = tc * a.tpc;
     const int t1 = min(t0 + a.tpc, a.T);
@@ -261,11 +264,11 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
         rc = load4<VEC>(a.frames + off, p0, a.P);   // the shift: trajectory 0
     };
 
-    dbl4 g[2][4];
+    dbl4 g[2][GWN];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) g[m][n] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int n = 0; n < GWN; ++n) g[m][n] = dbl4{0.0, 0.0, 0.0, 0.0};
     // the time sums live in this workgroup's own slab of the partials (the
     // pairs k <= j of its block), one read-modify-write per frame
     double* out = a.part + (long)tc * a.K * a.K;
@@ -338,15 +341,15 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
         const bool frame_done = c % cpt == cpt - 1;
 #pragma unroll
         for (int kk = 0; kk < GPC / 4; ++kk) {
-            double av[2], bv[4];
+            double av[2], bv[GWN];
 #pragma unroll
             for (int m = 0; m < 2; ++m) av[m] = Ac[(wr + 16 * m + li) * GLS + 4 * kk + lk];
 #pragma unroll
-            for (int n = 0; n < 4; ++n) bv[n] = Bc[(wc + 16 * n + li) * GLS + 4 * kk + lk];
+            for (int n = 0; n < GWN; ++n) bv[n] = Bc[(wc + 16 * n + li) * GLS + 4 * kk + lk];
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n)
+                for (int n = 0; n < GWN; ++n)
                     g[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], g[m][n], 0, 0, 0);
             if (kk == GPC * 3 / 16) {
                 // the staged norms so far cover the frame's chunks up to c
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n)
+                for (int n = 0; n < GWN; ++n)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = wr + 16 * m + 4 * r + lk, col = wc + 16 * n + li;
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n)
+        for (int n = 0; n < GWN; ++n)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int k = r0 + wr + 16 * m + 4 * r + lk, j = c0 + wc + 16 * n + li;

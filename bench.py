@@ -14,13 +14,18 @@ before the timed region starts.
 roofline: the dominant kernel is the launch kind that takes most of the
 timed region (the two-step sweep by default; the one-pass step or the
 half-step kernels when selected); its algorithmic bytes per launch are 20 B
-per cell in FP32 (read R, I, V once, write R, I once: two steps for the
-sweep, one for the one-pass step; 16 B for a half-step), divided by its
-average launch time measured with HIP events around each launch inside the
-timed region, on the stream the kernels run on.  traffic: calibrated
-rocprofv3 FETCH_SIZE + WRITE_SIZE per launch from profiles/, while the
-kernel sources and tile match.  cpu_baseline: the FP64 oracle timed on this
-host's cores on a bounded slab of the same workload.
+per cell in FP32, 40 B in FP64 (read R, I, V once, write R, I once: two
+steps for the sweep, one for the one-pass step; 16 / 32 B for a half-step),
+divided by its average launch time measured with HIP events around each
+launch inside the timed region, on the stream the kernels run on.  Launches
+that also write a detection record are timed apart and reported beside it.
+traffic: calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE per launch from
+profiles/, while the kernel sources and tile match.  The FP64 legs carry
+the same block for their own dominant kernel.  cpu_baseline: the FP64
+oracle on this host's physical cores (OMP_PROC_BIND=close, in a child
+process that never touches the GPU) on the 256x256x512 surface grid, 200
+timed steps after 10 warm-up steps, with a one-core leg and the 64^3 free
+packet in full beside it.
 """
 from __future__ import annotations
 
@@ -50,9 +55,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the FP64, adjoint and batched measurements")
-    p.add_argument("--cpu-seconds", type=float, default=15.0,
-                   help="target CPU time of the timed oracle sample")
-    p.add_argument("--cpu-planes", type=int, default=48)
+    p.add_argument("--cpu-steps", type=int, default=200,
+                   help="timed oracle steps on the 256x256x512 grid (after 10 warm-up steps)")
+    p.add_argument("--cpu-serial-steps", type=int, default=20,
+                   help="timed one-core oracle steps on the same grid (after 1 warm-up step)")
+    p.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--no-timing", action="store_true",
                    help="do not bracket launches with events (value only)")
     p.add_argument("--copy-probe", action="store_true",
@@ -91,59 +98,204 @@ def traffic_from_profiles(workload_name, precision, kind, tile):
     return float(t["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(w, seconds, planes):
-    """Time the FP64 oracle on a slab of `planes` z-planes of the workload
-    (the windowed potential and packet of the full grid, zero outside the
-    slab) for about `seconds` of wall time, on the host threads the oracle
-    is given (at most 16, the CPU share of one GPU)."""
+CPU_SHARE = 16   # host cores one GPU of the box may use
+
+
+def host_cpu():
+    """lscpu facts of this host and the physical cores of this process's
+    affinity mask."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                             "CPU(s)"):
+                info[k.strip()] = v.strip()
+    except Exception as e:  # context only
+        info["error"] = repr(e)
+    cpus = sorted(os.sched_getaffinity(0))
+    phys = len(cpus)
+    try:
+        out = subprocess.run(["lscpu", "-p=CPU,CORE,SOCKET"], capture_output=True, text=True,
+                             timeout=30).stdout
+        core_of = {}
+        for line in out.splitlines():
+            if line and not line.startswith("#"):
+                c, core, sock = line.split(",")[:3]
+                core_of[int(c)] = (sock, core)
+        phys = len({core_of.get(c, ("?", c)) for c in cpus})
+    except Exception:
+        pass
+    info["cpus_in_affinity"] = len(cpus)
+    info["physical_cores_in_affinity"] = phys
+    return info, phys
+
+
+def cpu_child(a):
+    """The oracle timings (run in a child process whose OpenMP runtime was
+    started with OMP_PROC_BIND=close): prints one JSON line."""
     import numpy as np
 
     import oracle
-    threads = min(16, len(os.sched_getaffinity(0)))
-    oracle.set_threads(threads)
-    g = oracle.Grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, bc=w.bc)
-    k0c = int(round(w.r0[2] / w.dz)) - planes // 2
-    size = (w.nx, w.ny, planes)
-    V = oracle.potential_window(g, w.atoms, (0, 0, k0c), size, soft=w.soft, cutoff=w.cutoff,
-                                kappa=w.kappa, a0=w.a0, screened=w.screened)
-    # time step of the full grid: the slab holds the deepest wells
-    Vs = oracle.potential_window(g, w.atoms, (0, 0, int(30.5 / w.dz) - 8), (w.nx, w.ny, 40),
-                                 soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
+    from paper_2401_07416_amd import workloads
+
+    def setup(w):
+        g = oracle.Grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, bc=w.bc)
+        if w.atoms is not None and len(w.atoms):
+            V = oracle.potential(g, w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
                                  screened=w.screened)
-    gs = oracle.Grid(w.nx, w.ny, 40, w.dx, w.dy, w.dz, w.hbar, w.mass)
-    dt = w.dt_frac * w.hbar / oracle.emax(gs, Vs)
-    k0 = oracle.wavevector(w.energy, w.hbar, w.mass) * np.array(w.k_dir)
-    R, I = oracle.init_gaussian_window(g, w.r0, k0, w.sigma, dt, (0, 0, k0c), size)
-    gw = oracle.Grid(w.nx, w.ny, planes, w.dx, w.dy, w.dz, w.hbar, w.mass, bc=(0, 0, 1))
-    s = oracle.Sim(gw, V, R, I, dt, k_det=planes // 2)
-    t0 = time.perf_counter()
-    s.step(2)
-    per = (time.perf_counter() - t0) / 2
-    steps = max(2, int(seconds / per))
-    t0 = time.perf_counter()
-    s.step(steps)
-    el = time.perf_counter() - t0
+        else:
+            V = np.zeros(g.shape)
+        dt = w.dt_frac * w.hbar / oracle.emax(g, V)
+        W = oracle.cap_quadratic(w.nz, *w.cap) if w.cap else None
+        k0 = (np.array(w.k0, dtype=np.float64) if w.k0 is not None
+              else oracle.wavevector(w.energy, w.hbar, w.mass) * np.array(w.k_dir))
+        R, I = oracle.init_gaussian(g, w.r0, k0, w.sigma, dt)
+        s = oracle.Sim(g, V, R, I, dt, W=W, k_det=w.k_det)
+        return s
+
+    def timed(s, warm, steps):
+        s.step(warm)
+        t0 = time.perf_counter()
+        s.step(steps)
+        return time.perf_counter() - t0
+
     threads = oracle.get_threads()
-    cells = w.nx * w.ny * planes
-    out = {"value": cells * steps / el / 1e9, "unit": "Gcell-steps/s", "cores": threads,
-           "kind": "oracle",
-           "sample": f"FP64 oracle, {w.nx}x{w.ny}x{planes}-plane slab of the {w.name} grid "
-                     f"around the packet, {steps} steps, {el:.1f} s",
-           "ns_per_cell_step": el / (cells * steps) * 1e9}
-    # the serial analogue (one core), on the same slab for about a quarter of
-    # the time
+    out = {"threads": threads}
+    w = workloads.c2_surface()
+    s = setup(w)
+    el = timed(s, 10, a.cpu_steps)
+    out["c2"] = {"cells": w.cells, "steps": a.cpu_steps, "warmup": 10, "s": el}
     oracle.set_threads(1)
-    t0 = time.perf_counter()
-    s.step(1)
-    per1 = time.perf_counter() - t0
-    steps1 = max(1, int(seconds / 4 / per1))
-    t0 = time.perf_counter()
-    s.step(steps1)
-    el1 = time.perf_counter() - t0
+    el1 = timed(s, 1, a.cpu_serial_steps)
+    out["c2_serial"] = {"cells": w.cells, "steps": a.cpu_serial_steps, "warmup": 1, "s": el1}
     oracle.set_threads(threads)
-    out["single_core"] = {"value": cells * steps1 / el1 / 1e9, "cores": 1, "steps": steps1,
-                          "ns_per_cell_step": el1 / (cells * steps1) * 1e9}
+    del s
+    w1 = workloads.c1_free_gaussian()
+    s1 = setup(w1)
+    el = timed(s1, 0, w1.steps)
+    out["c1"] = {"cells": w1.cells, "steps": w1.steps, "warmup": 0, "s": el}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(a, gpu_value, gpu_fp64_c2):
+    """Time the FP64 oracle on this host: all physical cores of the
+    process's affinity mask (at most the 16-core share of one GPU) with
+    OMP_PROC_BIND=close on the 256x256x512 surface grid, one core on the
+    same grid, and the 64^3 free packet in full."""
+    import subprocess
+    info, phys = host_cpu()
+    threads = max(1, min(phys, CPU_SHARE))
+    env = dict(os.environ, OMP_PROC_BIND="close", OMP_PLACES="cores", OMP_NUM_THREADS=str(threads))
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--cpu-steps", str(a.cpu_steps),
+           "--cpu-serial-steps", str(a.cpu_serial_steps)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle child failed ({r.returncode}): {r.stderr[-2000:]}")
+    t = json.loads(r.stdout.strip().splitlines()[-1])
+
+    def rate(x):
+        cs = x["cells"] * x["steps"]
+        return cs / x["s"] / 1e9, x["s"] / cs * 1e9
+
+    v, ns = rate(t["c2"])
+    v1, ns1 = rate(t["c2_serial"])
+    vc1, nsc1 = rate(t["c1"])
+    out = {"value": round(v, 4), "unit": "Gcell-steps/s", "cores": t["threads"], "kind": "oracle",
+           "sample": (f"FP64 oracle on the surface-256x256x512 grid (the surface-diffraction "
+                      f"workload at its 256x256x512 size), {t['c2']['steps']} timed steps after "
+                      f"{t['c2']['warmup']} warm-up steps, {t['c2']['s']:.1f} s, "
+                      f"{t['threads']} threads bound with OMP_PROC_BIND=close, OMP_PLACES=cores"),
+           "ns_per_cell_step": round(ns, 4), "host": info,
+           "single_core": {"value": round(v1, 5), "cores": 1, "steps": t["c2_serial"]["steps"],
+                           "s": round(t["c2_serial"]["s"], 2), "ns_per_cell_step": round(ns1, 3)},
+           "c1_free_gaussian_64cubed": {"value": round(vc1, 4), "cores": t["threads"],
+                                        "steps": t["c1"]["steps"], "s": round(t["c1"]["s"], 3),
+                                        "ns_per_cell_step": round(nsc1, 4),
+                                        "note": "2 MB per array: cache-resident"},
+           "speedup_gpu_over_cpu": round(gpu_value / v, 1),
+           "speedup_note": "headline FP32 value over the FP64 oracle on all cores"}
+    if gpu_fp64_c2:
+        out["speedup_gpu_fp64_over_cpu_same_grid"] = round(gpu_fp64_c2 / v, 1)
+        out["speedup_gpu_fp64_over_single_core_same_grid"] = round(gpu_fp64_c2 / v1, 1)
+    out["paper_context"] = {
+        "gpu_over_serial_cpu": 350, "gpu_over_multicore_cpu": 5.5,
+        "hardware": "Quadro K620 vs one core of a 1.6 GHz Xeon E5-2603 v3, and vs 16 two-thread "
+                    "Xeon Gold 6242 cores; precision not stated",
+        "ns_per_cell_step": {"k620": 6, "serial": 2000, "multicore": 30}}
     return out
+
+
+# algorithmic words per cell of one launch: a half-step reads the stencil
+# array, the updated array and V and writes the updated array (4 words); the
+# one-pass step reads R, I, V and writes R, I (5 words, one step); the
+# two-step sweep moves the same 5 words for two steps
+WORDS = {"half_i": 4, "half_r": 4, "fused": 5, "two_step": 5}
+STEPS_PER_LAUNCH = {"half_i": 0.5, "half_r": 0.5, "fused": 1, "two_step": 2}
+# a step of the two-pass form is both half-steps (8 words)
+WORDS_PER_CELL_STEP = {"half_i": 8, "half_r": 8, "fused": 5, "two_step": 2.5}
+KERNEL_NAMES = {"half_i": "half_step eq.(9) imaginary", "half_r": "half_step eq.(8) real",
+                "fused": "fused_step eqs.(9)+(8) one-pass",
+                "two_step": "fused2 two-step sweep eqs.(9)+(8)+(9)+(8)"}
+
+
+def roofline_of(kt, cells, prec, workload_name, tile):
+    """Roofline block of the dominant launch kind of a split timing read
+    (kinds without a record; those with one are reported apart)."""
+    es = 8 if prec == "f64" else 4
+    plain = {k: v for k, v in kt.items() if not k.endswith("_rec")}
+    dom = max(plain, key=lambda k: plain[k][0])
+    tot_ms, launches = plain[dom]
+    if not launches:
+        return None
+    avg = tot_ms / launches
+    alg_bytes = WORDS[dom] * es * cells
+    achieved = alg_bytes / (avg * 1e-3) / 1e9
+    traffic = traffic_from_profiles(workload_name, prec, dom, tile)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": KERNEL_NAMES[dom], "avg_launch_ms": round(avg, 5),
+            "alg_bytes_per_launch": alg_bytes,
+            "alg_bytes_per_cell_step": WORDS_PER_CELL_STEP[dom] * es,
+            "launches": {k: v[1] for k, v in kt.items()},
+            "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()}}
+    rec = kt.get(dom + "_rec")
+    if rec and rec[1]:
+        ravg = rec[0] / rec[1]
+        roof["record_launch_avg_ms"] = round(ravg, 5)
+    if traffic is not None:
+        # the memory-side rate: counted bytes per launch over this run's
+        # average launch time
+        roof["traffic_gbs"] = round(traffic / (avg * 1e-3) / 1e9, 1)
+        roof["traffic_frac"] = round(traffic / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return roof
+
+
+def record_cost(sim, w, intervals=4):
+    """Cost of the detection record (eq. (15)) on the two-step plan: a
+    window of whole record intervals timed launch by launch, the launches
+    that write a record against those that do not."""
+    h = w.record_every
+    sim.timing_read_split()
+    sim.set_timing(True)
+    sim.step(intervals * h)
+    sim.set_timing(False)
+    kt = sim.timing_read_split()
+    plain = {k: v for k, v in kt.items() if not k.endswith("_rec") and v[1]}
+    dom = max(plain, key=lambda k: plain[k][0])
+    rec = kt[dom + "_rec"]
+    if not rec[1]:
+        return None
+    pavg = plain[dom][0] / plain[dom][1]
+    ravg = rec[0] / rec[1]
+    launches_per_interval = h / STEPS_PER_LAUNCH[dom]
+    return {"record_every": h, "kernel": KERNEL_NAMES[dom], "record_launches": rec[1],
+            "plain_launches": plain[dom][1], "record_launch_avg_ms": round(ravg, 5),
+            "plain_launch_avg_ms": round(pavg, 5),
+            "extra_ms_per_record": round(ravg - pavg, 5),
+            "overhead_frac_of_interval": round((ravg - pavg) / (pavg * launches_per_interval), 5)}
 
 
 def time_steps(sim, n):
@@ -158,20 +310,30 @@ def time_steps(sim, n):
     return e0.elapsed_time(e1)
 
 
-def secondary_fp64(steps=400):
-    """FP64 throughput on the 256x256x512 surface grid (one-pass step)."""
-    from paper_2401_07416_amd import tdse, tuning, workloads
-    w = workloads.c2_surface()
+def secondary_fp64(w, steps):
+    """FP64 throughput in the tuned tile of the grid, with the roofline of
+    its dominant kernel (launch-by-launch HIP events on the handle's
+    stream)."""
+    from paper_2401_07416_amd import tdse, tuning
     sim = tdse.sim_from_workload(w, precision="f64", steps=steps + 20)
     t = tuning.tile_for(w, "f64")
     if t:
         sim.set_tile(**t)
     sim.step(20)
+    sim.timing_read_split()
+    sim.set_timing(True)
     ms = time_steps(sim, steps)
+    sim.set_timing(False)
+    kt = sim.timing_read_split()
     v = w.cells * steps / (ms * 1e-3) / 1e9
-    return {"workload": w.name + " FP64", "value": round(v, 2), "unit": "Gcell-steps/s",
-            "ms_per_step": round(ms / steps, 4),
-            "hbm_gbs_alg": round(v * 40, 1), "steps": steps}
+    tile = sim.get_tile().as_dict()
+    out = {"workload": w.name + " FP64", "value": round(v, 2), "unit": "Gcell-steps/s",
+           "ms_per_step": round(ms / steps, 4), "steps": steps, "tile": tile,
+           "roofline": roofline_of(kt, w.cells, "f64", w.name, tile)}
+    del sim
+    import torch
+    torch.cuda.empty_cache()
+    return out
 
 
 def secondary_interp():
@@ -357,7 +519,7 @@ def secondary_adjoint():
             "grad_finite": bool(torch.isfinite(gV).all())}
 
 
-def secondary_batch(n_configs=64, batch_steps=400, single_steps=100):
+def secondary_batch(n_configs=64, batch_steps=1000, single_steps=100):
     """The 64 uneven film grids stepped as one batch (one launch per step,
     a graph per 50-step record interval) against the same grids run one at
     a time with the plain path, FP32."""
@@ -412,6 +574,9 @@ def copy_probe():
 
 def main():
     a = parse()
+    if a.cpu_child:
+        cpu_child(a)
+        return
     if a.copy_probe:
         copy_probe()
         return
@@ -426,7 +591,9 @@ def main():
     w = workloads.ALL[a.workload]()
     prec = a.precision
     total = a.warmup + a.steps
-    sim = tdse.sim_from_workload(w, precision=prec, steps=total)
+    # capacity for the record-cost window after the timed region
+    rec_window = 4 * w.record_every if w.record_every else 0
+    sim = tdse.sim_from_workload(w, precision=prec, steps=total + rec_window)
     tile = json.loads(a.tile) if a.tile else tuning.tile_for(w, prec)
     if tile is not None:
         sim.set_tile(**tile)
@@ -434,7 +601,7 @@ def main():
     torch.cuda.synchronize()
     sim.step(a.warmup)
     torch.cuda.synchronize()
-    sim.timing_read()
+    sim.timing_read_split()
     sim.set_timing(not a.no_timing)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -447,41 +614,14 @@ def main():
     wall = time.perf_counter() - wall0
     ms = e0.elapsed_time(e1)
     sim.set_timing(False)
-    kt = sim.timing_read()
+    kt = sim.timing_read_split()
     det = sim.detect()
     cells = w.cells
     value = cells * a.steps / (ms * 1e-3) / 1e9
-    es = 8 if prec == "f64" else 4
-    # algorithmic bytes per launch: a half-step reads the stencil array, the
-    # updated array and V and writes the updated array (4 words per cell); the
-    # one-pass step reads R, I, V and writes R, I (5 words per cell); the
-    # two-step sweep moves the same 5 words per cell for two steps
-    words = {"half_i": 4, "half_r": 4, "fused": 5, "two_step": 5}
-    names = {"half_i": "half_step eq.(9) imaginary", "half_r": "half_step eq.(8) real",
-             "fused": "fused_step eqs.(9)+(8) one-pass",
-             "two_step": "fused2 two-step sweep eqs.(9)+(8)+(9)+(8)"}
-    roof = None
-    dom = max(kt, key=lambda k: kt[k][0])
-    tot_ms, launches = kt[dom]
-    if launches:
-        avg = tot_ms / launches
-        alg_bytes = words[dom] * es * cells
-        achieved = alg_bytes / (avg * 1e-3) / 1e9
-        traffic = traffic_from_profiles(w.name, prec, dom, t.as_dict())
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "frac_at_32B_per_cell_step": round(value * 32 / HBM_PEAK_GBS, 4),
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": names[dom], "avg_launch_ms": round(avg, 5),
-                "alg_bytes_per_launch": alg_bytes,
-                "launches": {k: v[1] for k, v in kt.items()},
-                "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()}}
-        if traffic is not None:
-            # the memory-side rate: counted bytes per launch over this run's
-            # average launch time
-            roof["traffic_gbs"] = round(traffic / (avg * 1e-3) / 1e9, 1)
-            roof["traffic_frac"] = round(traffic / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    roof = None if a.no_timing else roofline_of(kt, cells, prec, w.name, t.as_dict())
     # algorithmic bytes per cell-step of the launches the timed steps ran
-    alg_words = sum(words[k] * kt[k][1] for k in kt)
+    es = 8 if prec == "f64" else 4
+    alg_words = sum(WORDS[k.replace("_rec", "")] * v[1] for k, v in kt.items())
     bytes_per_cell_step = es * alg_words / max(1, a.steps)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-steps/s", "n_gpus": 1,
@@ -499,6 +639,15 @@ def main():
         "hbm_bytes_per_cell_step_alg": bytes_per_cell_step,
         "hbm_gbs_whole_step": round(value * bytes_per_cell_step, 1),
     }
+    if roof is not None and rec_window:
+        # the records (eq. (15), every h steps) cost, measured on a window of
+        # whole record intervals after the timed region
+        try:
+            out["record_cost"] = record_cost(sim, w)
+        except Exception as e:  # measurement context only
+            out["record_cost"] = {"error": repr(e)}
+    del sim
+    torch.cuda.empty_cache()
     if roof is not None:
         # the practical ceiling: streaming kernels with the copy's and the
         # one-pass step's mix of read and written streams, 1 GiB per stream
@@ -510,9 +659,12 @@ def main():
         except Exception as e:  # measurement context only
             roof["practical"] = {"error": str(e)}
         torch.cuda.empty_cache()
+    fp64_c2 = None
     if not a.no_secondary:
         sec = {}
-        for name, fn in (("fp64", secondary_fp64), ("adjoint", secondary_adjoint),
+        for name, fn in (("fp64", lambda: secondary_fp64(workloads.c2_surface(), 400)),
+                         ("fp64_headline_grid", lambda: secondary_fp64(workloads.c3_headline(), 100)),
+                         ("adjoint", secondary_adjoint),
                          ("batched", secondary_batch), ("interpolation", secondary_interp),
                          ("dissimilarity", secondary_dissim), ("paper_setup", secondary_paper),
                          ("shard_share", secondary_shard)):
@@ -520,13 +672,11 @@ def main():
                 sec[name] = fn()
             except Exception as ex:  # reported, never hidden
                 sec[name] = {"error": repr(ex)}
+            torch.cuda.empty_cache()
         out["secondary"] = sec
+        fp64_c2 = sec["fp64"].get("value")
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, a.cpu_planes)
-        out["cpu_baseline"]["speedup_gpu_over_cpu"] = round(value / out["cpu_baseline"]["value"], 1)
-        sc = out["cpu_baseline"]["single_core"]
-        sc["speedup_gpu_over_single_core"] = round(value / sc["value"], 1)
-        sc["paper_speedup_over_serial_cpu"] = 350
+        out["cpu_baseline"] = cpu_baseline(a, value, fp64_c2)
     print(json.dumps(out), flush=True)
 
 

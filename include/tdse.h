@@ -51,9 +51,15 @@
  *  - Threads: a handle is not thread-safe; distinct handles are independent.
  *  - Units: the caller chooses them through hbar and mass (atomic units:
  *    hbar = m = 1; eV-Angstrom-fs: hbar = 0.6582119569, m = hbar^2/7.619964).
- *  - Supported x extents: nx = W * G * L with W in {1, 2, 4} (FP32) or
- *    {1, 2} (FP64), G in {1, 2, 4, 8}, L <= 64 lanes; other nx return
- *    TDSE_ERR_UNSUPPORTED from tdse_create.
+ *  - Extents: any nx, ny <= 2^24 and nz <= 65535 (each <= 2^20 as a
+ *    description), with one z plane below 0x7ffffff0 bytes (nx ny x 4 in
+ *    FP32, x 8 in FP64: the kernels keep 32-bit byte offsets within a
+ *    plane); larger planes return TDSE_ERR_UNSUPPORTED from
+ *    tdse_validate_desc and tdse_create.  Where nx = W G L (W in {1, 2, 4}
+ *    floats or {1, 2} doubles, G in {1, 2, 4, 8}, L <= 64 lanes) the
+ *    half-steps spread a row over one wavefront; other nx take a half-step
+ *    kernel for any width (the same bits, slower), and the one-pass and
+ *    two-step kernels tile x either way.
  */
 #ifndef TDSE_H
 #define TDSE_H
@@ -309,7 +315,10 @@ tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2);
  *   r <- A r - G (B i_t);  i <- A i_t;  then record injections of level n,
  * G X = -(cx dxx + cy dyy + cz dzz) X + cv V X, A = diag(ca_k),
  * B = diag(cb_k).  In FP32 dL/dV is summed per segment in FP32 and folded
- * into FP64.  The handle's state is left at level n_steps.  Synchronises. */
+ * into FP64.  The handle's state is left at level n_steps.  Synchronises.
+ * TDSE_ERR_UNSUPPORTED where nx has no layout over 64 lanes and the
+ * one-pass reverse step does not fit either (no tdse_bind_pingpong, or
+ * whole rows beyond 256 vectors). */
 tdse_status tdse_adjoint_workspace_size(const tdse_desc* d, int64_t n_steps, int32_t ckpt_every,
                                         size_t* bytes);
 tdse_status tdse_bind_adjoint(tdse_handle h, void* adj_ws, size_t bytes, int64_t n_steps,
@@ -344,9 +353,16 @@ tdse_status tdse_potential_vjp(tdse_handle h, const tdse_atom* atoms, int64_t n,
  * tdse_batch_set_tile: one-pass tile shared by the members (fused_rows 2, 3,
  * 4 or 6; fused_zc >= 1; prefetch flag; threads per workgroup 64, 128 or
  * 256); invalidates a prepared batch.
- * tdse_batch_prepare: all members at the same record level; builds the
- * device tables (a few KB, allocated here, freed by destroy or the next
- * prepare) and captures the graph of one interval.
+ * tdse_batch_workspace_size / tdse_batch_bind_workspace: the device memory
+ * of the batch's tables (per-member kernel and finalisation arguments,
+ * workgroup starts, the record counter: about 1 KB per member), owned by
+ * the caller, 256-byte aligned, bound before tdse_batch_prepare and valid
+ * until the batch is destroyed or another workspace is bound (NULL
+ * unbinds; binding drops a prepared graph).  TDSE_ERR_ARG for a short or
+ * misaligned workspace.
+ * tdse_batch_prepare: all members at the same record level; writes the
+ * tables into the bound workspace (TDSE_ERR_STATE without one) and captures
+ * the graph of one interval; allocates no device memory.
  * tdse_batch_run: n steps, a multiple of the interval; asynchronous.
  * tdse_batch_status: synchronise; per_config[i] = tdse_detect's status of
  * member i (TDSE_ERR_NONFINITE flags a configuration whose sums went
@@ -370,6 +386,8 @@ tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_
  * into their bound arrays. */
 tdse_status tdse_batch_set_two_step(tdse_batch b, int32_t enable, int32_t tx, int32_t rows,
                                     int32_t zc, int32_t prefetch, int32_t threads);
+tdse_status tdse_batch_workspace_size(tdse_batch b, size_t* bytes);
+tdse_status tdse_batch_bind_workspace(tdse_batch b, void* workspace, size_t bytes);
 tdse_status tdse_batch_prepare(tdse_batch b);
 tdse_status tdse_batch_run(tdse_batch b, int64_t n);
 tdse_status tdse_batch_status(tdse_batch b, int32_t* per_config);
@@ -384,6 +402,11 @@ tdse_status tdse_batch_destroy(tdse_batch b);
  * clears them. */
 tdse_status tdse_set_timing(tdse_handle h, int32_t enable);
 tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count);
+/* The same with the launches that write a detection record (eq. (15))
+ * kept apart: ms[8], count[8], kinds 0-3 as above for launches without a
+ * record, 4 + kind for those with one (the eq. (8) half-step, one-pass step
+ * or two-step sweep whose last level is recorded).  Synchronises; clears. */
+tdse_status tdse_timing_read_split(tdse_handle h, double* ms, int64_t* count);
 
 /* Trajectory dissimilarity, eq. (16) (section 3.2): for trajectories k, j
  * the time average over [t0, t1] of the L2 distance between their
@@ -456,7 +479,11 @@ tdse_status tdse_hbm_probe(int32_t kind, void* const* bufs, int64_t n, int32_t g
  * (rows, threads) pair without a kernel or a tile that does not fit.
  *
  * tdse_create picks defaults; tdse_set_tile checks and replaces them.  The
- * last five fields are read-only. */
+ * last five fields are read-only; vec_groups and lanes are 0 where nx has
+ * no layout over 64 lanes (the any-width half-step kernel runs).  fused != 0
+ * with a one-pass band that does not fit (whole x rows in LDS: nx / W <=
+ * fused_threads) is accepted together with two_step: the sweep then takes
+ * the step pairs and half-steps the single steps. */
 typedef struct tdse_tile {
     int32_t rows, waves, zc;
     int32_t fused, fused_rows, fused_zc, fused_prefetch, graph, fused_threads;
@@ -468,13 +495,23 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out);
 
 /* Tile autotuner: times a built-in list of candidate tiles on the handle's
  * own grid and state (flags: bit 0 two-pass, bit 1 one-pass, bit 2 two-step
- * sweep; 0 = all; the one-pass and two-step candidates need
+ * sweep; none of the three = all; the one-pass and two-step candidates need
  * tdse_bind_pingpong), each for 2 warm-up and `steps` timed steps with HIP
  * events on the handle's stream, without records; keeps the fastest, sets
  * it and returns it in *out.  The state is spent: afterwards the handle
  * needs tdse_init_gaussian or tdse_set_state before tdse_step
  * (TDSE_ERR_STATE until then).  TDSE_ERR_STATE without a state, with
- * pending sums or with an adjoint bound. */
+ * pending sums or with an adjoint bound; TDSE_ERR_ARG for unknown flag bits.
+ *
+ * Cache: when the environment variable TDSE_TUNE_CACHE names a file, the
+ * tuner first looks there for this case (extents, precision, boundaries,
+ * candidate families, ping-pong pair bound or not, compute units and
+ * device architecture); on a hit it sets that tile, runs nothing and keeps
+ * the state.  Otherwise (or with TDSE_TUNE_REFRESH in flags) it times the
+ * candidates and writes the winner into the file (one text line per case,
+ * the file rewritten through a temporary and a rename; TDSE_ERR_ARG if it
+ * cannot be written). */
+#define TDSE_TUNE_REFRESH 8
 tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile* out);
 tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t);
 

@@ -15,8 +15,8 @@
 // through LDS: R(p+1) on the band plus two halo rows, I^{n+1/2}(p) on the
 // band plus one halo row (double-buffered).  Two barriers per plane.
 //
-// Cell arithmetic is the same expression as the two-pass kernel (lap7,
-// update_I, update_R of kernels.hpp), so both paths give identical bits.
+// Cell arithmetic is the same expression as the two-pass kernel (vterm,
+// hterm, upd_I, upd_R of kernels.hpp), so both paths give identical bits.
 #pragma once
 
 #include "kernels.hpp"
@@ -33,6 +33,7 @@ struct FusedArgs {
     const T* ca;
     const T* cb;
     T cx, cy, cz, cv;
+    T d0, dlo;             // 2 (cx + cy + cz) as hi + lo parts
     int nx, ny, nz;
     int tpr, rpp, ty;      // threads per row, rows per pass, band rows
     int nbands, zc, nzc, nwg;
@@ -191,9 +192,9 @@ __device__ __forceinline__ void fused_step_body(const FusedArgs<T>& a, int L,
                     const T c = Rz[1][i].v[e];
                     const T xl = e > 0 ? Rz[1][i].v[e - 1] : xle;
                     const T xr = e < W - 1 ? Rz[1][i].v[e + 1] : xre;
-                    const T lap = lap7(c, xl, xr, yl.v[e], yr.v[e], Rz[0][i].v[e], Rz[2][i].v[e],
-                                       a.cx, a.cy, a.cz);
-                    out.v[e] = zero ? T(0) : update_I(lap, vv[i].v[e], c, io[i].v[e], a.cv, cap, cbp);
+                    const T hx = hterm(c, xl, xr, yl.v[e], yr.v[e], Rz[0][i].v[e], Rz[2][i].v[e],
+                                       vterm(vv[i].v[e], a.cv, a.d0), a.cx, a.cy, a.cz, a.dlo);
+                    out.v[e] = zero ? T(0) : upd_I(hx, io[i].v[e], cap, cbp);
                 }
                 *reinterpret_cast<VT*>(li_row(buf, b) + x0) = out;
                 if (store) bstore_out<T, W>(prs(a.I1, gp), voffB[i], out, a.nt_out);
@@ -277,10 +278,10 @@ __device__ __forceinline__ void fused_step_body(const FusedArgs<T>& a, int L,
                 const T c = Iz[1][i].v[e];
                 const T xl = e > 0 ? Iz[1][i].v[e - 1] : xle;
                 const T xr = e < W - 1 ? Iz[1][i].v[e + 1] : xre;
-                const T lap = lap7(c, xl, xr, yl.v[e], yr.v[e], Iz[0][i].v[e], Iz[2][i].v[e],
-                                   a.cx, a.cy, a.cz);
+                const T hx = hterm(c, xl, xr, yl.v[e], yr.v[e], Iz[0][i].v[e], Iz[2][i].v[e],
+                                   vterm(vk[i].v[e], a.cv, a.d0), a.cx, a.cy, a.cz, a.dlo);
                 const T uo = Rz[0][i].v[e];
-                const T un = update_R(lap, vk[i].v[e], c, uo, a.cv, cak, cbk);
+                const T un = upd_R(hx, uo, cak, cbk);
                 out.v[e] = un;
                 if (at_det) f0 += (double)Iz[2][i].v[e] * ((double)uo + (double)un);
                 if (at_up) f1 += (double)Iz[0][i].v[e] * ((double)uo + (double)un);

@@ -20,7 +20,8 @@
 //   A2  I^{n+3/2}(k+1)  from R^{n+1}(k..k+2)
 //   B2  R^{n+2}(k)      from I^{n+3/2}(k-1..k+1)
 // Each thread keeps the z windows of the four fields (the new plane of each
-// plus the two below it that the next phases read) and four planes of cv V in
+// plus the two below it that the next phases read, in rings of three
+// register slots) and four planes of the potential term vterm(V) in
 // registers (its W-wide x vectors of M extended rows).  The x and y
 // neighbours of each phase's centre plane come from LDS, where the previous
 // iteration left them: every phase reads the LDS buffers of parity k and
@@ -28,7 +29,7 @@
 // reads and writes.  The march starts six planes before the chunk so
 // that every stored plane is exact.
 //
-// The cell arithmetic is lap7 / update_I / update_R of kernels.hpp, so the
+// The cell arithmetic is vterm / hterm / upd_* of kernels.hpp, so the
 // states are bitwise identical to those of the one-pass and two-pass steps.
 // The flux partials of both steps (every step) and, on the second step only,
 // the record fields are reduced per workgroup in a fixed order.
@@ -50,6 +51,7 @@ struct Fused2Args {
     const T* ca;
     const T* cb;
     T cx, cy, cz, cv;
+    T d0, dlo;            // 2 (cx + cy + cz) as hi + lo parts
     int nx, ny, nz;
     int tx, ty, ex, ey;   // interior and extended tile extents
     int tpr, rpp;         // threads per extended row, extended rows per pass
@@ -130,17 +132,21 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
         return z;
     };
 
-    // z windows at the start of iteration k: Rn[0..1] = R^n(k+2..k+3),
-    // Ia = I^{n+1/2}(k+1..k+2), Rb = R^{n+1}(k..k+1), Ib = I^{n+3/2}(k-1..k),
-    // Vw[0..2] = V(k..k+2).  The iteration loads R^n(k+4) into Rn[2],
-    // I^{n-1/2}(k+3) into io and V(k+3) into Vw[3], and adds one plane to
-    // each field.
-    VT Rn[3][M], Ia[2][M], Rb[2][M], Ib[2][M], Vw[4][M], io[M];
+    // z windows.  The four fields live in rings of three register slots,
+    // plane p of a field in slot (p + off) mod 3, so that an iteration
+    // writes each new plane over the one that has gone out of use and
+    // nothing moves between iterations; the march is unrolled three times
+    // so that every slot index is a compile-time constant.  At iteration k:
+    // R^n holds planes k+2, k+3 and receives k+4; I^{n+1/2} holds k+1, k+2
+    // and receives k+3; R^{n+1} holds k, k+1 and receives k+2; I^{n+3/2}
+    // holds k-1, k and receives k+1.  Vw[0..3] holds the potential term of
+    // V(k..k+3) (V(k+3) arrives in the iteration), io I^{n-1/2}(k+3).
+    VT Rn[3][M], Ia[3][M], Rb[3][M], Ib[3][M], Vw[4][M], io[M];
     VT pR[M], pI[M], pV[M];   // prefetched inputs of the next iteration
 #pragma unroll
     for (int i = 0; i < M; ++i) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
+        for (int s = 0; s < 3; ++s) {
             Ia[s][i] = zero_vec();
             Rb[s][i] = zero_vec();
             Ib[s][i] = zero_vec();
@@ -150,7 +156,8 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     }
 
     // one phase on plane p: centre c, z neighbours zl / zr, x / y neighbours
-    // from LDS buffer src (the centre plane), old value uo, cv V in cvv;
+    // from LDS buffer src (the centre plane), old value uo, potential term
+    // vterm(V) in vtv;
     // IS_R selects eq. (8), else eq. (9).  The result goes to out and, from
     // live threads, to LDS buffer dst (if not null).  A plane outside a zero
     // z boundary is zero.  The 1024-thread workgroups (one per CU, where
@@ -173,7 +180,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
         return false;
     };
     auto phase = [&](auto is_r, int depth, int p, const VT(&zl)[M], const VT(&c)[M], const VT(&zr)[M],
-                     const T* src, const VT(&uo)[M], const VT(&cvv)[M], VT(&out)[M], T* dst) {
+                     const T* src, const VT(&uo)[M], const VT(&vtv)[M], VT(&out)[M], T* dst) {
         constexpr bool IS_R = decltype(is_r)::value;
         // the march's first iterations reach planes below those the stored
         // planes [k0, k1) depend on: phase d needs planes >= k0 - (4 - d)
@@ -207,14 +214,13 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
                     const T cc = c[i].v[e];
                     const T xl = e > 0 ? c[i].v[e - 1] : xle;
                     const T xr = e < W - 1 ? c[i].v[e + 1] : xre;
-                    const T lap = lap7(cc, xl, xr, yl.v[e], yr.v[e], zl[i].v[e], zr[i].v[e], a.cx, a.cy, a.cz);
+                    const T hx = hterm(cc, xl, xr, yl.v[e], yr.v[e], zl[i].v[e], zr[i].v[e], vtv[i].v[e],
+                                       a.cx, a.cy, a.cz, a.dlo);
                     T u;
                     if constexpr (UNIT)
-                        u = IS_R ? update_R_unit(lap, cvv[i].v[e], cc, uo[i].v[e])
-                                 : update_I_unit(lap, cvv[i].v[e], cc, uo[i].v[e]);
+                        u = IS_R ? upd_R_unit(hx, uo[i].v[e]) : upd_I_unit(hx, uo[i].v[e]);
                     else
-                        u = IS_R ? update_R_cvv(lap, cvv[i].v[e], cc, uo[i].v[e], cap, cbp)
-                                 : update_I_cvv(lap, cvv[i].v[e], cc, uo[i].v[e], cap, cbp);
+                        u = IS_R ? upd_R(hx, uo[i].v[e], cap, cbp) : upd_I(hx, uo[i].v[e], cap, cbp);
                     if constexpr (SEL)
                         o.v[e] = zc_cell[i] ? T(0) : u;
                     else
@@ -250,55 +256,76 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     };
 
     const int ks = k0 - 6;
-    // prologue: R^n(ks+2), R^n(ks+3) into the window, R^n(ks+3) staged for A1
+    // ring slot of plane p: R^n and I^{n+1/2} by (p - ks) mod 3, R^{n+1} and
+    // I^{n+3/2} the same (their planes trail by one and two); as a
+    // compile-time function of the unrolled iteration u = (k - ks) mod 3
+    // and the plane's offset j from k
+    auto slot = [](int u, int j) -> int { return ((u + j) % 3 + 3) % 3; };
+    // prologue: R^n(ks+2), R^n(ks+3) into the ring, R^n(ks+3) staged for A1
     {
         const auto r2 = prs(a.R0, gplane(ks + 2)), r3 = prs(a.R0, gplane(ks + 3));
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-            Rn[0][i] = bload<T, W>(r2, voff[i]);
-            Rn[1][i] = bload<T, W>(r3, voff[i]);
+            Rn[slot(0, 2)][i] = bload<T, W>(r2, voff[i]);
+            Rn[slot(0, 3)][i] = bload<T, W>(r3, voff[i]);
         }
         if (live) {
 #pragma unroll
-            for (int i = 0; i < M; ++i) *reinterpret_cast<VT*>(buf(0, 0) + rowb[i] * ex + c0) = Rn[1][i];
+            for (int i = 0; i < M; ++i)
+                *reinterpret_cast<VT*>(buf(0, 0) + rowb[i] * ex + c0) = Rn[slot(0, 3)][i];
         }
         if (PF) load3(ks + 4, ks + 3, pR, pI, pV);
     }
     __syncthreads();
 
     double fa0 = 0.0, fa1 = 0.0, fb0 = 0.0, fb1 = 0.0, q = 0.0, nv = 0.0, pl = 0.0;
-    for (int k = ks; k < k1; ++k) {
+    // one iteration of the march; U = (k - ks) mod 3 as a type
+    auto iteration = [&](auto uc, int k) {
+        constexpr int U = decltype(uc)::value;
         const int par = (k - ks) & 1;
+        VT(&rN)[M] = Rn[slot(U, 4)];   // R^n(k+4), arriving
+        VT(&rC)[M] = Rn[slot(U, 3)];
+        VT(&rL)[M] = Rn[slot(U, 2)];
+        VT(&nA)[M] = Ia[slot(U, 3)];   // I^{n+1/2}(k+3), formed by A1
+        VT(&iC)[M] = Ia[slot(U, 2)];
+        VT(&iL)[M] = Ia[slot(U, 1)];
+        VT(&nB)[M] = Rb[slot(U, 2)];   // R^{n+1}(k+2), formed by B1
+        VT(&bC)[M] = Rb[slot(U, 1)];
+        VT(&bL)[M] = Rb[slot(U, 0)];
+        VT(&nC)[M] = Ib[slot(U, 1)];   // I^{n+3/2}(k+1), formed by A2
+        VT(&jC)[M] = Ib[slot(U, 0)];
+        VT(&jL)[M] = Ib[slot(U, -1)];
         if (PF) {
 #pragma unroll
             for (int i = 0; i < M; ++i) {
-                Rn[2][i] = pR[i];
+                rN[i] = pR[i];
                 io[i] = pI[i];
                 Vw[3][i] = pV[i];
             }
             if (k + 1 < k1) load3(k + 5, k + 4, pR, pI, pV);
         } else {
-            load3(k + 4, k + 3, Rn[2], io, Vw[3]);
+            load3(k + 4, k + 3, rN, io, Vw[3]);
         }
-        // the window keeps cv V, formed once per plane instead of per phase
+        // the window keeps the potential term of the update (vterm),
+        // formed once per plane instead of per phase
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
-            for (int e = 0; e < W; ++e) Vw[3][i].v[e] = a.cv * Vw[3][i].v[e];
+            for (int e = 0; e < W; ++e) Vw[3][i].v[e] = vterm(Vw[3][i].v[e], a.cv, a.d0);
         // stage R^n(k+4) for the next iteration's A1
         if (live) {
 #pragma unroll
-            for (int i = 0; i < M; ++i) *reinterpret_cast<VT*>(buf(0, par ^ 1) + rowb[i] * ex + c0) = Rn[2][i];
+            for (int i = 0; i < M; ++i) *reinterpret_cast<VT*>(buf(0, par ^ 1) + rowb[i] * ex + c0) = rN[i];
         }
-        VT nA[M], nB[M], nC[M], nD[M];
+        VT nD[M];   // R^{n+2}(k), formed by B2
         // A1: I^{n+1/2}(k+3)
-        phase(IsI{}, 1, k + 3, Rn[0], Rn[1], Rn[2], buf(0, par), io, Vw[3], nA, buf(1, par ^ 1));
+        phase(IsI{}, 1, k + 3, rL, rC, rN, buf(0, par), io, Vw[3], nA, buf(1, par ^ 1));
         // B1: R^{n+1}(k+2)
-        phase(IsR{}, 2, k + 2, Ia[0], Ia[1], nA, buf(1, par), Rn[0], Vw[2], nB, buf(2, par ^ 1));
+        phase(IsR{}, 2, k + 2, iL, iC, nA, buf(1, par), rL, Vw[2], nB, buf(2, par ^ 1));
         // A2: I^{n+3/2}(k+1)
-        phase(IsI{}, 3, k + 1, Rb[0], Rb[1], nB, buf(2, par), Ia[0], Vw[1], nC, buf(3, par ^ 1));
+        phase(IsI{}, 3, k + 1, bL, bC, nB, buf(2, par), iL, Vw[1], nC, buf(3, par ^ 1));
         // B2: R^{n+2}(k)
-        phase(IsR{}, 4, k, Ib[0], Ib[1], nC, buf(3, par), Rb[0], Vw[0], nD, nullptr);
+        phase(IsR{}, 4, k, jL, jC, nC, buf(3, par), bL, Vw[0], nD, nullptr);
         const int pB = k + 2, pC = k + 1, pD = k;
         if (pC >= k0 && pC < k1) {
             const auto rI = prs(a.I1, pC);
@@ -320,9 +347,9 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
                 if (soff[i] == OOB) continue;
 #pragma unroll
                 for (int e = 0; e < W; ++e) {
-                    const double s = (double)Rn[0][i].v[e] + (double)nB[i].v[e];
+                    const double s = (double)rL[i].v[e] + (double)nB[i].v[e];
                     if (det) fa0 += (double)nA[i].v[e] * s;
-                    if (up) fa1 += (double)Ia[0][i].v[e] * s;
+                    if (up) fa1 += (double)iL[i].v[e] * s;
                 }
             }
         }
@@ -333,9 +360,9 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
                 if (soff[i] == OOB) continue;
 #pragma unroll
                 for (int e = 0; e < W; ++e) {
-                    const double s = (double)Rb[0][i].v[e] + (double)nD[i].v[e];
+                    const double s = (double)bL[i].v[e] + (double)nD[i].v[e];
                     if (det) fb0 += (double)nC[i].v[e] * s;
-                    if (up) fb1 += (double)Ib[0][i].v[e] * s;
+                    if (up) fb1 += (double)jL[i].v[e] * s;
                 }
             }
         }
@@ -345,7 +372,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
                 if (soff[i] == OOB) continue;
 #pragma unroll
                 for (int e = 0; e < W; ++e) {
-                    const double dc = (double)Ib[1][i].v[e], du = (double)Rb[0][i].v[e];
+                    const double dc = (double)jC[i].v[e], du = (double)bL[i].v[e];
                     const double dn = (double)nD[i].v[e];
                     q += dc * dc + du * dn;
                     nv += dn * dn + dc * dc;
@@ -355,7 +382,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
                     const long poff = soff[i] / (int)sizeof(T);
 #pragma unroll
                     for (int e = 0; e < W; ++e) {
-                        const double dn = (double)nD[i].v[e], dc = (double)Ib[1][i].v[e];
+                        const double dn = (double)nD[i].v[e], dc = (double)jC[i].v[e];
                         const double rho = dn * dn + dc * dc;
                         rv.v[e] = (T)rho;
                         pl += rho;
@@ -365,22 +392,26 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
                 }
             }
         }
-        // shift the windows one plane up
+        // shift the potential window one plane up
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-            Rn[0][i] = Rn[1][i];
-            Rn[1][i] = Rn[2][i];
-            Ia[0][i] = Ia[1][i];
-            Ia[1][i] = nA[i];
-            Rb[0][i] = Rb[1][i];
-            Rb[1][i] = nB[i];
-            Ib[0][i] = Ib[1][i];
-            Ib[1][i] = nC[i];
             Vw[0][i] = Vw[1][i];
             Vw[1][i] = Vw[2][i];
             Vw[2][i] = Vw[3][i];
         }
         __syncthreads();
+    };
+    using U0 = std::integral_constant<int, 0>;
+    using U1 = std::integral_constant<int, 1>;
+    using U2 = std::integral_constant<int, 2>;
+    // k1 - ks >= 7 iterations; every exit is uniform over the workgroup
+    for (int k = ks;; k += 3) {
+        iteration(U0{}, k);
+        if (k + 1 >= k1) break;
+        iteration(U1{}, k + 1);
+        if (k + 2 >= k1) break;
+        iteration(U2{}, k + 2);
+        if (k + 3 >= k1) break;
     }
 
     // fixed-order workgroup sums of the partials

@@ -5,8 +5,8 @@
 // eq. (12), every neighbour read from global memory (the paper found shared
 // memory slower), periodic neighbours by the modular indices that replace
 // the branches of eqs. (13)-(14), one launch per half-step (eq. (9), then
-// eq. (8)), each in place.  The cell arithmetic is lap7 / update_I /
-// update_R, so the states equal those of the x-fastest kernels bit for bit,
+// eq. (8)), each in place.  The cell arithmetic is vterm / hterm / upd_I /
+// upd_R, so the states equal those of the x-fastest kernels bit for bit,
 // transposed.  No records or sums: the paper takes the detector plane on
 // the host.
 #include "kernels.hpp"
@@ -42,11 +42,10 @@ __global__ __launch_bounds__(1024) void zfast_half_kernel(ZArgs<T> a) {
     const T yr = nb(j, +1, ny, a.bcy, sy, idx - (long)j * sy);
     const T zl = nb(k, -1, nz, a.bcz, 1, idx - k);
     const T zr = nb(k, +1, nz, a.bcz, 1, idx - k);
-    const T lap = lap7(c, xl, xr, yl, yr, zl, zr, a.cx, a.cy, a.cz);
-    const T v = a.V[idx];
+    const T hx = hterm(c, xl, xr, yl, yr, zl, zr, vterm(a.V[idx], a.cv, a.d0), a.cx, a.cy, a.cz, a.dlo);
     const T uo = a.U[idx];
     const T cak = a.ca[k], cbk = a.cb[k];
-    a.U[idx] = IS_R ? update_R(lap, v, c, uo, a.cv, cak, cbk) : update_I(lap, v, c, uo, a.cv, cak, cbk);
+    a.U[idx] = IS_R ? upd_R(hx, uo, cak, cbk) : upd_I(hx, uo, cak, cbk);
 }
 
 hipError_t launch_zfast_f32(bool is_r, dim3 grid, dim3 block, hipStream_t st, const ZArgs<float>& a) {

@@ -15,6 +15,7 @@ struct ZArgs {
     const T* ca;   // [nz] CAP tables
     const T* cb;
     T cx, cy, cz, cv;
+    T d0, dlo;     // 2 (cx + cy + cz) as hi + lo parts
     int nx, ny, nz;
     int bcx, bcy, bcz;
     int nyb;       // blocks of Bz planes along y

@@ -374,47 +374,82 @@ struct InterpArgs {
     double dx, dy, dz;
 };
 
+// Per-axis samples and weight of one mesh index: the lower table sample a0,
+// the upper a1 and the weight t of a1.
+struct AxisW {
+    int a0, a1;
+    double t;
+};
+
 // fractional table coordinate u -> lower sample (wrapped), upper sample and weight
-__device__ __forceinline__ void cell_axis(double u, int n, int* a0, int* a1, double* t) {
+__device__ __forceinline__ AxisW cell_axis(double u, int n) {
     const double f = floor(u);
-    *t = u - f;
+    AxisW w;
+    w.t = u - f;
     long a = (long)f % n;
     if (a < 0) a += n;
-    *a0 = (int)a;
-    *a1 = (int)((a + 1) % n);
+    w.a0 = (int)a;
+    w.a1 = (int)((a + 1) % n);
+    return w;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void interp_potential_kernel(InterpArgs a, T* V) {
-    const long nxy = (long)a.nx * a.ny;
-    const long n = nxy * a.nz;
+// The weights of every mesh index of the three axes, once per call:
+// ax[0 .. nx) for x, ax[nx .. nx+ny) for y (both periodic over the cell),
+// ax[nx+ny .. nx+ny+nz) for z (clamped to the table's z range).
+__global__ __launch_bounds__(256) void interp_axes_kernel(InterpArgs a, AxisW* ax) {
+    const long n = (long)a.nx + a.ny + a.nz;
     for (long c = (long)blockIdx.x * 256 + threadIdx.x; c < n; c += (long)gridDim.x * 256) {
-        const int k = (int)(c / nxy);
-        const long r = c - (long)k * nxy;
-        const int j = (int)(r / a.nx);
-        const int i = (int)(r - (long)j * a.nx);
-        int x0, x1, y0, y1, z0 = 0, z1 = 0;
-        double tx, ty, tz = 0.0;
-        cell_axis(((double)i * a.dx - a.ox) / a.sx, a.ux, &x0, &x1, &tx);
-        cell_axis(((double)j * a.dy - a.oy) / a.sy, a.uy, &y0, &y1, &ty);
-        if (a.uz > 1) {
-            double w = ((double)k * a.dz - a.oz) / a.sz;
-            w = fmin(fmax(w, 0.0), (double)(a.uz - 1));
-            z0 = min((int)floor(w), a.uz - 2);
-            tz = w - (double)z0;
-            z1 = z0 + 1;
+        AxisW w{0, 0, 0.0};
+        if (c < a.nx) {
+            w = cell_axis(((double)c * a.dx - a.ox) / a.sx, a.ux);
+        } else if (c < (long)a.nx + a.ny) {
+            w = cell_axis(((double)(c - a.nx) * a.dy - a.oy) / a.sy, a.uy);
+        } else if (a.uz > 1) {
+            const long k = c - a.nx - a.ny;
+            double u = ((double)k * a.dz - a.oz) / a.sz;
+            u = fmin(fmax(u, 0.0), (double)(a.uz - 1));
+            w.a0 = min((int)floor(u), a.uz - 2);
+            w.t = u - (double)w.a0;
+            w.a1 = w.a0 + 1;
         }
-        const double* p0 = a.table + (long)z0 * a.uy * a.ux;
-        const double* p1 = a.table + (long)z1 * a.uy * a.ux;
-        const long r0 = (long)y0 * a.ux, r1 = (long)y1 * a.ux;
-        const double sx = 1.0 - tx, sy = 1.0 - ty;
-        const double b00 = sx * p0[r0 + x0] + tx * p0[r0 + x1];
-        const double b10 = sx * p0[r1 + x0] + tx * p0[r1 + x1];
-        const double b01 = sx * p1[r0 + x0] + tx * p1[r0 + x1];
-        const double b11 = sx * p1[r1 + x0] + tx * p1[r1 + x1];
-        const double c0 = sy * b00 + ty * b10;
-        const double c1 = sy * b01 + ty * b11;
-        V[c] = (T)((1.0 - tz) * c0 + tz * c1);
+        ax[c] = w;
+    }
+}
+
+// One workgroup: plane k = blockIdx.y, a segment of 256 x columns and rows
+// [j0, j0 + rows) (blockIdx.x = segment + nseg * row group).  Each thread
+// holds its column's x weights and reads the row's y and the plane's z
+// weights as wave-uniform values, so a cell costs its eight table samples
+// (four table rows that the whole row shares, from the caches), the blends
+// in x, then y, then z, and one coalesced store.
+template <typename T>
+__global__ __launch_bounds__(256) void interp_potential_kernel(InterpArgs a, const AxisW* ax, int nseg,
+                                                               int rows, T* V) {
+    const int seg = blockIdx.x % nseg;
+    const int j0 = (blockIdx.x / nseg) * rows;
+    const int k = blockIdx.y;
+    const int i = seg * 256 + threadIdx.x;
+    if (i >= a.nx) return;   // no barriers below
+    const AxisW wx = ax[i];
+    const AxisW wz = ax[a.nx + a.ny + k];
+    const double tx = wx.t, sx = 1.0 - tx;
+    const double tz = wz.t;
+    const long plane = (long)a.uy * a.ux;
+    const double* p0 = a.table + (long)wz.a0 * plane;
+    const double* p1 = a.table + (long)wz.a1 * plane;
+    T* out = V + ((long)k * a.ny) * a.nx + i;
+    const int j1 = min(j0 + rows, a.ny);
+    for (int j = j0; j < j1; ++j) {
+        const AxisW wy = ax[a.nx + j];
+        const double ty = wy.t;
+        const long r0 = (long)wy.a0 * a.ux, r1 = (long)wy.a1 * a.ux;
+        const double b00 = sx * p0[r0 + wx.a0] + tx * p0[r0 + wx.a1];
+        const double b10 = sx * p0[r1 + wx.a0] + tx * p0[r1 + wx.a1];
+        const double b01 = sx * p1[r0 + wx.a0] + tx * p1[r0 + wx.a1];
+        const double b11 = sx * p1[r1 + wx.a0] + tx * p1[r1 + wx.a1];
+        const double c0 = (1.0 - ty) * b00 + ty * b10;
+        const double c1 = (1.0 - ty) * b01 + ty * b11;
+        out[(long)j * a.nx] = (T)((1.0 - tz) * c0 + tz * c1);
     }
 }
 

@@ -10,10 +10,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "../../include/tdse.h"
 #include "kernels.hpp"
@@ -36,8 +39,11 @@ struct tdse_ctx {
     tdse_batch_ctx* gb = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
-    // x layout and tile
+    // x layout and tile: W-element vectors; the vector half-step kernel's
+    // row of G groups of NL lanes when half_vec (nx = W G NL, NL <= 64),
+    // else the any-width half-step kernel
     int W = 1, G = 1, NL = 1;
+    bool half_vec = true;
     int rows = 2, waves = 4, zc = 16;
     // one-pass (fused) step: rows per thread M, z chunk, enabled flag
     int fm = 3, fzc = 64, ft = 256;
@@ -120,6 +126,11 @@ struct tdse_batch_ctx {
     hipGraphExec_t exec1 = nullptr;
     bool prepared = false;
     bool owns = true;    // members are destroyed with the batch
+    // device memory of the tables (d_cfg, d_fin, d_wg, d_rec), borrowed
+    // from the caller (tdse_batch_bind_workspace) or, for a handle's own
+    // graph replays, from the handle's workspace
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
     int64_t step = 0;
     std::string err;
 };
@@ -130,6 +141,17 @@ constexpr size_t ALIGN = 256;
 constexpr int RED_SLOTS = 3 * 4096;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Bytes of the device tables of an n-member batch: the per-member kernel
+// arguments (either form), the finalisation arguments, the workgroup
+// starts and the record counter, each 256-byte aligned.
+size_t batch_tables_bytes(size_t n) {
+    const size_t cfg = std::max({sizeof(FusedArgs<float>), sizeof(FusedArgs<double>),
+                                 sizeof(Fused2Args<float>), sizeof(Fused2Args<double>)});
+    return align_up(n * cfg) + align_up(n * sizeof(FinArgs)) + align_up((n + 1) * sizeof(int)) +
+           align_up(sizeof(long));
+}
+
 
 size_t elem_size(const tdse_desc& d) { return d.precision == TDSE_F64 ? 8 : 4; }
 
@@ -158,12 +180,22 @@ constexpr size_t MALL_BYTES = (size_t)256 << 20;
 
 bool stream_outputs(size_t state_bytes_total) { return 5 * state_bytes_total > MALL_BYTES; }
 
+// The diagonal 2 (cx + cy + cz) of the 7-point Laplacian in the state
+// precision's coefficients, as hi + lo parts: FP32 coefficients sum exactly
+// in FP64, and hi + lo holds that sum exactly; FP64 kernels do not use it.
+template <typename T>
+void diag_parts(const tdse_ctx* h, T* hi, T* lo) {
+    const double d = 2.0 * ((double)(T)h->c[0] + (double)(T)h->c[1] + (double)(T)h->c[2]);
+    *hi = (T)d;
+    *lo = (T)(d - (double)*hi);
+}
+
 size_t state_bytes(const tdse_desc& d) {
     return (size_t)d.nx * d.ny * d.nz * (d.precision == TDSE_F64 ? 8 : 4);
 }
 
 struct Layout {
-    size_t ca, cb, acc, flux, part_q, part_n, part_p, red, gfac, total;
+    size_t ca, cb, acc, flux, part_q, part_n, part_p, red, gfac, gtab, total;
     int F;
 };
 
@@ -190,8 +222,30 @@ Layout layout_of(const tdse_desc& d) {
     L.part_p = o; o = align_up(o + ny * sizeof(double));
     L.red = o; o = align_up(o + (size_t)RED_SLOTS * sizeof(double));
     L.gfac = o; o = align_up(o + 2 * 2 * ((size_t)d.nx + ny + nz) * sizeof(double));
+    // tables of the one-member batch behind the handle's graph replays
+    L.gtab = o; o = align_up(o + batch_tables_bytes(1));
     L.total = o;
     return L;
+}
+
+// Widest vector of the precision's widths (4, 2, 1 floats; 2, 1 doubles)
+// that divides nx, so every row starts on a vector boundary.
+int vector_width(const tdse_desc& d) {
+    const int w0 = d.precision == TDSE_F64 ? 2 : 4;
+    for (int w = w0; w > 1; w /= 2)
+        if (d.nx % w == 0) return w;
+    return 1;
+}
+
+// The extents the kernels take: byte offsets within one z plane are 32-bit
+// (buffer resources of one plane, out-of-range reads as zero), so a plane
+// must stay below OOB = 0x7ffffff0 bytes; y and z extents within the
+// launch-grid and table limits.
+tdse_status supported_shape(const tdse_desc& d) {
+    const int64_t es = d.precision == TDSE_F64 ? 8 : 4;
+    if ((double)d.nx * (double)d.ny * (double)es >= (double)0x7ffffff0) return TDSE_ERR_UNSUPPORTED;
+    if (d.ny > (int64_t)1 << 24 || d.nz > 65535) return TDSE_ERR_UNSUPPORTED;
+    return TDSE_OK;
 }
 
 // nx = W * G * NL with NL <= 64 lanes; widest vectors first, fewest groups.
@@ -235,11 +289,26 @@ void default_tile(tdse_ctx* h) {
 void default_fused_tile(tdse_ctx* h);
 
 struct TileDims {
-    int ytiles, ywg, nzc, nwg;
+    int ytiles, ywg, nzc, nwg, zc;
 };
 
+// Geometry of the half-step kernels: the vector kernel's y tiles of `rows`
+// rows, `waves` tiles per workgroup, z chunks of zc planes; without a vector
+// layout of nx, the any-width kernel's one row per workgroup and z chunks
+// sized for about 2048 workgroups (rows, waves and zc do not apply).
 TileDims tile_dims(const tdse_ctx* h, int rows, int waves, int zc) {
     TileDims t;
+    if (!h->half_vec) {
+        const int64_t ny = h->d.ny, nz = h->d.nz;
+        const int64_t want = std::max<int64_t>(1, (2048 + ny - 1) / ny);
+        t.zc = (int)std::max<int64_t>(1, (nz + want - 1) / want);
+        t.ytiles = (int)ny;
+        t.ywg = (int)ny;
+        t.nzc = (int)((nz + t.zc - 1) / t.zc);
+        t.nwg = t.ywg * t.nzc;
+        return t;
+    }
+    t.zc = zc;
     t.ytiles = (int)((h->d.ny + rows - 1) / rows);
     t.ywg = (t.ytiles + waves - 1) / waves;
     t.nzc = (int)((h->d.nz + zc - 1) / zc);
@@ -252,6 +321,10 @@ TileDims tile_dims(const tdse_ctx* h, int rows, int waves, int zc) {
 namespace tdse {
 // Half-step launchers, one translation unit per (precision, vector width)
 // so the many template instances compile in parallel (half_*.hip).
+hipError_t launch_half_any_f32(int mode, dim3 grid, hipStream_t st, const HalfArgs<float>& a,
+                               hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_half_any_f64(int mode, dim3 grid, hipStream_t st, const HalfArgs<double>& a,
+                               hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_half_f32_w4(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
                               const HalfArgs<float>& a, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_half_f32_w2(int g, int rows, int mode, dim3 grid, dim3 block, hipStream_t st,
@@ -327,6 +400,7 @@ HalfArgs<T> make_args(tdse_ctx* h, int mode, int rows, int waves, int zc, long r
     a.cy = (T)h->c[1];
     a.cz = (T)h->c[2];
     a.cv = (T)h->c[3];
+    diag_parts(h, &a.d0, &a.dlo);
     a.nx = (int)d.nx;
     a.ny = (int)d.ny;
     a.nz = (int)d.nz;
@@ -334,7 +408,7 @@ HalfArgs<T> make_args(tdse_ctx* h, int mode, int rows, int waves, int zc, long r
     a.ytiles = td.ytiles;
     a.wpg = waves;
     a.ywg = td.ywg;
-    a.zc = zc;
+    a.zc = td.zc;
     a.nzc = td.nzc;
     a.nwg = td.nwg;
     a.bcx = d.bc[0] == TDSE_BC_ZERO;
@@ -359,7 +433,8 @@ HalfArgs<T> make_args(tdse_ctx* h, int mode, int rows, int waves, int zc, long r
 }
 
 // Event pair around the next launch when timing is on.  kind: 0 = eq. (9)
-// half-step, 1 = eq. (8) half-step, 2 = one-pass step, 3 = two-step sweep.
+// half-step, 1 = eq. (8) half-step, 2 = one-pass step, 3 = two-step sweep;
+// plus 4 for a launch that writes a record.
 tdse_status timing_events(tdse_ctx* h, int kind, hipEvent_t* e0, hipEvent_t* e1) {
     *e0 = *e1 = nullptr;
     if (!h->timing) return TDSE_OK;
@@ -382,16 +457,18 @@ tdse_status launch_half(tdse_ctx* h, int mode, int rows, int waves, int zc, long
     dim3 grid(td.nwg), block(64, waves);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (mode != MODE_I_PEEK) {
-        tdse_status s = timing_events(h, mode == MODE_I ? 0 : 1, &e0, &e1);
+        tdse_status s = timing_events(h, mode == MODE_I ? 0 : (mode == MODE_R_REC ? 5 : 1), &e0, &e1);
         if (s != TDSE_OK) return s;
     }
     hipError_t e;
     if (h->d.precision == TDSE_F64) {
         HalfArgs<double> a = make_args<double>(h, mode, rows, waves, zc, rec_idx, flux_slot);
-        e = launch_half_f64(h->W, h->G, rows, mode, grid, block, h->stream, a, e0, e1);
+        e = h->half_vec ? launch_half_f64(h->W, h->G, rows, mode, grid, block, h->stream, a, e0, e1)
+                        : launch_half_any_f64(mode, grid, h->stream, a, e0, e1);
     } else {
         HalfArgs<float> a = make_args<float>(h, mode, rows, waves, zc, rec_idx, flux_slot);
-        e = launch_half_f32(h->W, h->G, rows, mode, grid, block, h->stream, a, e0, e1);
+        e = h->half_vec ? launch_half_f32(h->W, h->G, rows, mode, grid, block, h->stream, a, e0, e1)
+                        : launch_half_any_f32(mode, grid, h->stream, a, e0, e1);
     }
     return hip_check(h, e, "half-step launch");
 }
@@ -451,6 +528,7 @@ FusedArgs<T> make_fused_args(tdse_ctx* h, const FusedDims& f, bool rec, long rec
     a.cy = (T)h->c[1];
     a.cz = (T)h->c[2];
     a.cv = (T)h->c[3];
+    diag_parts(h, &a.d0, &a.dlo);
     a.nx = (int)d.nx;
     a.ny = (int)d.ny;
     a.nz = (int)d.nz;
@@ -483,7 +561,7 @@ FusedArgs<T> make_fused_args(tdse_ctx* h, const FusedDims& f, bool rec, long rec
 // One one-pass step from (R, I) into (R2, I2); the caller swaps the pairs.
 tdse_status launch_fused(tdse_ctx* h, const FusedDims& f, bool rec, long rec_idx, int flux_slot) {
     hipEvent_t e0, e1;
-    tdse_status s = timing_events(h, 2, &e0, &e1);
+    tdse_status s = timing_events(h, rec ? 6 : 2, &e0, &e1);
     if (s != TDSE_OK) return s;
     hipError_t e;
     if (h->d.precision == TDSE_F64) {
@@ -561,6 +639,7 @@ Fused2Args<T> make_fused2_args(tdse_ctx* h, const Fused2Dims& f, bool rec, long 
     a.cy = (T)h->c[1];
     a.cz = (T)h->c[2];
     a.cv = (T)h->c[3];
+    diag_parts(h, &a.d0, &a.dlo);
     a.nx = (int)d.nx;
     a.ny = (int)d.ny;
     a.nz = (int)d.nz;
@@ -597,7 +676,7 @@ Fused2Args<T> make_fused2_args(tdse_ctx* h, const Fused2Dims& f, bool rec, long 
 // if rec.  Flux partials go to ring slots flux_slot and flux_slot + 1.
 tdse_status launch_fused2(tdse_ctx* h, const Fused2Dims& f, bool rec, long rec_idx, int flux_slot) {
     hipEvent_t e0, e1;
-    tdse_status s = timing_events(h, 3, &e0, &e1);
+    tdse_status s = timing_events(h, rec ? 7 : 3, &e0, &e1);
     if (s != TDSE_OK) return s;
     hipError_t e;
     if (h->d.precision == TDSE_F64) {
@@ -1018,16 +1097,31 @@ static void batch_free_device(tdse_batch_ctx* b) {
     if (b->graph1) (void)hipGraphDestroy(b->graph1);
     b->exec1 = nullptr;
     b->graph1 = nullptr;
-    if (b->d_cfg) (void)hipFree(b->d_cfg);
-    if (b->d_wg) (void)hipFree(b->d_wg);
-    if (b->d_rec) (void)hipFree(b->d_rec);
-    if (b->d_fin) (void)hipFree(b->d_fin);
+    // the tables live in borrowed memory: nothing to free
     b->exec = nullptr;
     b->graph = nullptr;
     b->d_cfg = b->d_fin = nullptr;
     b->d_wg = nullptr;
     b->d_rec = nullptr;
     b->prepared = false;
+}
+
+// Point the tables into the batch's workspace; false if none is bound or it
+// is short.
+static bool batch_carve_tables(tdse_batch_ctx* b) {
+    const size_t n = b->members.size();
+    if (!b->ws || b->ws_bytes < batch_tables_bytes(n)) return false;
+    char* w = static_cast<char*>(b->ws);
+    const size_t cfg = std::max({sizeof(FusedArgs<float>), sizeof(FusedArgs<double>),
+                                 sizeof(Fused2Args<float>), sizeof(Fused2Args<double>)});
+    b->d_cfg = w;
+    w += align_up(n * cfg);
+    b->d_fin = w;
+    w += align_up(n * sizeof(FinArgs));
+    b->d_wg = reinterpret_cast<int*>(w);
+    w += align_up((n + 1) * sizeof(int));
+    b->d_rec = reinterpret_cast<long*>(w);
+    return true;
 }
 
 // the members run together, so their summed footprint decides the hint
@@ -1173,13 +1267,8 @@ static tdse_status batch_prepare2_t(tdse_batch_ctx* b, bool* used) {
     hipError_t e = sizeof(T) == 8 ? fused2_batch_allow_lds_f64(W, b->t2m, b->t2t, lds)
                                   : fused2_batch_allow_lds_f32(W, b->t2m, b->t2t, lds);
     if (e != hipSuccess) return bfail(b, TDSE_ERR_DEVICE, std::string("batch LDS: ") + hipGetErrorString(e));
-    if (hipMalloc(&b->d_cfg, n * sizeof(Fused2Args<T>)) != hipSuccess ||
-        hipMalloc(&b->d_fin, n * sizeof(FinArgs)) != hipSuccess ||
-        hipMalloc(&b->d_wg, (n + 1) * sizeof(int)) != hipSuccess ||
-        hipMalloc(&b->d_rec, sizeof(long)) != hipSuccess) {
-        batch_free_device(b);
-        return bfail(b, TDSE_ERR_OOM, "batch tables");
-    }
+    if (!batch_carve_tables(b))
+        return bfail(b, TDSE_ERR_STATE, "bind a batch workspace of tdse_batch_workspace_size bytes first");
     e = hipMemcpyAsync(b->d_cfg, cfg.data(), n * sizeof(Fused2Args<T>), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_fin, fin.data(), n * sizeof(FinArgs), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_wg, wg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream);
@@ -1264,13 +1353,8 @@ static tdse_status batch_prepare_t(tdse_batch_ctx* b) {
     b->W = W;
     b->lds = lds;
     b->total_wg = wg[n];
-    if (hipMalloc(&b->d_cfg, n * sizeof(FusedArgs<T>)) != hipSuccess ||
-        hipMalloc(&b->d_fin, n * sizeof(FinArgs)) != hipSuccess ||
-        hipMalloc(&b->d_wg, (n + 1) * sizeof(int)) != hipSuccess ||
-        hipMalloc(&b->d_rec, sizeof(long)) != hipSuccess) {
-        batch_free_device(b);
-        return bfail(b, TDSE_ERR_OOM, "batch tables");
-    }
+    if (!batch_carve_tables(b))
+        return bfail(b, TDSE_ERR_STATE, "bind a batch workspace of tdse_batch_workspace_size bytes first");
     hipError_t e = hipMemcpyAsync(b->d_cfg, cfg.data(), n * sizeof(FusedArgs<T>), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_fin, fin.data(), n * sizeof(FinArgs), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_wg, wg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream);
@@ -1303,6 +1387,113 @@ static void graph_invalidate(tdse_ctx* h) {
     delete h->gb;
     h->gb = nullptr;
 }
+
+namespace {
+
+// The tile cache of tdse_autotune: a text file, one line per tuned case,
+//   tdse-tune-v1 <nx ny nz precision bcx bcy bcz families pingpong CUs arch> : <15 tile fields>
+// read and rewritten whole (through a temporary file renamed over it).
+constexpr const char* TUNE_TAG = "tdse-tune-v1";
+
+std::string tune_key(const tdse_ctx* h, int families) {
+    const tdse_desc& d = h->d;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char& c : arch)
+        if (c == ' ' || c == ':') c = '_';
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%lld %lld %lld %d %d %d %d %d %d %d %s", (long long)d.nx,
+                  (long long)d.ny, (long long)d.nz, d.precision, d.bc[0], d.bc[1], d.bc[2], families,
+                  h->R2 ? 1 : 0, h->cus, arch.c_str());
+    return buf;
+}
+
+void tile_fields(const tdse_tile& t, int v[15]) {
+    const int f[15] = {t.rows, t.waves, t.zc, t.fused, t.fused_rows, t.fused_zc, t.fused_prefetch,
+                       t.graph, t.fused_threads, t.two_step, t.two_step_tx, t.two_step_rows,
+                       t.two_step_zc, t.two_step_prefetch, t.two_step_threads};
+    for (int i = 0; i < 15; ++i) v[i] = f[i];
+}
+
+void tile_from_fields(tdse_tile* t, const int v[15]) {
+    t->rows = v[0];
+    t->waves = v[1];
+    t->zc = v[2];
+    t->fused = v[3];
+    t->fused_rows = v[4];
+    t->fused_zc = v[5];
+    t->fused_prefetch = v[6];
+    t->graph = v[7];
+    t->fused_threads = v[8];
+    t->two_step = v[9];
+    t->two_step_tx = v[10];
+    t->two_step_rows = v[11];
+    t->two_step_zc = v[12];
+    t->two_step_prefetch = v[13];
+    t->two_step_threads = v[14];
+}
+
+std::vector<std::string> read_lines(const char* path) {
+    std::vector<std::string> lines;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return lines;
+    char buf[1024];
+    while (std::fgets(buf, sizeof buf, f)) {
+        std::string l(buf);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        if (!l.empty()) lines.push_back(l);
+    }
+    std::fclose(f);
+    return lines;
+}
+
+// The cached tile of key, if the file has a well-formed line for it.
+bool tune_cache_lookup(const char* path, const std::string& key, tdse_tile* t) {
+    const std::string head = std::string(TUNE_TAG) + " " + key + " :";
+    for (const std::string& l : read_lines(path)) {
+        if (l.compare(0, head.size(), head) != 0) continue;
+        int v[15];
+        int used = 0;
+        const char* p = l.c_str() + head.size();
+        int i = 0;
+        for (; i < 15; ++i) {
+            if (std::sscanf(p, "%d%n", &v[i], &used) != 1) break;
+            p += used;
+        }
+        if (i == 15) {
+            tile_from_fields(t, v);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Replace (or add) the line of key; false if the file cannot be written.
+bool tune_cache_store(const char* path, const std::string& key, const tdse_tile& t) {
+    const std::string head = std::string(TUNE_TAG) + " " + key + " :";
+    std::vector<std::string> lines;
+    for (const std::string& l : read_lines(path))
+        if (l.compare(0, head.size(), head) != 0) lines.push_back(l);
+    int v[15];
+    tile_fields(t, v);
+    std::string line = head;
+    for (int i = 0; i < 15; ++i) line += " " + std::to_string(v[i]);
+    lines.push_back(line);
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    bool ok = true;
+    for (const std::string& l : lines) ok = ok && std::fprintf(f, "%s\n", l.c_str()) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return false;
+    }
+    return true;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1344,7 +1535,7 @@ tdse_status tdse_validate_desc(const tdse_desc* d) {
     if (!std::isfinite(d->dt) || !std::isfinite(d->dt_frac)) return TDSE_ERR_ARG;
     if (d->flags & ~(uint32_t)(TDSE_FLAG_ALLOW_UNSTABLE | TDSE_FLAG_PIXEL_INTEGRAL))
         return TDSE_ERR_ARG;
-    return TDSE_OK;
+    return supported_shape(*d);
 }
 
 tdse_status tdse_time_step_bound(const tdse_desc* d, double vmin, double vmax, double* e_max,
@@ -1380,9 +1571,11 @@ tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out) {
     *out = nullptr;
     tdse_status s = tdse_validate_desc(d);
     if (s != TDSE_OK) return s;
-    int W, G, NL;
-    if (!choose_x_layout(*d, &W, &G, &NL)) return TDSE_ERR_UNSUPPORTED;
-    if (d->ny > (int64_t)1 << 24 || d->nz > 65535) return TDSE_ERR_UNSUPPORTED;
+    s = supported_shape(*d);
+    if (s != TDSE_OK) return s;
+    int W = 1, G = 0, NL = 0;
+    const bool half_vec = choose_x_layout(*d, &W, &G, &NL);
+    if (!half_vec) W = vector_width(*d);
     tdse_ctx* h = new (std::nothrow) tdse_ctx();
     if (!h) return TDSE_ERR_OOM;
     h->d = *d;
@@ -1390,6 +1583,7 @@ tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out) {
     h->W = W;
     h->G = G;
     h->NL = NL;
+    h->half_vec = half_vec;
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return TDSE_ERR_DEVICE;
@@ -1616,14 +1810,26 @@ tdse_status tdse_interpolate_potential(tdse_handle h, const double* table, int32
     a.dx = d.dx;
     a.dy = d.dy;
     a.dz = d.dz;
-    const long n = (long)d.nx * d.ny * d.nz;
-    const unsigned g = (unsigned)std::min<long>((n + 255) / 256, 32768);
+    // axis weights into the workspace's setup scratch (16 B per mesh index
+    // of the three axes; the region holds 32 B per index)
+    AxisW* ax = reinterpret_cast<AxisW*>(h->gfac);
+    const long nax = (long)d.nx + d.ny + d.nz;
+    hipLaunchKernelGGL(interp_axes_kernel, dim3((unsigned)std::min<long>((nax + 255) / 256, 4096)),
+                       dim3(256), 0, h->stream, a, ax);
+    HIPCHK(h, hipGetLastError());
+    // about 16 rows of one plane per workgroup (fewer on small grids)
+    const int nseg = (int)((d.nx + 255) / 256);
+    int rows = 16;
+    while (rows > 1 && (long)nseg * ((d.ny + rows - 1) / rows) * d.nz < 4096) rows /= 2;
+    const long ngx = (long)nseg * ((d.ny + rows - 1) / rows);
+    if (ngx >= (1L << 31)) return fail(h, TDSE_ERR_UNSUPPORTED, "grid too large for the interpolation launch");
+    const dim3 grid((unsigned)ngx, (unsigned)d.nz);
     if (d.precision == TDSE_F64)
-        hipLaunchKernelGGL(interp_potential_kernel<double>, dim3(g), dim3(256), 0, h->stream, a,
-                           static_cast<double*>(h->V));
+        hipLaunchKernelGGL(interp_potential_kernel<double>, grid, dim3(256), 0, h->stream, a, ax, nseg,
+                           rows, static_cast<double*>(h->V));
     else
-        hipLaunchKernelGGL(interp_potential_kernel<float>, dim3(g), dim3(256), 0, h->stream, a,
-                           static_cast<float*>(h->V));
+        hipLaunchKernelGGL(interp_potential_kernel<float>, grid, dim3(256), 0, h->stream, a, ax, nseg,
+                           rows, static_cast<float*>(h->V));
     return hip_check(h, hipGetLastError(), "interpolation launch");
 }
 
@@ -1856,7 +2062,9 @@ static tdse_status step_plain(tdse_ctx* h, int64_t n) {
     const FusedDims fd = fused_dims(h, h->fm, h->fzc);
     const bool use_fused = h->fused && h->R2 && fd.ok;
     const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t);
-    const bool use_f2 = use_fused && h->two && f2.ok;
+    // the two-step sweep tiles x, so it also runs where the one-pass band
+    // (whole x rows in LDS) does not fit; single steps are then half-steps
+    const bool use_f2 = h->fused && h->R2 && h->two && f2.ok;
     const TileDims td = tile_dims(h, h->rows, h->waves, h->zc);
     auto is_rec = [&](int64_t s) { return hrec > 0 && (s + 1) % hrec == 0; };
     auto ckpt_at = [&](int64_t level) {
@@ -1874,16 +2082,22 @@ static tdse_status step_plain(tdse_ctx* h, int64_t n) {
             i += 1;
         }
     }
-    if (use_fused && ops.size() % 2 == 1) {
+    // every one-pass step and sweep swaps the state pairs: an even number of
+    // them leaves the state in the buffers of tdse_bind
+    const size_t swaps = (size_t)std::count_if(ops.begin(), ops.end(), [](char o) { return o != OP_H; });
+    if (swaps % 2 == 1) {
         size_t j = ops.size();
         while (j > 0 && ops[j - 1] != OP_F1) --j;
         if (j > 0) {
             ops[j - 1] = OP_H;
         } else {
+            // the last sweep as two single steps (one-pass, which swap, or
+            // half-steps, which do not: either way one swap more or less)
             j = ops.size();
             while (ops[j - 1] != OP_F2) --j;
-            ops[j - 1] = OP_F1;
-            ops.insert(ops.begin() + (long)j, (char)OP_F1);
+            const char single = use_fused ? OP_F1 : OP_H;
+            ops[j - 1] = single;
+            ops.insert(ops.begin() + (long)j, single);
         }
     }
     // flux slots per step and partial slots per record of each kind
@@ -1972,6 +2186,9 @@ tdse_status tdse_step(tdse_handle h, int64_t n) {
             if (!b) return fail(h, TDSE_ERR_OOM, "graph context");
             b->members.push_back(h);
             b->owns = false;
+            const Layout L = layout_of(d);
+            b->ws = static_cast<char*>(h->ws) + L.gtab;
+            b->ws_bytes = L.total - L.gtab;
             b->two = false;
             b->stream = h->stream;
             b->precision = d.precision;
@@ -2046,22 +2263,37 @@ tdse_status tdse_set_timing(tdse_handle h, int32_t enable) {
     return TDSE_OK;
 }
 
-tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count) {
-    if (!h || !ms || !count) return TDSE_ERR_ARG;
+namespace {
+
+// Sum the timed launches per kind into ms[nk], count[nk]: nk = 8 keeps the
+// record flag, nk = 4 folds it.
+tdse_status timing_collect(tdse_handle h, double* ms, int64_t* count, int nk) {
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < nk; ++k) {
         ms[k] = 0.0;
         count[k] = 0;
     }
     for (size_t e = 0; e + 1 < h->ev_used; e += 2) {
         float t = 0.f;
         HIPCHK(h, hipEventElapsedTime(&t, h->ev[e], h->ev[e + 1]));
-        const int k = h->ev_kind[e];
+        const int k = h->ev_kind[e] % nk;
         ms[k] += t;
         count[k] += 1;
     }
     h->ev_used = 0;
     return TDSE_OK;
+}
+
+}  // namespace
+
+tdse_status tdse_timing_read(tdse_handle h, double* ms, int64_t* count) {
+    if (!h || !ms || !count) return TDSE_ERR_ARG;
+    return timing_collect(h, ms, count, 4);
+}
+
+tdse_status tdse_timing_read_split(tdse_handle h, double* ms, int64_t* count) {
+    if (!h || !ms || !count) return TDSE_ERR_ARG;
+    return timing_collect(h, ms, count, 8);
 }
 
 tdse_status tdse_paper_layout_run(tdse_handle h, void* psi_r, void* psi_i, const void* v, int64_t n,
@@ -2092,6 +2324,7 @@ tdse_status tdse_paper_layout_run(tdse_handle h, void* psi_r, void* psi_i, const
         a.cy = (T)h->c[1];
         a.cz = (T)h->c[2];
         a.cv = (T)h->c[3];
+        diag_parts(h, &a.d0, &a.dlo);
         a.nx = (int)d.nx;
         a.ny = (int)d.ny;
         a.nz = (int)d.nz;
@@ -2159,7 +2392,9 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
         return fail(h, TDSE_ERR_ARG, "fused_threads must be 64, 128 or 256");
     if (t->fused) {
         if (!h->R2) return fail(h, TDSE_ERR_STATE, "one-pass step needs tdse_bind_pingpong");
-        if (!fused_dims(h, t->fused_rows, fzc, t->fused_threads).ok)
+        // without a fitting one-pass band the pair still serves the two-step
+        // sweep, with half-steps for the single steps
+        if (!fused_dims(h, t->fused_rows, fzc, t->fused_threads).ok && !t->two_step)
             return fail(h, TDSE_ERR_UNSUPPORTED, "one-pass tile does not fit this grid");
     }
     if (t->two_step_zc < 1) return fail(h, TDSE_ERR_ARG, "z chunks must be >= 1");
@@ -2195,13 +2430,24 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
     return TDSE_OK;
 }
 
+
 tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile* out) {
     if (!h || !out || steps < 1) return TDSE_ERR_ARG;
+    if (flags & ~(int32_t)(1 | 2 | 4 | TDSE_TUNE_REFRESH)) return TDSE_ERR_ARG;
     if (!h->ready) return fail(h, TDSE_ERR_STATE, "no state: init_gaussian or set_state first");
     if (h->pending != 0) return fail(h, TDSE_ERR_STATE, "pending flux partials");
     if (h->adj_ws) return fail(h, TDSE_ERR_STATE, "unbind the adjoint before tuning");
-    const bool want2p = flags == 0 || (flags & 1), want1p = flags == 0 || (flags & 2),
-               want2s = flags == 0 || (flags & 4);
+    const int families = (flags & 7) ? (flags & 7) : 7;
+    const char* cache = std::getenv("TDSE_TUNE_CACHE");
+    if (cache && !*cache) cache = nullptr;
+    const std::string key = cache ? tune_key(h, families) : std::string();
+    if (cache && !(flags & TDSE_TUNE_REFRESH)) {
+        tdse_tile hit;
+        tdse_get_tile(h, &hit);
+        if (tune_cache_lookup(cache, key, &hit) && tdse_set_tile(h, &hit) == TDSE_OK)
+            return tdse_get_tile(h, out);
+    }
+    const bool want2p = families & 1, want1p = families & 2, want2s = families & 4;
     tdse_tile base;
     tdse_get_tile(h, &base);
     std::vector<tdse_tile> cands;
@@ -2299,6 +2545,8 @@ tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile
     if (st != TDSE_OK) return st;
     st = tdse_set_tile(h, &win);
     if (st != TDSE_OK) return st;
+    if (cache && !tune_cache_store(cache, key, win))
+        return fail(h, TDSE_ERR_ARG, std::string("cannot write the tile cache ") + cache);
     return tdse_get_tile(h, out);
 }
 
@@ -2314,7 +2562,8 @@ tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2) {
     graph_invalidate(h);
     h->R2 = psi_r2;
     h->I2 = psi_i2;
-    h->fused = fused_dims(h, h->fm, h->fzc).ok;
+    h->fused = fused_dims(h, h->fm, h->fzc).ok ||
+               (h->two && fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t).ok);
     return TDSE_OK;
 }
 
@@ -2353,6 +2602,10 @@ tdse_status tdse_adjoint(tdse_handle h, const void* dL_drho, double* dL_dV, void
     if (h->step != h->adj_N) return fail(h, TDSE_ERR_STATE, "run exactly n_steps forward before the adjoint");
     if (h->d.record_every > 0 && !dL_drho) return fail(h, TDSE_ERR_ARG, "dL_drho required");
     if (h->pending != 0) return fail(h, TDSE_ERR_STATE, "pending flux partials");
+    if (!h->half_vec && !adj_fused_dims(h).ok)
+        return fail(h, TDSE_ERR_UNSUPPORTED,
+                    "the reverse step of this x extent needs the one-pass band (tdse_bind_pingpong, "
+                    "nx / vector width <= 256 and its rows in LDS)");
     if (h->d.precision == TDSE_F64)
         return run_adjoint<double>(h, static_cast<const double*>(dL_drho), dL_dV,
                                    static_cast<double*>(dL_dR0), static_cast<double*>(dL_dI0));
@@ -2494,6 +2747,22 @@ tdse_status tdse_batch_set_two_step(tdse_batch b, int32_t enable, int32_t tx, in
     b->t2zc = zc;
     b->t2pf = prefetch != 0;
     b->t2t = threads;
+    return TDSE_OK;
+}
+
+tdse_status tdse_batch_workspace_size(tdse_batch b, size_t* bytes) {
+    if (!b || !bytes) return TDSE_ERR_ARG;
+    *bytes = batch_tables_bytes(b->members.size());
+    return TDSE_OK;
+}
+
+tdse_status tdse_batch_bind_workspace(tdse_batch b, void* ws, size_t bytes) {
+    if (!b) return TDSE_ERR_ARG;
+    if (ws && (!aligned(ws) || bytes < batch_tables_bytes(b->members.size())))
+        return bfail(b, TDSE_ERR_ARG, "batch workspace short or not 256-byte aligned");
+    batch_free_device(b);
+    b->ws = ws;
+    b->ws_bytes = ws ? bytes : 0;
     return TDSE_OK;
 }
 

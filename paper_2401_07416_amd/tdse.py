@@ -23,6 +23,7 @@ BC_PERIODIC, BC_ZERO = 0, 1
 F32, F64 = 0, 1
 INIT_HALFSTEP, INIT_NAIVE = 0, 1
 FLAG_ALLOW_UNSTABLE, FLAG_PIXEL_INTEGRAL = 1, 2
+TUNE_REFRESH = 8   # tdse_autotune flag: time the candidates even on a cache hit
 
 # every symbol include/tdse.h declares
 EXPORTS = [
@@ -37,6 +38,8 @@ EXPORTS = [
     "tdse_batch_destroy", "tdse_hbm_probe", "tdse_interpolate_potential",
     "tdse_dissimilarity_workspace_size", "tdse_dissimilarity", "tdse_set_cap_paper",
     "tdse_time_step_paper", "tdse_batch_set_two_step", "tdse_autotune", "tdse_paper_layout_run",
+    "tdse_timing_read_split", "tdse_batch_workspace_size",
+    "tdse_batch_bind_workspace",
 ]
 
 
@@ -134,6 +137,7 @@ def load():
         "tdse_copy_scalars": (i32, [vp, dp, i64]),
         "tdse_set_timing": (i32, [vp, i32]),
         "tdse_timing_read": (i32, [vp, dp, ctypes.POINTER(i64)]),
+        "tdse_timing_read_split": (i32, [vp, dp, ctypes.POINTER(i64)]),
         "tdse_bind_pingpong": (i32, [vp, vp, vp]),
         "tdse_adjoint_workspace_size": (i32, [ctypes.POINTER(Desc), i64, i32,
                                               ctypes.POINTER(ctypes.c_size_t)]),
@@ -145,6 +149,8 @@ def load():
         "tdse_batch_member": (i32, [vp, i32, ctypes.POINTER(vp)]),
         "tdse_batch_set_tile": (i32, [vp, i32, i32, i32, i32]),
         "tdse_batch_set_two_step": (i32, [vp, i32, i32, i32, i32, i32, i32]),
+        "tdse_batch_workspace_size": (i32, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "tdse_batch_bind_workspace": (i32, [vp, vp, ctypes.c_size_t]),
         "tdse_batch_prepare": (i32, [vp]),
         "tdse_batch_run": (i32, [vp, i64]),
         "tdse_batch_status": (i32, [vp, ctypes.POINTER(i32)]),
@@ -430,6 +436,16 @@ class Sim:
         self._check(self.lib.tdse_timing_read(self.h, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(("half_i", "half_r", "fused", "two_step"))}
 
+    def timing_read_split(self):
+        """As timing_read, with the launches that write a record under the
+        same names plus '_rec'."""
+        ms = (ctypes.c_double * 8)()
+        n = (ctypes.c_int64 * 8)()
+        self._check(self.lib.tdse_timing_read_split(self.h, ms, n))
+        names = ("half_i", "half_r", "fused", "two_step")
+        names = names + tuple(k + "_rec" for k in names)
+        return {k: (ms[i], n[i]) for i, k in enumerate(names)}
+
     def autotune(self, steps: int = 10, flags: int = 0) -> Tile:
         """Library autotuner: times its candidate tiles on this grid, keeps the
         fastest.  The state is spent (set a new one before stepping)."""
@@ -601,6 +617,12 @@ class Batch:
             h = ctypes.c_void_p()
             self._check(self.lib.tdse_batch_member(self.b, i, ctypes.byref(h)))
             self.members.append(Sim(d, device=self.device, stream=self.stream, handle=h))
+        # the batch's device tables: caller-owned memory bound to the batch
+        nb = ctypes.c_size_t()
+        self._check(self.lib.tdse_batch_workspace_size(self.b, ctypes.byref(nb)))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.tdse_batch_bind_workspace(self.b, ctypes.c_void_p(self.ws.data_ptr()),
+                                                       int(nb.value)))
         torch.cuda.synchronize(self.device)
 
     def _check(self, st):

@@ -97,15 +97,41 @@ def test_workspace_size_scales_and_is_aligned():
     assert a % 256 == 0 and b > a
 
 
-def test_create_rejects_unsupported_x_extent():
+def test_create_accepts_any_x_extent():
+    """Any number of divisions along x (section 2.3): nx = 67, 130, 1100 (no
+    layout over 64 lanes) are created like nx = 37 (TDSE_ERR_DEVICE only
+    where no GPU is present)."""
+    L = tdse.load()
+    for nx in (37, 67, 130, 1100):
+        h = ctypes.c_void_p()
+        d = base_desc(nx=nx)
+        assert L.tdse_create(ctypes.byref(d), None, ctypes.byref(h)) in (tdse.OK, tdse.ERR_DEVICE)
+        if h.value:
+            assert L.tdse_destroy(h) == tdse.OK
+
+
+@pytest.mark.parametrize("prec,nx,ny,ok", [
+    ("f32", 2048, 262144, False),   # a 2 GiB plane: 32-bit plane offsets would overflow
+    ("f64", 1024, 262144, False),
+    ("f32", 2048, 262143, True),    # 8 KiB below 2 GiB: the last supported plane height
+    ("f64", 1024, 262143, True),
+])
+def test_plane_size_limit(prec, nx, ny, ok):
+    """Byte offsets within a z plane are 32-bit in the kernels: a plane of
+    0x7ffffff0 bytes or more is refused before anything touches a device,
+    by the description check and by tdse_create alike."""
+    d = base_desc(nx=nx, ny=ny, nz=2, k_det=0, precision=prec)
+    want = tdse.OK if ok else tdse.ERR_UNSUPPORTED
+    assert tdse.validate_desc(d) == want
     L = tdse.load()
     h = ctypes.c_void_p()
-    d = base_desc(nx=67)  # prime > 64: cannot be spread over 64 lanes
-    assert L.tdse_create(ctypes.byref(d), None, ctypes.byref(h)) == tdse.ERR_UNSUPPORTED
-    d = base_desc(nx=37)
-    assert L.tdse_create(ctypes.byref(d), None, ctypes.byref(h)) in (tdse.OK, tdse.ERR_DEVICE)
-    if h.value:
-        assert L.tdse_destroy(h) == tdse.OK
+    st = L.tdse_create(ctypes.byref(d), None, ctypes.byref(h))
+    if ok:
+        assert st in (tdse.OK, tdse.ERR_DEVICE)
+        if h.value:
+            assert L.tdse_destroy(h) == tdse.OK
+    else:
+        assert st == tdse.ERR_UNSUPPORTED and not h.value
 
 
 def test_wavevector_agrees_with_oracle_reading_of_eq4():

@@ -3,7 +3,9 @@ against central finite differences of the GPU forward run (arXiv 2401.07416
 section 2.1, eqs. (8)-(10), (15); the gradient is of a loss of the detection
 records).  Tolerances: FP64 gradient vs FP64 oracle adjoint <= 1e-10
 (max-norm relative); FP32 gradient vs FP64 oracle <= 2e-3 (relative L2);
-FP64 end-to-end gradient vs central differences <= 1e-5 relative."""
+FP64 end-to-end gradient vs central differences <= 1e-5 relative; the
+reverse sweep as the transpose of the forward map (dot-product test) and a
+second-order Taylor remainder in the potential, FP64."""
 import sys
 
 import numpy as np
@@ -206,3 +208,81 @@ def test_one_pass_reverse_step_equals_the_two_phase_form(prec):
     b, _ = gpu_adjoint(p, prec, pingpong=False)
     for x, y, name in zip(a, b, ("dL/dV", "dL/dR0", "dL/dI0")):
         assert np.array_equal(x, y), name
+
+
+def gpu_forward_and_adjoint(p, R0, I0, V, dt, adjoint=True):
+    """FP64 GPU run at a fixed time step: the record loss L = sum rho_bar *
+    rho (in FP64 from the records) and, if asked, (dL/dV, dL/dR0, dL/dI0)
+    from the library's reverse sweep."""
+    nx, ny, nz = p["shape"]
+    # the perturbed potentials of the Taylor test move E_max by a fraction of
+    # a percent: the fixed dt may sit that far above hbar / E_max (the
+    # leapfrog's own limit is twice that bound)
+    d = tdse.make_desc(nx, ny, nz, *p["sp"], hbar=p["hbar"], mass=p["mass"], dt=dt,
+                       precision="f64", k_det=p["kdet"], record_every=p["h"],
+                       max_records=p["N"] // p["h"] + 1, flags=tdse.FLAG_ALLOW_UNSTABLE)
+    s = tdse.Sim(d, pingpong=True)
+    s.v.copy_(torch.from_numpy(V))
+    s.set_cap_quadratic(*p["cap"])
+    s.finalize()
+    s.set_state(torch.from_numpy(R0), torch.from_numpy(I0), step=0)
+    if adjoint:
+        s.bind_adjoint(p["N"], p["K"])
+    s.step(p["N"])
+    rho, _ = s.records_host()
+    L = float(np.sum(p["rho_bar"] * rho))
+    if not adjoint:
+        return L, None
+    gV, gR, gI = s.adjoint(torch.from_numpy(p["rho_bar"]))
+    return L, (gV.cpu().numpy(), gR.cpu().numpy(), gI.cpu().numpy())
+
+
+def test_adjoint_is_the_transpose_of_the_forward_map():
+    """For a fixed potential the records are quadratic in the initial state,
+    rho^n = (A_n x)^2 with A_n linear (the leapfrog with the CAP), so the
+    loss L(x) = x^T Q x with Q symmetric and the reverse sweep must return
+    grad L(x) = 2 Q x: the dot-product test <y, grad L(x)> = <x, grad L(y)>
+    for two unrelated states, and L(x) = <x, grad L(x)> / 2 (degree-2
+    homogeneity), both to FP64 rounding."""
+    p = small_problem(seed=4)
+    rng = np.random.default_rng(44)
+    g = oracle.Grid(*p["shape"], *p["sp"], hbar=p["hbar"], mass=p["mass"])
+    dt = 0.9 * g.hbar / oracle.emax(g, p["V"])
+    x = (p["R0"], p["I0"])
+    y = (rng.standard_normal(p["R0"].shape), rng.standard_normal(p["I0"].shape))
+    Lx, (_, gxR, gxI) = gpu_forward_and_adjoint(p, *x, p["V"], dt)
+    Ly, (_, gyR, gyI) = gpu_forward_and_adjoint(p, *y, p["V"], dt)
+    yx = float(np.sum(y[0] * gxR) + np.sum(y[1] * gxI))
+    xy = float(np.sum(x[0] * gyR) + np.sum(x[1] * gyI))
+    scale = float(np.sqrt(np.sum(gxR ** 2) + np.sum(gxI ** 2)) *
+                  np.sqrt(np.sum(y[0] ** 2) + np.sum(y[1] ** 2)))
+    say("dot-product test", yx, xy, "scale", scale)
+    assert abs(yx - xy) <= 1e-12 * scale
+    for L, s, gR, gI in ((Lx, x, gxR, gxI), (Ly, y, gyR, gyI)):
+        half = 0.5 * float(np.sum(s[0] * gR) + np.sum(s[1] * gI))
+        say("homogeneity", L, half)
+        assert half == pytest.approx(L, rel=1e-12)
+
+
+def test_potential_gradient_taylor_remainder_is_second_order():
+    """Taylor test of dL/dV (the potential enters the propagator, so L is
+    not quadratic in it): the remainder r(e) = |L(V + e dV) - L(V) -
+    e <dL/dV, dV>| falls as e^2 (ratio 4 per halving of e) until rounding
+    takes over, at a fixed time step."""
+    p = small_problem(seed=5)
+    rng = np.random.default_rng(55)
+    g = oracle.Grid(*p["shape"], *p["sp"], hbar=p["hbar"], mass=p["mass"])
+    dt = 0.9 * g.hbar / oracle.emax(g, p["V"])
+    dV = rng.standard_normal(p["V"].shape)
+    L0, (gV, _, _) = gpu_forward_and_adjoint(p, p["R0"], p["I0"], p["V"], dt)
+    slope = float(np.sum(gV * dV))
+    eps = [0.2, 0.1, 0.05, 0.025]
+    r = []
+    for e in eps:
+        Le, _ = gpu_forward_and_adjoint(p, p["R0"], p["I0"], p["V"] + e * dV, dt, adjoint=False)
+        r.append(abs(Le - L0 - e * slope))
+    ratios = [r[i] / r[i + 1] for i in range(len(r) - 1)]
+    say("Taylor remainders", r, "ratios", ratios, "first-order term", abs(eps[-1] * slope))
+    assert r[-1] < 1e-2 * abs(eps[-1] * slope)
+    for q in ratios:
+        assert 3.6 <= q <= 4.4

@@ -184,3 +184,32 @@ def test_library_autotuner_picks_a_tile_and_spends_the_state():
     s.set_state(r0.psi_r, r0.psi_i, step=0)
     s.step(100)
     assert bool((s.psi_r == ref.psi_r).all()) and bool((s.psi_i == ref.psi_i).all())
+
+
+def test_autotuner_cache_round_trip(tmp_path, monkeypatch):
+    """TDSE_TUNE_CACHE: the first tuning of a case times the candidates and
+    writes one line for it; the next finds the line, sets that tile without
+    running anything (the state is kept); TDSE_TUNE_REFRESH times again and
+    leaves one line per case."""
+    path = tmp_path / "tiles.txt"
+    monkeypatch.setenv("TDSE_TUNE_CACHE", str(path))
+    w = workloads.c2_reduced().with_(steps=100)
+    s = tdse.sim_from_workload(w, precision="f32", steps=100)
+    t1 = s.autotune(steps=4, flags=6)
+    lines = path.read_text().splitlines()
+    say("cache after tuning", lines)
+    assert len(lines) == 1 and lines[0].startswith("tdse-tune-v1 64 64 128 0 ")
+    s2 = tdse.sim_from_workload(w, precision="f32", steps=100)
+    t2 = s2.autotune(steps=4, flags=6)
+    assert t2.as_dict() == t1.as_dict()
+    s2.step(10)   # a hit keeps the state
+    assert s2.detect().step == 10
+    s3 = tdse.sim_from_workload(w, precision="f32", steps=100)
+    s3.autotune(steps=4, flags=6 | tdse.TUNE_REFRESH)
+    with pytest.raises(tdse.TdseError) as e:   # timed again: the state is spent
+        s3.step(2)
+    assert e.value.status == tdse.ERR_STATE
+    assert len(path.read_text().splitlines()) == 1
+    s4 = tdse.sim_from_workload(w.with_(nx=48), precision="f32", steps=100)
+    s4.autotune(steps=4, flags=6)
+    assert len(path.read_text().splitlines()) == 2

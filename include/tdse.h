@@ -82,7 +82,7 @@ enum {
     TDSE_ERR_DEVICE = 5,      /* HIP runtime error; message kept */
     TDSE_ERR_OOM = 6,         /* device allocation failed (setup temporaries) */
     TDSE_ERR_UNSUPPORTED = 7, /* shape or option the library does not handle */
-    TDSE_ERR_CAPACITY = 8     /* the record buffer would overflow */
+    TDSE_ERR_CAPACITY = 8     /* the record buffer (or the no-alloc scratch) would overflow */
 };
 
 enum { TDSE_BC_PERIODIC = 0, TDSE_BC_ZERO = 1 };
@@ -432,6 +432,32 @@ tdse_status tdse_dissimilarity_workspace_size(int32_t K, int32_t T, size_t* byte
 tdse_status tdse_dissimilarity(int32_t precision, const void* frames, int32_t K, int32_t T, int64_t P,
                                const double* weights, double dA, double* out, void* workspace,
                                size_t workspace_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and launches as tdse_dissimilarity, with the partial sums in
+ * a fixed device array inside the library instead of a caller workspace.
+ * The array holds TDSE_DISSIM_NOALLOC_MAX_BYTES on every GPU the library
+ * runs on, from the load of its code object until the process ends; the
+ * first call on a device looks up its address there (hipGetSymbolAddress),
+ * later calls reuse it.  No call allocates or frees anything.  Arguments
+ * as tdse_dissimilarity without the workspace; the kernels run on the
+ * current device, on stream (a hipStream_t of that device, may be null);
+ * the result is bitwise that of tdse_dissimilarity.  Every call on one GPU
+ * shares its array and leaves its partial sums there (each call writes
+ * every entry it reads, so nothing needs clearing): calls whose executions
+ * can overlap on one GPU (unordered streams, host threads) race and give
+ * wrong results; calls on one stream are ordered.  TDSE_ERR_CAPACITY when
+ * the partial sums of the precision's kernel exceed the maximum, checked
+ * before anything is launched: ceil(T / frames per chunk) x K x K doubles,
+ * at most tdse_dissimilarity_workspace_size(K, T) (FP32 frames of K = 879
+ * trajectories x T = 77 frames need 53 MiB and fit; FP64 frames of that
+ * size need 118 MiB and do not).  Other errors as tdse_dissimilarity;
+ * TDSE_ERR_UNSUPPORTED on a device index >= 64. */
+#define TDSE_DISSIM_NOALLOC_MAX_BYTES (64u << 20)
+tdse_status tdse_dissimilarity_noalloc(int32_t precision, const void* frames, int32_t K, int32_t T,
+                                       int64_t P, const double* weights, double dA, double* out,
+                                       void* stream);
 
 /* HBM probe: the practical bandwidth ceiling of this device, measured by
  * streaming kernels that do no part of the method.  kind 0: a copy, bufs[0]

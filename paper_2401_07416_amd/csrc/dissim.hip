@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/tdse.h"
 
@@ -460,16 +461,15 @@ extern "C" tdse_status tdse_dissimilarity_workspace_size(int32_t K, int32_t T, s
     return TDSE_OK;
 }
 
-extern "C" tdse_status tdse_dissimilarity(int32_t precision, const void* frames, int32_t K, int32_t T,
-                                          int64_t P, const double* weights, double dA, double* out,
-                                          void* workspace, size_t workspace_bytes, void* stream) {
-    if (!frames || !weights || !out || !workspace || K < 1 || T < 1 || P < 1) return TDSE_ERR_ARG;
-    if (precision != TDSE_F32 && precision != TDSE_F64) return TDSE_ERR_ARG;
-    if (!(dA > 0)) return TDSE_ERR_ARG;
+namespace {
+
+// The launches of tdse_dissimilarity with the partial sums at `part`
+// (ntc x K x K doubles of the plan; every entry the reduction reads is
+// written first, so stale contents do no harm).
+tdse_status dissim_launch(int32_t precision, const void* frames, int32_t K, int32_t T, int64_t P,
+                          const double* weights, double dA, double* out, double* part,
+                          hipStream_t st) {
     const Plan p = precision == TDSE_F32 ? plan_gram(K, T) : plan_of(K, T);
-    if (workspace_bytes < (size_t)p.ntc * K * K * sizeof(double)) return TDSE_ERR_ARG;
-    if ((long)p.npb * p.ntc > (1L << 31) - 1) return TDSE_ERR_ARG;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     const dim3 grid((unsigned)(p.npb * p.ntc));
     if (precision == TDSE_F32) {
         GramArgs g;
@@ -482,7 +482,7 @@ extern "C" tdse_status tdse_dissimilarity(int32_t precision, const void* frames,
         g.nb = p.nb;
         g.npb = p.npb;
         g.tpc = p.tpc;
-        g.part = static_cast<double*>(workspace);
+        g.part = part;
         const bool vec = P % 4 == 0 && (reinterpret_cast<uintptr_t>(frames) & 15) == 0;
         if (vec)
             hipLaunchKernelGGL(dissim_gram_kernel<true>, grid, dim3(GTHREADS), 0, st, g);
@@ -499,13 +499,79 @@ extern "C" tdse_status tdse_dissimilarity(int32_t precision, const void* frames,
         a.nb = p.nb;
         a.npb = p.npb;
         a.tpc = p.tpc;
-        a.part = static_cast<double*>(workspace);
+        a.part = part;
         hipLaunchKernelGGL(dissim_kernel<double>, grid, dim3(256), 0, st, a);
     }
     if (hipGetLastError() != hipSuccess) return TDSE_ERR_DEVICE;
     const long kk = (long)K * K;
     const unsigned g = (unsigned)std::min<long>((kk + 255) / 256, 4096);
     hipLaunchKernelGGL(dissim_reduce_kernel, dim3(g), dim3(256), 0, st,
-                       static_cast<const double*>(workspace), p.ntc, kk, out);
+                       static_cast<const double*>(part), p.ntc, kk, out);
     return hipGetLastError() == hipSuccess ? TDSE_OK : TDSE_ERR_DEVICE;
+}
+
+// Checks shared by both entry points; *need = bytes of partial sums.
+tdse_status dissim_check(int32_t precision, const void* frames, int32_t K, int32_t T, int64_t P,
+                         const double* weights, double dA, const double* out, size_t* need) {
+    if (!frames || !weights || !out || K < 1 || T < 1 || P < 1) return TDSE_ERR_ARG;
+    if (precision != TDSE_F32 && precision != TDSE_F64) return TDSE_ERR_ARG;
+    if (!(dA > 0)) return TDSE_ERR_ARG;
+    const Plan p = precision == TDSE_F32 ? plan_gram(K, T) : plan_of(K, T);
+    if ((long)p.npb * p.ntc > (1L << 31) - 1) return TDSE_ERR_ARG;
+    *need = (size_t)p.ntc * K * K * sizeof(double);
+    return TDSE_OK;
+}
+
+// Partial sums of tdse_dissimilarity_noalloc: one fixed array per GPU,
+// allocated with the code object, never by a call.  Host code must not use
+// this name as a device address (on the host it names a stand-in); it uses
+// the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocScratchBytes = (size_t)TDSE_DISSIM_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) double scratch[kNoallocScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device.
+tdse_status scratch_on_current_device(double** ptr) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return TDSE_ERR_DEVICE;
+    if (dev >= kMaxDevices) return TDSE_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TDSE_ERR_DEVICE;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return TDSE_OK;
+}
+
+}  // namespace
+
+extern "C" tdse_status tdse_dissimilarity(int32_t precision, const void* frames, int32_t K, int32_t T,
+                                          int64_t P, const double* weights, double dA, double* out,
+                                          void* workspace, size_t workspace_bytes, void* stream) {
+    size_t need = 0;
+    const tdse_status st = dissim_check(precision, frames, K, T, P, weights, dA, out, &need);
+    if (st != TDSE_OK) return st;
+    if (!workspace || workspace_bytes < need) return TDSE_ERR_ARG;
+    return dissim_launch(precision, frames, K, T, P, weights, dA, out, static_cast<double*>(workspace),
+                         static_cast<hipStream_t>(stream));
+}
+
+extern "C" tdse_status tdse_dissimilarity_noalloc(int32_t precision, const void* frames, int32_t K,
+                                                  int32_t T, int64_t P, const double* weights, double dA,
+                                                  double* out, void* stream) {
+    size_t need = 0;
+    tdse_status st = dissim_check(precision, frames, K, T, P, weights, dA, out, &need);
+    if (st != TDSE_OK) return st;
+    if (need > kNoallocScratchBytes) return TDSE_ERR_CAPACITY;
+    double* part = nullptr;
+    st = scratch_on_current_device(&part);
+    if (st != TDSE_OK) return st;
+    return dissim_launch(precision, frames, K, T, P, weights, dA, out, part,
+                         static_cast<hipStream_t>(stream));
 }

@@ -1509,7 +1509,7 @@ const char* tdse_status_string(tdse_status s) {
         case TDSE_ERR_DEVICE: return "HIP device error";
         case TDSE_ERR_OOM: return "device allocation failed";
         case TDSE_ERR_UNSUPPORTED: return "unsupported shape or option";
-        case TDSE_ERR_CAPACITY: return "record buffer too small";
+        case TDSE_ERR_CAPACITY: return "record buffer or fixed scratch too small";
         default: return "unknown status";
     }
 }

@@ -38,7 +38,7 @@ EXPORTS = [
     "tdse_batch_destroy", "tdse_hbm_probe", "tdse_interpolate_potential",
     "tdse_dissimilarity_workspace_size", "tdse_dissimilarity", "tdse_set_cap_paper",
     "tdse_time_step_paper", "tdse_batch_set_two_step", "tdse_autotune", "tdse_paper_layout_run",
-    "tdse_timing_read_split", "tdse_batch_workspace_size",
+    "tdse_dissimilarity_noalloc", "tdse_timing_read_split", "tdse_batch_workspace_size",
     "tdse_batch_bind_workspace",
 ]
 
@@ -167,6 +167,7 @@ def load():
         "tdse_dissimilarity_workspace_size": (i32, [i32, i32, ctypes.POINTER(ctypes.c_size_t)]),
         "tdse_dissimilarity": (i32, [i32, vp, i32, i32, i64, vp, ctypes.c_double, vp, vp,
                                      ctypes.c_size_t, vp]),
+        "tdse_dissimilarity_noalloc": (i32, [i32, vp, i32, i32, i64, vp, ctypes.c_double, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -545,6 +546,38 @@ def dissimilarity(frames, weights, dA: float):
                                 ctypes.c_void_p(w.data_ptr()), float(dA),
                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                 nb.value, ctypes.c_void_p(stream))
+    if st != OK:
+        raise TdseError(st, lib.tdse_status_string(st).decode())
+    return out
+
+
+# TDSE_DISSIM_NOALLOC_MAX_BYTES of include/tdse.h
+DISSIM_NOALLOC_MAX_BYTES = 64 << 20
+
+
+def dissimilarity_noalloc(frames, weights, dA: float, out=None):
+    """d_kj of eq. (16) through tdse_dissimilarity_noalloc: the library's
+    fixed per-GPU scratch instead of a workspace (for callers that cannot
+    allocate; the binding itself allocates `out` unless one is given, a
+    contiguous [K][K] float64 CUDA tensor).  frames and weights as for
+    dissimilarity(); weights must already be a float64 CUDA tensor."""
+    import torch
+    lib = load()
+    if frames.dim() != 3 or not frames.is_cuda or not frames.is_contiguous():
+        raise ValueError("frames must be a contiguous [K][T][P] CUDA tensor")
+    prec = {torch.float32: F32, torch.float64: F64}[frames.dtype]
+    K, T, P = frames.shape
+    if not (weights.is_cuda and weights.dtype == torch.float64 and weights.shape == (T,)
+            and weights.is_contiguous()):
+        raise ValueError("weights must be a contiguous float64 CUDA tensor of one entry per frame")
+    if out is None:
+        out = torch.empty((K, K), dtype=torch.float64, device=frames.device)
+    elif not (out.is_cuda and out.dtype == torch.float64 and out.shape == (K, K) and out.is_contiguous()):
+        raise ValueError("out must be a contiguous [K][K] float64 CUDA tensor")
+    stream = torch.cuda.current_stream(frames.device).cuda_stream
+    st = lib.tdse_dissimilarity_noalloc(prec, ctypes.c_void_p(frames.data_ptr()), K, T, P,
+                                        ctypes.c_void_p(weights.data_ptr()), float(dA),
+                                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream))
     if st != OK:
         raise TdseError(st, lib.tdse_status_string(st).decode())
     return out

@@ -58,6 +58,7 @@ struct Fused2Args {
     int ntx, ntiles, zc, nzc, nwg;
     int bcx, bcy, bcz;
     int k_det, k_up;
+    int ulo, uhi;         // planes [ulo, uhi) have no absorption (ca = cb = 1)
     double* flux_a;       // [2][ntiles], step n -> n+1
     double* flux_b;       // [2][ntiles], step n+1 -> n+2
     // record of level n+2 (REC instances only)
@@ -244,6 +245,34 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     using IsR = std::integral_constant<bool, true>;
     using IsI = std::integral_constant<bool, false>;
 
+    // The straight-line iteration (one row per thread, 1024 threads): the
+    // cells of one phase with unit CAP factors from the LDS buffer src,
+    // and the write slot of each buffer (wslot + buffer index x wstep; idle
+    // threads: the slot past the eight buffers, wstep 0).
+    constexpr bool FAST = M == 1 && NT == 1024;
+    const bool fast_grid = !sel_xy;
+    const bool need4 = M != 1 || wave_needed(4);
+    T* const wslot = live ? buf(0, 0) + rowb[0] * ex + c0 : lds + 8 * fstride;
+    const long wstep = live ? fstride : 0;
+    const int rofs = rowb[0] * ex + c0;
+    auto fast_cells = [&](auto is_r, const VT& zl, const VT& c, const VT& zr, const T* src, const VT& uo,
+                          const VT& vtv, VT& out) {
+        constexpr bool IS_R = decltype(is_r)::value;
+        const T* row = src + rofs;
+        const VT yl = *reinterpret_cast<const VT*>(row - ex);
+        const VT yr = *reinterpret_cast<const VT*>(row + ex);
+        const T xle = row[-1], xre = row[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const T cc = c.v[e];
+            const T xl = e > 0 ? c.v[e - 1] : xle;
+            const T xr = e < W - 1 ? c.v[e + 1] : xre;
+            const T hx = hterm(cc, xl, xr, yl.v[e], yr.v[e], zl.v[e], zr.v[e], vtv.v[e], a.cx, a.cy, a.cz,
+                               a.dlo);
+            out.v[e] = IS_R ? upd_R_unit(hx, uo.v[e]) : upd_I_unit(hx, uo.v[e]);
+        }
+    };
+
     auto load3 = [&](int pr, int pi, VT(&r)[M], VT(&iv)[M], VT(&vv)[M]) {
         const int gr = gplane(pr), gi = gplane(pi);
         const auto rR = prs(a.R0, gr), rI = prs(a.I0, gi), rV = prs(a.V, gi);
@@ -312,20 +341,44 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
         for (int i = 0; i < M; ++i)
 #pragma unroll
             for (int e = 0; e < W; ++e) Vw[3][i].v[e] = vterm(Vw[3][i].v[e], a.cv, a.d0);
-        // stage R^n(k+4) for the next iteration's A1
-        if (live) {
-#pragma unroll
-            for (int i = 0; i < M; ++i) *reinterpret_cast<VT*>(buf(0, par ^ 1) + rowb[i] * ex + c0) = rN[i];
-        }
         VT nD[M];   // R^{n+2}(k), formed by B2
-        // A1: I^{n+1/2}(k+3)
-        phase(IsI{}, 1, k + 3, rL, rC, rN, buf(0, par), io, Vw[3], nA, buf(1, par ^ 1));
-        // B1: R^{n+1}(k+2)
-        phase(IsR{}, 2, k + 2, iL, iC, nA, buf(1, par), rL, Vw[2], nB, buf(2, par ^ 1));
-        // A2: I^{n+3/2}(k+1)
-        phase(IsI{}, 3, k + 1, bL, bC, nB, buf(2, par), iL, Vw[1], nC, buf(3, par ^ 1));
-        // B2: R^{n+2}(k)
-        phase(IsR{}, 4, k, jL, jC, nC, buf(3, par), bL, Vw[0], nD, nullptr);
+        if (FAST && fast_grid && k >= k0 && k >= a.ulo && k + 3 < a.uhi) {
+            // the common iteration as one straight-line block: all four
+            // planes inside the chunk's dependence range and the grid, no
+            // absorption on them, periodic x and y.  Every LDS read of the
+            // iteration comes before its first LDS write (the reads take
+            // parity k, the writes parity k + 1), so the compiler may issue
+            // a phase's neighbour reads ahead of the previous phase's
+            // arithmetic; idle threads write a slot past the buffers
+            // instead of branching around the writes.  Same bits as the
+            // phases below.
+            fast_cells(IsI{}, rL[0], rC[0], rN[0], buf(0, par), io[0], Vw[3][0], nA[0]);
+            fast_cells(IsR{}, iL[0], iC[0], nA[0], buf(1, par), rL[0], Vw[2][0], nB[0]);
+            fast_cells(IsI{}, bL[0], bC[0], nB[0], buf(2, par), iL[0], Vw[1][0], nC[0]);
+            if (need4)
+                fast_cells(IsR{}, jL[0], jC[0], nC[0], buf(3, par), bL[0], Vw[0][0], nD[0]);
+            else
+                nD[0] = zero_vec();
+            *reinterpret_cast<VT*>(wslot + (0 * 2 + (par ^ 1)) * wstep) = rN[0];
+            *reinterpret_cast<VT*>(wslot + (1 * 2 + (par ^ 1)) * wstep) = nA[0];
+            *reinterpret_cast<VT*>(wslot + (2 * 2 + (par ^ 1)) * wstep) = nB[0];
+            *reinterpret_cast<VT*>(wslot + (3 * 2 + (par ^ 1)) * wstep) = nC[0];
+        } else {
+            // stage R^n(k+4) for the next iteration's A1
+            if (live) {
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+                    *reinterpret_cast<VT*>(buf(0, par ^ 1) + rowb[i] * ex + c0) = rN[i];
+            }
+            // A1: I^{n+1/2}(k+3)
+            phase(IsI{}, 1, k + 3, rL, rC, rN, buf(0, par), io, Vw[3], nA, buf(1, par ^ 1));
+            // B1: R^{n+1}(k+2)
+            phase(IsR{}, 2, k + 2, iL, iC, nA, buf(1, par), rL, Vw[2], nB, buf(2, par ^ 1));
+            // A2: I^{n+3/2}(k+1)
+            phase(IsI{}, 3, k + 1, bL, bC, nB, buf(2, par), iL, Vw[1], nC, buf(3, par ^ 1));
+            // B2: R^{n+2}(k)
+            phase(IsR{}, 4, k, jL, jC, nC, buf(3, par), bL, Vw[0], nD, nullptr);
+        }
         const int pB = k + 2, pC = k + 1, pD = k;
         if (pC >= k0 && pC < k1) {
             const auto rI = prs(a.I1, pC);

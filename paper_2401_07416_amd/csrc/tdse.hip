@@ -88,6 +88,9 @@ struct tdse_ctx {
     std::vector<double> wcap;
     std::vector<double> ca_h, cb_h;
     std::vector<float> caf_h, cbf_h;
+    // the longest run of planes [unit_lo, unit_hi) without absorption (ca =
+    // cb = 1 exactly in the state precision)
+    int unit_lo = 0, unit_hi = 0;
     int64_t step = 0;
     int pending = 0;
     std::string err;
@@ -615,7 +618,8 @@ Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc, int nt) {
     f.ntiles = f.ntx * f.nty;
     f.nzc = (int)((d.nz + zc - 1) / zc);
     f.nwg = f.ntiles * f.nzc;
-    f.lds = (size_t)8 * (f.ey + 2) * f.ex * es;
+    // eight buffers and one vector slot that idle threads write
+    f.lds = (size_t)8 * (f.ey + 2) * f.ex * es + 16;
     // flux and partial slots are sized for ny per step / plane; 8 B per
     // wavefront of static LDS for the reductions
     f.ok = f.ntiles <= d.ny && f.lds + 8 * (size_t)(nt / 64) <= (size_t)h->lds_max &&
@@ -669,6 +673,8 @@ Fused2Args<T> make_fused2_args(tdse_ctx* h, const Fused2Dims& f, bool rec, long 
     a.pixel = (rec && (d.flags & TDSE_FLAG_PIXEL_INTEGRAL)) ? h->pix : nullptr;
     a.pixel_w = (double)d.record_every * h->dt;
     a.nt_out = stream_outputs(state_bytes(d));
+    a.ulo = h->unit_lo;
+    a.uhi = h->unit_hi;
     return a;
 }
 
@@ -1779,6 +1785,24 @@ static tdse_status upload_tables(tdse_ctx* h) {
         h->cbf_h.assign(h->cb_h.begin(), h->cb_h.end());
         HIPCHK(h, hipMemcpyAsync(h->ca, h->caf_h.data(), nz * 4, hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->cb, h->cbf_h.data(), nz * 4, hipMemcpyHostToDevice, h->stream));
+    }
+    h->unit_lo = h->unit_hi = 0;
+    for (size_t k = 0; k < nz;) {
+        auto unit = [&](size_t q) {
+            return d.precision == TDSE_F64 ? (h->ca_h[q] == 1.0 && h->cb_h[q] == 1.0)
+                                           : (h->caf_h[q] == 1.0f && h->cbf_h[q] == 1.0f);
+        };
+        if (!unit(k)) {
+            ++k;
+            continue;
+        }
+        size_t e = k;
+        while (e < nz && unit(e)) ++e;
+        if (e - k > (size_t)(h->unit_hi - h->unit_lo)) {
+            h->unit_lo = (int)k;
+            h->unit_hi = (int)e;
+        }
+        k = e;
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return TDSE_OK;

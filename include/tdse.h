@@ -495,17 +495,20 @@ tdse_status tdse_hbm_probe(int32_t kind, void* const* bufs, int64_t n, int32_t g
  * checkpoint).  two_step_tx = interior tile width (a multiple of the vector
  * width, >= 8), two_step_threads = threads per workgroup (256, 512 or 1024),
  * two_step_rows = rows per thread (2 or 3 with 256 threads, 1 or 2 with
- * 512, 1 with 1024), so the interior tile height is two_step_ty = (threads
- * / ((tx + 8) / vector width)) * rows - 8 (read-only); two_step_zc = z
- * planes per workgroup, two_step_prefetch != 0 loads the next plane's
- * inputs one iteration ahead.  The sweep needs at most ny tiles per plane
+ * 512, 1 with 1024), so the interior tile height is at most (threads /
+ * ((tx + 8) / vector width)) * rows - 8; two_step_ty > 0 asks for a
+ * shorter tile (rounded up to whole rows per pass; the threads past the
+ * last row idle), 0 for the tallest, and tdse_get_tile returns the height
+ * in use; two_step_zc = z planes per workgroup, two_step_prefetch != 0
+ * loads the next plane's inputs one iteration ahead.  The sweep needs at most ny tiles per plane
  * and its LDS ((2 x 4) buffers of (ty + 10) x (tx + 8) values, plus 8 bytes
  * per wavefront) within the device's per-workgroup limit.  TDSE_ERR_ARG for
  * a thread count other than 256, 512 or 1024; TDSE_ERR_UNSUPPORTED for a
  * (rows, threads) pair without a kernel or a tile that does not fit.
  *
- * tdse_create picks defaults; tdse_set_tile checks and replaces them.  The
- * last five fields are read-only; vec_groups and lanes are 0 where nx has
+ * tdse_create picks defaults; tdse_set_tile checks and replaces them.
+ * vec_elems, vec_groups, lanes and band_rows are read-only (and
+ * two_step_ty as described above); vec_groups and lanes are 0 where nx has
  * no layout over 64 lanes (the any-width half-step kernel runs).  fused != 0
  * with a one-pass band that does not fit (whole x rows in LDS: nx / W <=
  * fused_threads) is accepted together with two_step: the sweep then takes

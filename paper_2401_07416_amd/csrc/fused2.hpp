@@ -252,6 +252,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     constexpr bool FAST = M == 1 && NT == 1024;
     const bool fast_grid = !sel_xy;
     const bool need4 = M != 1 || wave_needed(4);
+    const bool wave_live = wlo < a.rpp;   // some thread of the wavefront owns a row
     T* const wslot = live ? buf(0, 0) + rowb[0] * ex + c0 : lds + 8 * fstride;
     const long wstep = live ? fstride : 0;
     const int rofs = rowb[0] * ex + c0;
@@ -352,17 +353,23 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
             // arithmetic; idle threads write a slot past the buffers
             // instead of branching around the writes.  Same bits as the
             // phases below.
-            fast_cells(IsI{}, rL[0], rC[0], rN[0], buf(0, par), io[0], Vw[3][0], nA[0]);
-            fast_cells(IsR{}, iL[0], iC[0], nA[0], buf(1, par), rL[0], Vw[2][0], nB[0]);
-            fast_cells(IsI{}, bL[0], bC[0], nB[0], buf(2, par), iL[0], Vw[1][0], nC[0]);
-            if (need4)
-                fast_cells(IsR{}, jL[0], jC[0], nC[0], buf(3, par), bL[0], Vw[0][0], nD[0]);
-            else
-                nD[0] = zero_vec();
-            *reinterpret_cast<VT*>(wslot + (0 * 2 + (par ^ 1)) * wstep) = rN[0];
-            *reinterpret_cast<VT*>(wslot + (1 * 2 + (par ^ 1)) * wstep) = nA[0];
-            *reinterpret_cast<VT*>(wslot + (2 * 2 + (par ^ 1)) * wstep) = nB[0];
-            *reinterpret_cast<VT*>(wslot + (3 * 2 + (par ^ 1)) * wstep) = nC[0];
+            if (wave_live) {
+                fast_cells(IsI{}, rL[0], rC[0], rN[0], buf(0, par), io[0], Vw[3][0], nA[0]);
+                fast_cells(IsR{}, iL[0], iC[0], nA[0], buf(1, par), rL[0], Vw[2][0], nB[0]);
+                fast_cells(IsI{}, bL[0], bC[0], nB[0], buf(2, par), iL[0], Vw[1][0], nC[0]);
+                if (need4)
+                    fast_cells(IsR{}, jL[0], jC[0], nC[0], buf(3, par), bL[0], Vw[0][0], nD[0]);
+                else
+                    nD[0] = zero_vec();
+                *reinterpret_cast<VT*>(wslot + (0 * 2 + (par ^ 1)) * wstep) = rN[0];
+                *reinterpret_cast<VT*>(wslot + (1 * 2 + (par ^ 1)) * wstep) = nA[0];
+                *reinterpret_cast<VT*>(wslot + (2 * 2 + (par ^ 1)) * wstep) = nB[0];
+                *reinterpret_cast<VT*>(wslot + (3 * 2 + (par ^ 1)) * wstep) = nC[0];
+            } else {
+                // a wavefront of idle threads (a tile shorter than the
+                // threads cover): nothing of it is stored or read
+                nA[0] = nB[0] = nC[0] = nD[0] = zero_vec();
+            }
         } else {
             // stage R^n(k+4) for the next iteration's A1
             if (live) {

@@ -52,6 +52,7 @@ struct tdse_ctx {
     // two-step sweep: interior tile width, rows per thread, z chunk
     bool two = false;
     int t2x = 56, t2m = 2, t2zc = 64, t2t = 256;
+    int t2ty = 0;   // requested interior tile height (0: the tallest the threads cover)
     bool t2pf = false;
     int lds_max = 65536;   // dynamic + static LDS per workgroup of the device
     int cus = 256;         // compute units of the device
@@ -586,7 +587,10 @@ struct Fused2Dims {
     bool ok;
 };
 
-Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc, int nt) {
+// ty_req > 0 asks for a shorter tile than the threads cover (fewer rows per
+// pass, the threads past them idle): a tile count that fills the last round
+// of workgroups can outweigh the larger rim share.
+Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc, int nt, int ty_req) {
     const tdse_desc& d = h->d;
     Fused2Dims f{};
     f.ok = false;
@@ -610,6 +614,7 @@ Fused2Dims fused2_dims(const tdse_ctx* h, int tx, int m, int zc, int nt) {
     f.ex = tx + 8;
     f.tpr = f.ex / f.W;
     f.rpp = nt / f.tpr;
+    if (ty_req > 0) f.rpp = std::min(f.rpp, (ty_req + 8 + m - 1) / m);
     f.ey = f.rpp * m;
     f.ty = f.ey - 8;
     if (f.ty < 1) return f;
@@ -1060,22 +1065,33 @@ void default_two_step(tdse_ctx* h) {
     h->t2t = cl[0].nt;
     h->t2pf = true;
     h->t2zc = (int)std::min<int64_t>(64, d.nz);
+    h->t2ty = 0;
     double best = 0.0;
     for (int i = 0; i < nc; ++i) {
-        for (int zc0 = 32; zc0 <= 256; zc0 += 4) {
-            if (zc0 > d.nz) break;
-            const Fused2Dims f = fused2_dims(h, cl[i].tx, cl[i].m, zc0, cl[i].nt);
-            // at least three quarters of one wave of workgroups, else the
-            // one-pass step (more, smaller workgroups) keeps the CUs busier
-            if (!f.ok || 4L * f.nwg < 3L * fused2_wg_per_cu(h, f, cl[i].m) * h->cus) continue;
-            const double c = fused2_cost(h, f, cl[i].m, zc0);
-            if (!h->two || c < best) {
-                best = c;
-                h->two = true;
-                h->t2x = cl[i].tx;
-                h->t2m = cl[i].m;
-                h->t2t = cl[i].nt;
-                h->t2zc = zc0;
+        const Fused2Dims tall = fused2_dims(h, cl[i].tx, cl[i].m, 64, cl[i].nt, 0);
+        if (tall.ty < 1) continue;
+        // the tallest tile the threads cover and up to a sixth shorter (a
+        // tile count that fills the last round of workgroups)
+        const int rmax = tall.rpp, rmin = std::max(1, rmax - rmax / 6);
+        for (int r = rmax; r >= rmin; --r) {
+            const int ty_req = r == rmax ? 0 : r * cl[i].m - 8;
+            if (r != rmax && ty_req < 1) break;
+            for (int zc0 = 32; zc0 <= 256; zc0 += 4) {
+                if (zc0 > d.nz) break;
+                const Fused2Dims f = fused2_dims(h, cl[i].tx, cl[i].m, zc0, cl[i].nt, ty_req);
+                // at least three quarters of one wave of workgroups, else the
+                // one-pass step (more, smaller workgroups) keeps the CUs busier
+                if (!f.ok || 4L * f.nwg < 3L * fused2_wg_per_cu(h, f, cl[i].m) * h->cus) continue;
+                const double c = fused2_cost(h, f, cl[i].m, zc0);
+                if (!h->two || c < best) {
+                    best = c;
+                    h->two = true;
+                    h->t2x = cl[i].tx;
+                    h->t2m = cl[i].m;
+                    h->t2t = cl[i].nt;
+                    h->t2zc = zc0;
+                    h->t2ty = ty_req;
+                }
             }
         }
     }
@@ -1227,7 +1243,7 @@ static tdse_status batch_prepare2_t(tdse_batch_ctx* b, bool* used) {
     for (size_t i = 0; i < n; ++i) {
         tdse_ctx* h = b->members[i];
         const int zc = (int)std::min<int64_t>(b->t2zc, h->d.nz);
-        const Fused2Dims f = fused2_dims(h, b->t2x, b->t2m, zc, b->t2t);
+        const Fused2Dims f = fused2_dims(h, b->t2x, b->t2m, zc, b->t2t, 0);
         if (!f.ok) return TDSE_OK;
         if (W == 0) W = f.W;
         if (f.W != W) return TDSE_OK;
@@ -1841,19 +1857,31 @@ tdse_status tdse_interpolate_potential(tdse_handle h, const double* table, int32
     hipLaunchKernelGGL(interp_axes_kernel, dim3((unsigned)std::min<long>((nax + 255) / 256, 4096)),
                        dim3(256), 0, h->stream, a, ax);
     HIPCHK(h, hipGetLastError());
-    // about 16 rows of one plane per workgroup (fewer on small grids)
+    // the z-blended table plane of a mesh plane in LDS when it fits (48
+    // KB); rows of one plane per workgroup: 64 with the staging (it is paid
+    // once per workgroup), 16 without, fewer on small grids
+    const size_t lds = (size_t)uy * (ux + 1) * sizeof(double);
+    const bool staged = lds <= 48 * 1024;
     const int nseg = (int)((d.nx + 255) / 256);
-    int rows = 16;
+    int rows = staged ? 64 : 16;
     while (rows > 1 && (long)nseg * ((d.ny + rows - 1) / rows) * d.nz < 4096) rows /= 2;
     const long ngx = (long)nseg * ((d.ny + rows - 1) / rows);
     if (ngx >= (1L << 31)) return fail(h, TDSE_ERR_UNSUPPORTED, "grid too large for the interpolation launch");
     const dim3 grid((unsigned)ngx, (unsigned)d.nz);
-    if (d.precision == TDSE_F64)
+    if (staged) {
+        if (d.precision == TDSE_F64)
+            hipLaunchKernelGGL(interp_potential_lds_kernel<double>, grid, dim3(256), lds, h->stream, a, ax,
+                               nseg, rows, static_cast<double*>(h->V));
+        else
+            hipLaunchKernelGGL(interp_potential_lds_kernel<float>, grid, dim3(256), lds, h->stream, a, ax,
+                               nseg, rows, static_cast<float*>(h->V));
+    } else if (d.precision == TDSE_F64) {
         hipLaunchKernelGGL(interp_potential_kernel<double>, grid, dim3(256), 0, h->stream, a, ax, nseg,
                            rows, static_cast<double*>(h->V));
-    else
+    } else {
         hipLaunchKernelGGL(interp_potential_kernel<float>, grid, dim3(256), 0, h->stream, a, ax, nseg,
                            rows, static_cast<float*>(h->V));
+    }
     return hip_check(h, hipGetLastError(), "interpolation launch");
 }
 
@@ -2085,7 +2113,7 @@ static tdse_status step_plain(tdse_ctx* h, int64_t n) {
     const int64_t hrec = d.record_every;
     const FusedDims fd = fused_dims(h, h->fm, h->fzc);
     const bool use_fused = h->fused && h->R2 && fd.ok;
-    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t);
+    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t, h->t2ty);
     // the two-step sweep tiles x, so it also runs where the one-pass band
     // (whole x rows in LDS) does not fit; single steps are then half-steps
     const bool use_f2 = h->fused && h->R2 && h->two && f2.ok;
@@ -2193,7 +2221,7 @@ tdse_status tdse_step(tdse_handle h, int64_t n) {
     if (hrec > 0 && (h->step + n) / hrec + 1 > d.max_records)
         return fail(h, TDSE_ERR_CAPACITY, "record buffer would overflow");
     const FusedDims fd = fused_dims(h, h->fm, h->fzc);
-    const bool two = h->two && fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t).ok;
+    const bool two = h->two && fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t, h->t2ty).ok;
     const bool graph_ok = h->fused && h->R2 && fd.ok && h->graph_on && h->stream != nullptr &&
                           !h->timing && !h->adj_ws && !two && hrec > 0 && hrec % 2 == 0 &&
                           hrec <= 256;
@@ -2392,7 +2420,7 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out) {
     out->two_step_zc = h->t2zc;
     out->two_step_prefetch = h->t2pf ? 1 : 0;
     out->two_step_threads = h->t2t;
-    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t);
+    const Fused2Dims f2 = fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t, h->t2ty);
     out->two_step_ty = f2.ok ? f2.ty : 0;
     out->vec_elems = h->W;
     out->vec_groups = h->G;
@@ -2432,7 +2460,8 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
               (pt == 1024 && pm == 1)))
             return fail(h, TDSE_ERR_UNSUPPORTED,
                         "two-step (rows, threads) must be (2,256), (3,256), (1,512), (2,512) or (1,1024)");
-        if (!fused2_dims(h, t->two_step_tx, t->two_step_rows, t2zc, t->two_step_threads).ok)
+        if (t->two_step_ty < 0) return fail(h, TDSE_ERR_ARG, "two_step_ty must be >= 0");
+        if (!fused2_dims(h, t->two_step_tx, t->two_step_rows, t2zc, t->two_step_threads, t->two_step_ty).ok)
             return fail(h, TDSE_ERR_UNSUPPORTED, "two-step tile does not fit this grid");
     }
     graph_invalidate(h);
@@ -2451,6 +2480,7 @@ tdse_status tdse_set_tile(tdse_handle h, const tdse_tile* t) {
     h->t2zc = t2zc;
     h->t2pf = t->two_step_prefetch != 0;
     h->t2t = t->two_step_threads;
+    h->t2ty = t->two_step ? std::max(0, t->two_step_ty) : 0;
     return TDSE_OK;
 }
 
@@ -2587,7 +2617,7 @@ tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2) {
     h->R2 = psi_r2;
     h->I2 = psi_i2;
     h->fused = fused_dims(h, h->fm, h->fzc).ok ||
-               (h->two && fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t).ok);
+               (h->two && fused2_dims(h, h->t2x, h->t2m, h->t2zc, h->t2t, h->t2ty).ok);
     return TDSE_OK;
 }
 

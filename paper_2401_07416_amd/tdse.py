@@ -475,15 +475,21 @@ class Sim:
     def set_tile(self, rows=None, waves=None, zc=None, fused=None, fused_rows=None,
                  fused_zc=None, fused_prefetch=None, graph=None, fused_threads=None,
                  two_step=None, two_step_tx=None, two_step_rows=None, two_step_zc=None,
-                 two_step_prefetch=None, two_step_threads=None):
+                 two_step_prefetch=None, two_step_threads=None, two_step_ty=None):
+        """Replace some tile fields, keep the rest.  two_step_ty: the sweep's
+        interior tile height (0 = the tallest its threads cover); when the
+        sweep's shape changes and no height is given, the tallest."""
         t = self.get_tile()
+        shape = (two_step_tx, two_step_rows, two_step_threads)
+        if two_step_ty is None and any(v is not None for v in shape):
+            two_step_ty = 0
         for name, v in (("rows", rows), ("waves", waves), ("zc", zc), ("fused", fused),
                         ("fused_rows", fused_rows), ("fused_zc", fused_zc),
                         ("fused_prefetch", fused_prefetch), ("graph", graph),
                         ("fused_threads", fused_threads), ("two_step", two_step),
                         ("two_step_tx", two_step_tx), ("two_step_rows", two_step_rows),
                         ("two_step_zc", two_step_zc), ("two_step_prefetch", two_step_prefetch),
-                        ("two_step_threads", two_step_threads)):
+                        ("two_step_threads", two_step_threads), ("two_step_ty", two_step_ty)):
             if v is not None:
                 setattr(t, name, int(v))
         self._check(self.lib.tdse_set_tile(self.h, ctypes.byref(t)))

@@ -296,7 +296,8 @@ tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2);
  *
  * tdse_adjoint_workspace_size: bytes of the adjoint workspace for a forward
  * run of n_steps steps with checkpoints every ckpt_every steps: 2 ceil(N/K)
- * checkpoint arrays, 2 (K + 1) segment arrays and 4 work arrays, each
+ * checkpoint arrays, 4 (K + 1) segment arrays (two banks: one segment is
+ * recomputed while the next is swept) and 5 work arrays, each
  * [nz][ny][nx] in the state precision (host only).
  *
  * tdse_bind_adjoint: attach that caller-owned device workspace (256-byte
@@ -310,7 +311,9 @@ tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2);
  * from dL_drho (device, state precision, [n_rec][ny][nx], the derivative of
  * the loss with respect to each record, n_rec = n_steps/h + 1).  Each
  * segment between checkpoints is recomputed forward (bit-identical to the
- * forward run) and then swept backwards:
+ * forward run; on a second stream of the handle's device, created at the
+ * first call, overlapping the backward sweep of the segment after it) and
+ * then swept backwards:
  *   i_t = i + G (B r);  dL/dV += cv (B r) o psiI^{n+1/2} - cv (B i_t) o psiR^n;
  *   r <- A r - G (B i_t);  i <- A i_t;  then record injections of level n,
  * G X = -(cx dxx + cy dyy + cz dzz) X + cv V X, A = diag(ca_k),

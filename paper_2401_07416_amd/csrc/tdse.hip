@@ -59,6 +59,11 @@ struct tdse_ctx {
     // adjoint: checkpoints every adj_K steps of an adj_N-step forward run
     void* adj_ws = nullptr;
     int64_t adj_N = 0;
+    // a second stream (default priority) on which the adjoint recomputes
+    // the next segment while the handle's stream sweeps the current one
+    // backwards, and the events that order the two
+    hipStream_t adj_stream = nullptr;
+    hipEvent_t adj_ev[5] = {};
     int adj_K = 0;
     // bound memory
     void* R = nullptr;
@@ -756,7 +761,8 @@ AdjLayout adj_layout(const tdse_desc& d, int64_t N, int K) {
     L.nck = (size_t)((N + K - 1) / K);
     size_t o = 0;
     L.ckpt = o; o += 2 * L.nck * L.arr;
-    L.seg = o; o += 2 * ((size_t)K + 1) * L.arr;
+    // two banks of segment states: one recomputed while the other is swept
+    L.seg = o; o += 2 * 2 * ((size_t)K + 1) * L.arr;
     L.rb = o; o += L.arr;
     L.rc = o; o += L.arr;
     L.ia = o; o += L.arr;
@@ -910,7 +916,10 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
     const long n = (long)d.nx * d.ny * d.nz;
     const long nxy = (long)d.nx * d.ny;
     auto ck = [&](size_t c, int which) { return reinterpret_cast<T*>(w + L.ckpt + (2 * c + which) * L.arr); };
-    auto sg = [&](size_t m, int which) { return reinterpret_cast<T*>(w + L.seg + (2 * m + which) * L.arr); };
+    // state (which = 0: psiR, 1: psiI) of level s0 + m of the segment in bank b
+    auto sgb = [&](int b, size_t m, int which) {
+        return reinterpret_cast<T*>(w + L.seg + ((size_t)b * 2 * ((size_t)K + 1) + 2 * m + which) * L.arr);
+    };
     T* rb = reinterpret_cast<T*>(w + L.rb);
     T* rc = reinterpret_cast<T*>(w + L.rc);
     T* ia = reinterpret_cast<T*>(w + L.ia);
@@ -932,25 +941,61 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
     };
     // the one-pass reverse step where the one-pass forward step is on
     const FusedDims af = adj_fused_dims(h);
+    // Segments are swept last to first.  Segment c's states are recomputed
+    // from its checkpoint into bank c mod 2 on the second stream while the
+    // handle's stream sweeps segment c + 1 (bank (c + 1) mod 2) backwards:
+    // ev[b] (recompute into bank b done) gates the sweep, ev[2 + b] (sweep
+    // of bank b done) gates the next recompute into it, ev[4] hands the
+    // forward run's checkpoints to the second stream.  The kernels and their
+    // order per stream are those of one stream, so the bits are the same.
+    if (!h->adj_stream) {
+        HIPCHK(h, hipStreamCreateWithFlags(&h->adj_stream, hipStreamNonBlocking));
+        for (hipEvent_t& e : h->adj_ev) HIPCHK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    hipStream_t s1 = h->stream, s2 = h->adj_stream;
+    hipEvent_t* ev = h->adj_ev;
+    auto recompute = [&](int64_t c) -> tdse_status {
+        const int b = (int)(c & 1);
+        const int64_t s0 = c * K;
+        const int64_t s1_ = std::min<int64_t>(s0 + K, N);
+        HIPCHK(h, hipMemcpyAsync(sgb(b, 0, 0), ck(c, 0), bytes, hipMemcpyDeviceToDevice, s2));
+        HIPCHK(h, hipMemcpyAsync(sgb(b, 0, 1), ck(c, 1), bytes, hipMemcpyDeviceToDevice, s2));
+        h->stream = s2;
+        tdse_status st = TDSE_OK;
+        for (int64_t m = s0; m < s1_ && st == TDSE_OK; ++m)
+            st = forward_step_explicit(h, sgb(b, m - s0, 0), sgb(b, m - s0, 1), sgb(b, m - s0 + 1, 0),
+                                       sgb(b, m - s0 + 1, 1));
+        h->stream = s1;
+        if (st != TDSE_OK) return st;
+        HIPCHK(h, hipEventRecord(ev[b], s2));
+        return TDSE_OK;
+    };
+    HIPCHK(h, hipEventRecord(ev[4], s1));
+    HIPCHK(h, hipStreamWaitEvent(s2, ev[4], 0));
+    {
+        const tdse_status st = recompute((int64_t)L.nck - 1);
+        if (st != TDSE_OK) return st;
+    }
     bool first = true;
     for (int64_t c = (int64_t)L.nck - 1; c >= 0; --c) {
+        const int b = (int)(c & 1);
         const int64_t s0 = c * K;
-        const int64_t s1 = std::min<int64_t>(s0 + K, N);
-        HIPCHK(h, hipMemcpyAsync(sg(0, 0), ck(c, 0), bytes, hipMemcpyDeviceToDevice, h->stream));
-        HIPCHK(h, hipMemcpyAsync(sg(0, 1), ck(c, 1), bytes, hipMemcpyDeviceToDevice, h->stream));
-        for (int64_t m = s0; m < s1; ++m) {
-            tdse_status st = forward_step_explicit(h, sg(m - s0, 0), sg(m - s0, 1),
-                                                   sg(m - s0 + 1, 0), sg(m - s0 + 1, 1));
+        const int64_t s1_ = std::min<int64_t>(s0 + K, N);
+        if (c >= 1) {
+            // the previous segment into the other bank, once its last sweep is done
+            if (c + 1 < (int64_t)L.nck) HIPCHK(h, hipStreamWaitEvent(s2, ev[2 + (b ^ 1)], 0));
+            const tdse_status st = recompute(c - 1);
             if (st != TDSE_OK) return st;
         }
+        HIPCHK(h, hipStreamWaitEvent(s1, ev[b], 0));
         if (first) {
-            tdse_status st = inject(N, sg(s1 - s0, 0), sg(s1 - s0, 1));
+            tdse_status st = inject(N, sgb(b, s1_ - s0, 0), sgb(b, s1_ - s0, 1));
             if (st != TDSE_OK) return st;
             first = false;
         }
-        for (int64_t m = s1 - 1; m >= s0; --m) {
-            const T* Rn = sg(m - s0, 0);
-            const T* Ih = sg(m - s0 + 1, 1);
+        for (int64_t m = s1_ - 1; m >= s0; --m) {
+            const T* Rn = sgb(b, m - s0, 0);
+            const T* Ih = sgb(b, m - s0 + 1, 1);
             tdse_status st;
             if (af.ok) {
                 st = launch_adj_fused<T>(h, af, rb, ia, rc, ib, Rn, Ih, gv);
@@ -963,9 +1008,10 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
                 if (st != TDSE_OK) return st;
             }
             std::swap(ia, ib);
-            st = inject(m, sg(m - s0, 0), sg(m - s0, 1));
+            st = inject(m, sgb(b, m - s0, 0), sgb(b, m - s0, 1));
             if (st != TDSE_OK) return st;
         }
+        HIPCHK(h, hipEventRecord(ev[2 + b], s1));
         if (sizeof(T) != 8) {
             hipLaunchKernelGGL(adjoint_fold_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                                h->stream, gV64, gv, n);
@@ -1630,6 +1676,9 @@ tdse_status tdse_destroy(tdse_handle h) {
     if (!h) return TDSE_OK;
     graph_invalidate(h);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->adj_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->adj_stream) (void)hipStreamDestroy(h->adj_stream);
     delete h;
     return TDSE_OK;
 }

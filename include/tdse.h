@@ -426,8 +426,11 @@ tdse_status tdse_timing_read_split(tdse_handle h, double* ms, int64_t* count);
  * differences on the vector ALU.  FP32 frames: on the FP64 matrix cores as
  * |x_k|^2 + |x_j|^2 - 2 x_k . x_j with x = frame - (the frame of trajectory
  * 0 at the same time), exact in FP64 (the shift leaves every distance
- * unchanged and keeps the cancellation to a few FP64 ulps of |x|^2); a
- * negative rounding residue counts as zero.  The result is bitwise
+ * unchanged); the cancellation costs a few FP64 ulps of |x_k|^2 + |x_j|^2,
+ * so a frame's squared distance d^2 has a relative error of about
+ * 1e-16 (|x_k|^2 + |x_j|^2) / d^2 (pairs much closer to each other than to
+ * trajectory 0 lose accuracy: FP64 frames avoid it); a negative rounding
+ * residue counts as zero.  The result is bitwise
  * reproducible and exactly symmetric.  Asynchronous on stream (a
  * hipStream_t, may be null).  TDSE_ERR_ARG for null pointers, sizes < 1,
  * dA <= 0 or a short workspace; TDSE_ERR_DEVICE for launch errors. */

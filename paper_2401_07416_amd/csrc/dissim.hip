@@ -174,11 +174,14 @@ __global__ __launch_bounds__(256) void dissim_kernel(DissimArgs a) {
 // frame of a time t is shifted by the same image c_t, and with x_k = rho_k - c
 //   sum_p (rho_k - rho_j)^2 = |x_k|^2 + |x_j|^2 - 2 x_k . x_j,
 // a Gram contraction.  Formed in FP64 from FP32 frames: x = rho - c is exact
-// in FP64, and the shift c_t = the frame of trajectory 0 keeps |x|^2 of the
-// order of the distances themselves for trajectories that are close to one
-// another (the case a dissimilarity has to resolve), so the cancellation in
-// the expansion costs a few FP64 ulps of |x|^2, not the FP32 cross term's
-// 1e-7.  The Gram block of a workgroup (GB x GB pairs, sixteen wavefronts
+// in FP64 with the shift c_t = the frame of trajectory 0, and the
+// cancellation in the expansion costs a few FP64 ulps of |x_k|^2 + |x_j|^2:
+// a squared frame distance d^2 carries a relative error of about
+// eps64 (|x_k|^2 + |x_j|^2) / d^2, tiny while a pair's distance is not far
+// below the distances to trajectory 0 (1e-15 for random frames), larger for
+// a tight cluster far from trajectory 0 (pairs 1e-6 apart at unit distance
+// from it: about 1e-4 in d^2); the FP64-frame form below has no such
+// cancellation.  The Gram block of a workgroup (GB x GB pairs, sixteen wavefronts
 // of 32 x 32 pairs: four per SIMD) accumulates on v_mfma_f64_16x16x4_f64
 // over chunks of GPC pixels staged in LDS as FP64 rows; the squared norms
 // come from the same FP64 values as they are staged.

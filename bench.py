@@ -62,6 +62,8 @@ def parse():
     p.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     p.add_argument("--no-timing", action="store_true",
                    help="do not bracket launches with events (value only)")
+    p.add_argument("--only", default=None, choices=sorted(SECONDARIES),
+                   help="run only this one secondary measurement and print its JSON (for profiling)")
     p.add_argument("--copy-probe", action="store_true",
                    help="run only a plain device copy of 1 GiB five times (calibrates the "
                         "FETCH_SIZE / WRITE_SIZE counters against known bytes)")
@@ -587,6 +589,24 @@ def copy_probe():
                       "launches": 5}), flush=True)
 
 
+def _sec_fp64_c2():
+    from paper_2401_07416_amd import workloads
+    return secondary_fp64(workloads.c2_surface(), 400)
+
+
+def _sec_fp64_c3():
+    from paper_2401_07416_amd import workloads
+    return secondary_fp64(workloads.c3_headline(), 100)
+
+
+# the secondary measurements of the bench line, in the order they run
+SECONDARIES = {"fp64": _sec_fp64_c2, "fp64_headline_grid": _sec_fp64_c3,
+               "free_gaussian_64cubed": secondary_free_gaussian, "adjoint": secondary_adjoint,
+               "batched": secondary_batch, "interpolation": secondary_interp,
+               "dissimilarity": secondary_dissim, "paper_setup": secondary_paper,
+               "shard_share": secondary_shard}
+
+
 def main():
     a = parse()
     if a.cpu_child:
@@ -594,6 +614,9 @@ def main():
         return
     if a.copy_probe:
         copy_probe()
+        return
+    if a.only:
+        print(json.dumps({a.only: SECONDARIES[a.only]()}), flush=True)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "libtdse runs on one GPU; a sharded multi-GPU path is not "
@@ -614,6 +637,34 @@ def main():
         sim.set_tile(**tile)
     t = sim.get_tile()
     torch.cuda.synchronize()
+    # The practical ceiling: streaming kernels with the copy's and the
+    # step's mix of read and written streams, 1 GiB per stream.  Measured
+    # before the warm-up steps: its ~25 ms of streaming also carries the
+    # device through the clock transient that follows the compute-bound
+    # potential build (without it, the sweep's launches 2-15 after the build
+    # run up to 17% slower than the steady state).
+    practical = None
+    if not a.no_timing:
+        try:
+            copy_gbs = tdse.hbm_probe("copy", reps=16)
+            mix_gbs = tdse.hbm_probe("mix", reps=16)
+            practical = {"copy_gbs": round(copy_gbs, 1), "mix_gbs": round(mix_gbs, 1)}
+        except Exception as e:  # measurement context only
+            practical = {"error": str(e)}
+        torch.cuda.empty_cache()
+    # The records (eq. (15), every h steps) cost, on a window of whole record
+    # intervals.  Measured before the warm-up steps: the sweep's launches
+    # after the set-up run up to 10% slower than the steady state for about
+    # 20 ms (a device transient the probe above does not remove), which a
+    # short timed window would otherwise mostly consist of.
+    rec_cost = None
+    if not a.no_timing and rec_window:
+        try:
+            rec_cost = record_cost(sim, w)
+            if rec_cost is not None:
+                rec_cost["measured"] = "before the warm-up steps"
+        except Exception as e:  # measurement context only
+            rec_cost = {"error": repr(e)}
     sim.step(a.warmup)
     torch.cuda.synchronize()
     sim.timing_read_split()
@@ -654,36 +705,18 @@ def main():
         "hbm_bytes_per_cell_step_alg": bytes_per_cell_step,
         "hbm_gbs_whole_step": round(value * bytes_per_cell_step, 1),
     }
-    if roof is not None and rec_window:
-        # the records (eq. (15), every h steps) cost, measured on a window of
-        # whole record intervals after the timed region
-        try:
-            out["record_cost"] = record_cost(sim, w)
-        except Exception as e:  # measurement context only
-            out["record_cost"] = {"error": repr(e)}
+    if rec_cost is not None:
+        out["record_cost"] = rec_cost
     del sim
     torch.cuda.empty_cache()
-    if roof is not None:
-        # the practical ceiling: streaming kernels with the copy's and the
-        # one-pass step's mix of read and written streams, 1 GiB per stream
-        try:
-            copy_gbs = tdse.hbm_probe("copy")
-            mix_gbs = tdse.hbm_probe("mix")
-            roof["practical"] = {"copy_gbs": round(copy_gbs, 1), "mix_gbs": round(mix_gbs, 1),
-                                 "frac_of_mix": round(roof["achieved"] / mix_gbs, 4)}
-        except Exception as e:  # measurement context only
-            roof["practical"] = {"error": str(e)}
-        torch.cuda.empty_cache()
+    if roof is not None and practical is not None:
+        if "mix_gbs" in practical:
+            practical["frac_of_mix"] = round(roof["achieved"] / practical["mix_gbs"], 4)
+        roof["practical"] = practical
     fp64_c2 = None
     if not a.no_secondary:
         sec = {}
-        for name, fn in (("fp64", lambda: secondary_fp64(workloads.c2_surface(), 400)),
-                         ("fp64_headline_grid", lambda: secondary_fp64(workloads.c3_headline(), 100)),
-                         ("free_gaussian_64cubed", secondary_free_gaussian),
-                         ("adjoint", secondary_adjoint),
-                         ("batched", secondary_batch), ("interpolation", secondary_interp),
-                         ("dissimilarity", secondary_dissim), ("paper_setup", secondary_paper),
-                         ("shard_share", secondary_shard)):
+        for name, fn in SECONDARIES.items():
             try:
                 sec[name] = fn()
             except Exception as ex:  # reported, never hidden

@@ -254,10 +254,11 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
         va[i] = r0 + srow + GRP * i < a.K;
         vb[i] = c0 + srow + GRP * i < a.K;
     }
-    auto fetch = [&](long c) {
-        const int t = t0 + (int)(c / cpt);
-        const long p0 = (c % cpt) * GPC + 4 * quad;
-        const long off = (long)t * a.P;
+    // chunk pc of frame t0 + f of the workgroup's frames (positions are
+    // advanced incrementally: no 64-bit division in the loop)
+    auto fetch = [&](int f, long pc) {
+        const long p0 = pc * GPC + 4 * quad;
+        const long off = (long)(t0 + f) * a.P;
 #pragma unroll
         for (int i = 0; i < GNP; ++i) {
             ra[i] = va[i] ? load4<VEC>(a.frames + (long)(r0 + srow + GRP * i) * TP + off, p0, a.P)
@@ -332,17 +333,29 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
     // two LDS buffers: chunk c + 1 is staged into the other buffer while
     // chunk c is contracted (late in it: its loads, issued a chunk ahead,
     // have landed), one barrier per chunk
+    auto advance = [&](int& f, long& pc) {
+        if (++pc == cpt) {
+            pc = 0;
+            ++f;
+        }
+    };
+    int fc = 0, fn = 0;     // frame of the current chunk and of the next one to fetch
+    long pcc = 0, pn = 0;   // their chunks within the frame
     if (nch > 0) {
-        fetch(0);
+        fetch(fn, pn);
         stage_chunk(0);
-        if (nch > 1) fetch(1);
+        advance(fn, pn);
+        if (nch > 1) {
+            fetch(fn, pn);
+            advance(fn, pn);
+        }
     }
     __syncthreads();
     for (long c = 0; c < nch; ++c) {
         const int cur = (int)(c & 1);
         const double* Ac = As + cur * GB * GLS;
         const double* Bc = Bs + cur * GB * GLS;
-        const bool frame_done = c % cpt == cpt - 1;
+        const bool frame_done = pcc == cpt - 1;
 #pragma unroll
         for (int kk = 0; kk < GPC / 4; ++kk) {
             double av[2], bv[GWN];
@@ -357,16 +370,19 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
                     g[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[m], bv[n], g[m][n], 0, 0, 0);
             if (kk == GPC * 3 / 16) {
                 // the staged norms so far cover the frame's chunks up to c
-                if (frame_done) frame_norms((int)(c / cpt));
+                if (frame_done) frame_norms(fc);
                 if (c + 1 < nch) {
                     stage_chunk(cur ^ 1);
-                    if (c + 2 < nch) fetch(c + 2);
+                    if (c + 2 < nch) {
+                        fetch(fn, pn);
+                        advance(fn, pn);
+                    }
                 }
             }
         }
         __syncthreads();
         if (frame_done) {
-            const int f = (int)(c / cpt);
+            const int f = fc;
             const double wt = a.w[t0 + f];
             const double* nf = nrm + (f & 1) * 2 * GB;
             // element r of a lane's accumulator is pair (4 r + lk, li) of the 16 x 16 tile
@@ -386,7 +402,12 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
                             *o = f == 0 ? v : *o + v;
                         }
                     }
+            // nothing of the frame's epilogue stays in flight: the loop's
+            // wait bookkeeping then never holds the next chunk's LDS reads
+            // or the prefetch behind these accesses
+            __builtin_amdgcn_s_waitcnt(0);
         }
+        advance(fc, pcc);
     }
     // a diagonal block holds both (k, j) and (j, k): the pair with k < j
     // writes both, so the result is exactly symmetric; d_kk = 0

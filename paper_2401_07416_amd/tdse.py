@@ -322,9 +322,15 @@ class Sim:
         sp = (ctypes.c_double * 3)(*[float(x) for x in spacing])
         org = (ctypes.c_double * 3)(*[float(x) for x in origin])
         with torch.cuda.device(self.device):
+            cur = torch.cuda.current_stream(self.device)
+            if self.stream != cur:
+                self.stream.wait_stream(cur)   # the table as written on torch's stream
             self._check(self.lib.tdse_interpolate_potential(self.h, ctypes.c_void_p(t.data_ptr()),
                                                             ux, uy, uz, sp, org))
-            self.stream.synchronize()  # the table must outlive the launch
+            # the table's memory is not reused before the launch has read it
+            t.record_stream(self.stream)
+            if self.stream != cur:
+                cur.wait_stream(self.stream)   # torch work queued next sees V
 
     def set_cap(self, w: Optional[np.ndarray]):
         if w is None:

@@ -28,12 +28,36 @@ def interp_sim(nx, ny, nz, dx, dy, dz, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_interpolated_potential_matches_oracle(prec):
+@pytest.mark.parametrize("shape", [(37, 29, 53), (40, 29, 53), (1100, 5, 7)])
+def test_interpolated_potential_matches_oracle(prec, shape):
+    """Odd rows (one cell per thread), rows of whole 16-byte vectors, and
+    rows longer than one workgroup's segment with a partial last one."""
     table = workloads.unit_cell_table(uz=80, z_top=10.0)
     sp = (2.556 / 24, 4.427 / 28, 0.2)
     org = (0.031, -0.27, 0.15)
-    nx, ny, nz = 37, 29, 53
-    say("interpolation 37x29x53", prec)
+    nx, ny, nz = shape
+    say("interpolation", shape, prec)
+    s = interp_sim(nx, ny, nz, 0.21, 0.19, 0.23, prec)
+    s.interpolate_potential(table, sp, org)
+    g = oracle.Grid(nx, ny, nz, 0.21, 0.19, 0.23, hbar=1.0, mass=1.0)
+    ref = oracle.interp_potential(g, table, sp, org)
+    got = s.v.double().cpu().numpy()
+    scale = np.max(np.abs(ref))
+    tol = 1e-13 if prec == "f64" else 1e-7
+    err = float(np.max(np.abs(got - ref)) / scale)
+    say(" max err / max|V|", err)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_interpolated_potential_large_table_matches_oracle(prec):
+    """A cell table whose z-blended plane does not fit the LDS staging
+    (96 x 80 samples): the gather kernel with the separate weights launch."""
+    table = workloads.unit_cell_table(ux=96, uy=80, uz=40, z_top=6.0)
+    sp = (2.556 / 96, 4.427 / 80, 0.2)
+    org = (0.013, 0.4, -0.05)
+    nx, ny, nz = 45, 31, 23
+    say("interpolation, large table", prec)
     s = interp_sim(nx, ny, nz, 0.21, 0.19, 0.23, prec)
     s.interpolate_potential(table, sp, org)
     g = oracle.Grid(nx, ny, nz, 0.21, 0.19, 0.23, hbar=1.0, mass=1.0)

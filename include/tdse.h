@@ -150,8 +150,12 @@ const char* tdse_last_error(tdse_handle h);
 
 /* Host-only check of a description: sizes > 0, spacings, hbar, mass > 0,
  * boundary and precision codes, 0 <= k_det < nz, record settings, and
- * dt or dt_frac > 0.  Touches no device. */
-tdse_status tdse_validate_desc(const tdse_desc* d);
+ * dt or dt_frac > 0.  Touches no device.  dt_bound (may be NULL): hbar /
+ * E_kin with E_kin = (hbar^2/2m) sum_d 4/d^2, the time-step bound of
+ * section 2.1 for V = 0 (the potential enters E_max only once it is known:
+ * tdse_time_step_bound for a range of V, tdse_finalize_setup for the bound
+ * V); +inf when no axis couples cells. */
+tdse_status tdse_validate_desc(const tdse_desc* d, double* dt_bound);
 
 /* Host-only Gershgorin bound on max |E| of the discrete Hamiltonian of the
  * section 2.1 scheme for a potential with range [vmin, vmax]:
@@ -375,6 +379,14 @@ typedef struct tdse_batch_ctx* tdse_batch;
 
 tdse_status tdse_batch_create(const tdse_desc* descs, int32_t n, void* stream, tdse_batch* out);
 tdse_status tdse_batch_member(tdse_batch b, int32_t i, tdse_handle* h);
+/* tdse_batch_bind: tdse_bind and tdse_bind_pingpong of member i in one call
+ * (the same arguments, rules and errors; psi_r2, psi_i2 the member's second
+ * state pair, which a batch requires); drops a prepared graph.
+ * tdse_batch_detect: tdse_detect of member i. */
+tdse_status tdse_batch_bind(tdse_batch b, int32_t i, void* psi_r, void* psi_i, void* v, void* workspace,
+                            size_t workspace_bytes, void* records, double* scalars, double* pixel,
+                            void* psi_r2, void* psi_i2);
+tdse_status tdse_batch_detect(tdse_batch b, int32_t i, tdse_detect_out* out);
 tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc,
                                 int32_t prefetch, int32_t threads);
 /* Two-step sweeps for the whole batch (on by default, with tx 64, one row,

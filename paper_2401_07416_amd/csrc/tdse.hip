@@ -1594,7 +1594,11 @@ const char* tdse_status_string(tdse_status s) {
 
 const char* tdse_last_error(tdse_handle h) { return h ? h->err.c_str() : ""; }
 
-tdse_status tdse_validate_desc(const tdse_desc* d) {
+}  // extern "C"
+
+namespace {
+
+tdse_status check_desc(const tdse_desc* d) {
     if (!d) return TDSE_ERR_ARG;
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return TDSE_ERR_ARG;
     if (d->nx > (1 << 20) || d->ny > (1 << 20) || d->nz > (1 << 20)) return TDSE_ERR_ARG;
@@ -1616,11 +1620,9 @@ tdse_status tdse_validate_desc(const tdse_desc* d) {
     return supported_shape(*d);
 }
 
-tdse_status tdse_time_step_bound(const tdse_desc* d, double vmin, double vmax, double* e_max,
-                                 double* dt_bound) {
-    tdse_status s = tdse_validate_desc(d);
-    if (s != TDSE_OK) return s;
-    if (!std::isfinite(vmin) || !std::isfinite(vmax) || vmin > vmax) return TDSE_ERR_ARG;
+// The kinetic part of the Gershgorin bound: (hbar^2/2m) sum_d 4/d^2 over
+// the axes that couple cells (a periodic axis of length 1 adds nothing).
+double kinetic_bound(const tdse_desc* d) {
     const int64_t n[3] = {d->nx, d->ny, d->nz};
     const double sp[3] = {d->dx, d->dy, d->dz};
     double kin = 0.0;
@@ -1628,7 +1630,29 @@ tdse_status tdse_time_step_bound(const tdse_desc* d, double vmin, double vmax, d
         if (n[a] == 1 && d->bc[a] == TDSE_BC_PERIODIC) continue;
         kin += 4.0 / (sp[a] * sp[a]);
     }
-    kin *= d->hbar * d->hbar / (2.0 * d->mass);
+    return kin * d->hbar * d->hbar / (2.0 * d->mass);
+}
+
+}  // namespace
+
+extern "C" {
+
+tdse_status tdse_validate_desc(const tdse_desc* d, double* dt_bound) {
+    const tdse_status s = check_desc(d);
+    if (s != TDSE_OK) return s;
+    if (dt_bound) {
+        const double kin = kinetic_bound(d);
+        *dt_bound = kin > 0 ? d->hbar / kin : INFINITY;
+    }
+    return TDSE_OK;
+}
+
+tdse_status tdse_time_step_bound(const tdse_desc* d, double vmin, double vmax, double* e_max,
+                                 double* dt_bound) {
+    tdse_status s = check_desc(d);
+    if (s != TDSE_OK) return s;
+    if (!std::isfinite(vmin) || !std::isfinite(vmax) || vmin > vmax) return TDSE_ERR_ARG;
+    const double kin = kinetic_bound(d);
     const double em = std::max(std::fabs(vmin), std::fabs(vmax + kin));
     if (!(em > 0)) return TDSE_ERR_ARG;
     if (e_max) *e_max = em;
@@ -1637,7 +1661,7 @@ tdse_status tdse_time_step_bound(const tdse_desc* d, double vmin, double vmax, d
 }
 
 tdse_status tdse_workspace_size(const tdse_desc* d, size_t* bytes) {
-    tdse_status s = tdse_validate_desc(d);
+    tdse_status s = check_desc(d);
     if (s != TDSE_OK) return s;
     if (!bytes) return TDSE_ERR_ARG;
     *bytes = layout_of(*d).total;
@@ -1647,7 +1671,7 @@ tdse_status tdse_workspace_size(const tdse_desc* d, size_t* bytes) {
 tdse_status tdse_create(const tdse_desc* d, void* stream, tdse_handle* out) {
     if (!out) return TDSE_ERR_ARG;
     *out = nullptr;
-    tdse_status s = tdse_validate_desc(d);
+    tdse_status s = check_desc(d);
     if (s != TDSE_OK) return s;
     s = supported_shape(*d);
     if (s != TDSE_OK) return s;
@@ -1995,7 +2019,7 @@ tdse_status tdse_set_cap_paper(tdse_handle h, double alpha, double r_cut) {
 }
 
 tdse_status tdse_time_step_paper(const tdse_desc* d, double* dt) {
-    tdse_status s = tdse_validate_desc(d);
+    tdse_status s = check_desc(d);
     if (s != TDSE_OK) return s;
     if (!dt) return TDSE_ERR_ARG;
     const double dmin = std::min(d->dx, std::min(d->dy, d->dz));
@@ -2682,7 +2706,7 @@ tdse_status tdse_bind_pingpong(tdse_handle h, void* psi_r2, void* psi_i2) {
 
 tdse_status tdse_adjoint_workspace_size(const tdse_desc* d, int64_t n_steps, int32_t ckpt_every,
                                         size_t* bytes) {
-    tdse_status s = tdse_validate_desc(d);
+    tdse_status s = check_desc(d);
     if (s != TDSE_OK) return s;
     if (!bytes || n_steps < 1 || ckpt_every < 1) return TDSE_ERR_ARG;
     *bytes = adj_layout(*d, n_steps, ckpt_every).total;
@@ -2831,6 +2855,25 @@ tdse_status tdse_batch_member(tdse_batch b, int32_t i, tdse_handle* h) {
     if (!b || !h || i < 0 || i >= (int32_t)b->members.size()) return TDSE_ERR_ARG;
     *h = b->members[(size_t)i];
     return TDSE_OK;
+}
+
+tdse_status tdse_batch_bind(tdse_batch b, int32_t i, void* psi_r, void* psi_i, void* v, void* workspace,
+                            size_t workspace_bytes, void* records, double* scalars, double* pixel,
+                            void* psi_r2, void* psi_i2) {
+    if (!b || i < 0 || i >= (int32_t)b->members.size()) return TDSE_ERR_ARG;
+    tdse_handle h = b->members[(size_t)i];
+    // the captured graph holds the member's old pointers
+    batch_free_device(b);
+    tdse_status s = tdse_bind(h, psi_r, psi_i, v, workspace, workspace_bytes, records, scalars, pixel);
+    if (s != TDSE_OK) return bfail(b, s, h->err);
+    s = tdse_bind_pingpong(h, psi_r2, psi_i2);
+    if (s != TDSE_OK) return bfail(b, s, h->err);
+    return TDSE_OK;
+}
+
+tdse_status tdse_batch_detect(tdse_batch b, int32_t i, tdse_detect_out* out) {
+    if (!b || i < 0 || i >= (int32_t)b->members.size()) return TDSE_ERR_ARG;
+    return tdse_detect(b->members[(size_t)i], out);
 }
 
 tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc, int32_t prefetch,

@@ -39,7 +39,7 @@ EXPORTS = [
     "tdse_dissimilarity_workspace_size", "tdse_dissimilarity", "tdse_set_cap_paper",
     "tdse_time_step_paper", "tdse_batch_set_two_step", "tdse_autotune", "tdse_paper_layout_run",
     "tdse_dissimilarity_noalloc", "tdse_timing_read_split", "tdse_batch_workspace_size",
-    "tdse_batch_bind_workspace",
+    "tdse_batch_bind_workspace", "tdse_batch_bind", "tdse_batch_detect",
 ]
 
 
@@ -119,7 +119,7 @@ def load():
         "tdse_abi_version": (i32, []),
         "tdse_status_string": (ctypes.c_char_p, [i32]),
         "tdse_last_error": (ctypes.c_char_p, [vp]),
-        "tdse_validate_desc": (i32, [ctypes.POINTER(Desc)]),
+        "tdse_validate_desc": (i32, [ctypes.POINTER(Desc), dp]),
         "tdse_time_step_bound": (i32, [ctypes.POINTER(Desc), dbl, dbl, dp, dp]),
         "tdse_workspace_size": (i32, [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)]),
         "tdse_create": (i32, [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]),
@@ -147,6 +147,8 @@ def load():
                                      dp, dp]),
         "tdse_batch_create": (i32, [ctypes.POINTER(Desc), i32, vp, ctypes.POINTER(vp)]),
         "tdse_batch_member": (i32, [vp, i32, ctypes.POINTER(vp)]),
+        "tdse_batch_bind": (i32, [vp, i32, vp, vp, vp, vp, ctypes.c_size_t, vp, vp, vp, vp, vp]),
+        "tdse_batch_detect": (i32, [vp, i32, ctypes.POINTER(DetectOut)]),
         "tdse_batch_set_tile": (i32, [vp, i32, i32, i32, i32]),
         "tdse_batch_set_two_step": (i32, [vp, i32, i32, i32, i32, i32, i32]),
         "tdse_batch_workspace_size": (i32, [vp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -193,7 +195,14 @@ def make_desc(nx, ny, nz, dx, dy, dz, hbar=1.0, mass=1.0, dt=0.0, dt_frac=0.9,
 
 
 def validate_desc(d: Desc) -> int:
-    return int(load().tdse_validate_desc(ctypes.byref(d)))
+    return int(load().tdse_validate_desc(ctypes.byref(d), None))
+
+
+def validate_desc_bound(d: Desc):
+    """(status, dt bound for V = 0) of tdse_validate_desc."""
+    b = ctypes.c_double()
+    st = int(load().tdse_validate_desc(ctypes.byref(d), ctypes.byref(b)))
+    return st, b.value
 
 
 def time_step_bound(d: Desc, vmin: float, vmax: float):

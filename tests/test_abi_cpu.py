@@ -91,6 +91,23 @@ def test_time_step_bound_matches_oracle_gershgorin():
         tdse.time_step_bound(base_desc(), 1.0, -1.0)
 
 
+def test_validate_desc_bound_is_the_free_particle_bound():
+    """tdse_validate_desc's dt bound is hbar / E_max of the oracle's
+    Gershgorin bound for V = 0 (a periodic axis of one cell adds nothing;
+    no coupled axis: no bound)."""
+    for shape, sp, bc in [((4, 5, 6), (0.3, 0.25, 0.2), (0, 0, 0)),
+                          ((1, 7, 3), (0.3, 0.21, 0.2), (1, 1, 0))]:
+        g = oracle.Grid(*shape, *sp, hbar=0.658, mass=0.0568, bc=bc)
+        d = tdse.make_desc(*shape, *sp, hbar=0.658, mass=0.0568, bc=bc)
+        st, dtb = tdse.validate_desc_bound(d)
+        assert st == tdse.OK
+        assert dtb == pytest.approx(0.658 / oracle.emax(g, np.zeros(shape[::-1])), rel=1e-14)
+    st, dtb = tdse.validate_desc_bound(tdse.make_desc(1, 1, 1, 0.2, 0.2, 0.2, hbar=0.658, mass=0.0568))
+    assert st == tdse.OK and dtb == float("inf")
+    st, _ = tdse.validate_desc_bound(base_desc(nx=0))
+    assert st == tdse.ERR_ARG
+
+
 def test_workspace_size_scales_and_is_aligned():
     a = tdse.workspace_size(base_desc())
     b = tdse.workspace_size(base_desc(nz=400))

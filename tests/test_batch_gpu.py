@@ -66,6 +66,51 @@ def test_batch_equals_single_runs(prec, form):
         assert m.detect().flux == pytest.approx(single.detect().flux, rel=1e-11, abs=1e-15)
 
 
+def test_batch_bind_and_detect_calls():
+    """tdse_batch_bind (members bound through the batch, here to the arrays
+    the member handles were bound to, before their set-up) and
+    tdse_batch_detect give exactly what the member handles' own calls give."""
+    import ctypes
+    steps = 40
+    ws = small_set(steps)[:3]
+    say("batch bind / detect", [w.name for w in ws])
+    ref = tdse.batch_from_workloads(ws, precision="f32", steps=steps)
+    ref.prepare()
+    ref.run(steps)
+    descs = [tdse.make_desc(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.hbar, w.mass, dt_frac=w.dt_frac,
+                            bc=w.bc, precision="f32", k_det=w.k_det, record_every=w.record_every,
+                            max_records=w.n_records(steps)) for w in ws]
+    b = tdse.Batch(descs)
+    lib = b.lib
+    for i, (w, s) in enumerate(zip(ws, b.members)):
+        st = lib.tdse_batch_bind(b.b, i, s.psi_r.data_ptr(), s.psi_i.data_ptr(), s.v.data_ptr(),
+                                 s.workspace.data_ptr(), s.workspace.numel(), s.records.data_ptr(),
+                                 s.scalars.data_ptr(), None, s.psi_r2.data_ptr(), s.psi_i2.data_ptr())
+        assert st == tdse.OK
+        with torch.cuda.stream(b.stream):
+            s.build_potential(w.atoms, soft=w.soft, cutoff=w.cutoff, kappa=w.kappa, a0=w.a0,
+                              screened=w.screened)
+            s.set_cap_quadratic(*w.cap)
+            s.finalize()
+            s.init_gaussian(w.r0, w.k0 if w.k0 is not None else
+                            tuple(tdse.wavevector(w.energy, w.hbar, w.mass) * c for c in w.k_dir), w.sigma)
+    torch.cuda.synchronize()
+    b.prepare()
+    b.run(steps)
+    assert all(st == tdse.OK for st in b.status())
+    for i, (m, r) in enumerate(zip(b.members, ref.members)):
+        assert bool((m.psi_r == r.psi_r).all()) and bool((m.psi_i == r.psi_i).all())
+        o = tdse.DetectOut()
+        assert lib.tdse_batch_detect(b.b, i, ctypes.byref(o)) == tdse.OK
+        d = r.detect()
+        assert (o.step, o.n_records) == (d.step, d.n_records)
+        assert o.flux_acc == d.flux and o.dt == d.dt
+    o = tdse.DetectOut()
+    assert lib.tdse_batch_detect(b.b, len(ws), ctypes.byref(o)) == tdse.ERR_ARG
+    assert lib.tdse_batch_bind(b.b, -1, None, None, None, None, 0, None, None, None, None,
+                               None) == tdse.ERR_ARG
+
+
 @pytest.mark.parametrize("form", ["two-step", "one-pass"])
 def test_preparing_a_batch_keeps_members_tiles(form):
     """A batch's tile is the batch's: after prepare() each member still

@@ -99,7 +99,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     if (gx < 0 || gx >= nx) colg = a.bcx ? -1 : ((gx % nx) + nx) % nx;
     const bool xin = c0 >= 4 && c0 < 4 + a.tx && gx < nx;
 
-    int rowb[M], voff[M], soff[M];
+    int rowb[M], voff[M], soff[M], voff_iv[M];
     bool zc_cell[M];   // cell outside a zero-boundary axis (or idle thread): forced to 0
 #pragma unroll
     for (int i = 0; i < M; ++i) {
@@ -112,6 +112,9 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
         voff[i] = ok ? (rj * nx + colg) * (int)sizeof(T) : OOB;
         const bool st = live && xin && rowb[i] >= 4 && rowb[i] < 4 + a.ty && gy < ny;
         soff[i] = st ? voff[i] : OOB;
+        // I^{n-1/2} and V of the outermost extended rows feed only the
+        // first phase's results there, which are discarded: not read
+        voff_iv[i] = (rowb[i] >= 1 && rowb[i] < ey - 1) ? voff[i] : OOB;
     }
     auto gplane = [&](int p) -> int {
         if (p < 0) {
@@ -280,8 +283,8 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             r[i] = bload<T, W>(rR, voff[i]);
-            iv[i] = bload<T, W>(rI, voff[i]);
-            vv[i] = bload<T, W>(rV, voff[i]);
+            iv[i] = bload<T, W>(rI, voff_iv[i]);
+            vv[i] = bload<T, W>(rV, voff_iv[i]);
         }
     };
 

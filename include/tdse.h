@@ -438,14 +438,17 @@ tdse_status tdse_timing_read_split(tdse_handle h, double* ms, int64_t* count);
  * differences on the vector ALU.  FP32 frames: on the FP64 matrix cores as
  * |x_k|^2 + |x_j|^2 - 2 x_k . x_j with x = frame - (the frame of trajectory
  * 0 at the same time), exact in FP64 (the shift leaves every distance
- * unchanged); the cancellation costs a few FP64 ulps of |x_k|^2 + |x_j|^2,
- * so a frame's squared distance d^2 has a relative error of about
- * 1e-16 (|x_k|^2 + |x_j|^2) / d^2 (pairs much closer to each other than to
- * trajectory 0 lose accuracy: FP64 frames avoid it); a negative rounding
- * residue counts as zero.  The result is bitwise
- * reproducible and exactly symmetric.  Asynchronous on stream (a
- * hipStream_t, may be null).  TDSE_ERR_ARG for null pointers, sizes < 1,
- * dA <= 0 or a short workspace; TDSE_ERR_DEVICE for launch errors. */
+ * unchanged).  The expansion's rounding error in a frame's d^2 is below
+ * about 0.4 P eps64 (|x_k|^2 + |x_j|^2); a pair with a frame whose d^2 is
+ * below P 2^-30 (|x_k|^2 + |x_j|^2) (pairs much closer to each other than
+ * to trajectory 0) is evaluated again in the direct form, from the
+ * differences, for all its frames; so every d^2 the result uses is good to
+ * about 5e-8 of itself, and identical trajectories are at distance 0.  The
+ * result is bitwise reproducible and exactly symmetric.  Workspace: the
+ * partial sums, and for FP32 frames the list of such pairs (room for all K
+ * (K - 1) / 2).  Asynchronous on stream (a hipStream_t, may be null).
+ * TDSE_ERR_ARG for null pointers, sizes < 1, dA <= 0 or a short workspace;
+ * TDSE_ERR_DEVICE for launch errors. */
 tdse_status tdse_dissimilarity_workspace_size(int32_t K, int32_t T, size_t* bytes);
 tdse_status tdse_dissimilarity(int32_t precision, const void* frames, int32_t K, int32_t T, int64_t P,
                                const double* weights, double dA, double* out, void* workspace,
@@ -466,10 +469,11 @@ tdse_status tdse_dissimilarity(int32_t precision, const void* frames, int32_t K,
  * every entry it reads, so nothing needs clearing): calls whose executions
  * can overlap on one GPU (unordered streams, host threads) race and give
  * wrong results; calls on one stream are ordered.  TDSE_ERR_CAPACITY when
- * the partial sums of the precision's kernel exceed the maximum, checked
- * before anything is launched: ceil(T / frames per chunk) x K x K doubles,
- * at most tdse_dissimilarity_workspace_size(K, T) (FP32 frames of K = 879
- * trajectories x T = 77 frames need 53 MiB and fit; FP64 frames of that
+ * the precision's workspace would exceed the maximum, checked before
+ * anything is launched: ceil(T / frames per chunk) x K x K doubles of
+ * partial sums, and for FP32 frames the pair list, at most
+ * tdse_dissimilarity_workspace_size(K, T) (FP32 frames of K = 879
+ * trajectories x T = 77 frames need 56 MiB and fit; FP64 frames of that
  * size need 118 MiB and do not).  Other errors as tdse_dissimilarity;
  * TDSE_ERR_UNSUPPORTED on a device index >= 64. */
 #define TDSE_DISSIM_NOALLOC_MAX_BYTES (64u << 20)

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <mutex>
 
@@ -206,7 +207,9 @@ struct GramArgs {
     int K, T;
     long P;
     int nb, npb, tpc;
+    double tau;           // a frame's d^2 below tau (|x_k|^2 + |x_j|^2) marks the pair
     double* part;         // [ntc][K][K]
+    unsigned* count;      // length of the list of marked pairs (zeroed here)
 };
 
 // four consecutive pixels p0 .. p0 + 3 of a row (zero past P)
@@ -244,6 +247,8 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
     const long TP = (long)a.T * a.P;
     const long cpt = (a.P + GPC - 1) / GPC;
     const long nch = cpt * (t1 - t0);
+    // the reduction that follows on the stream appends the marked pairs
+    if (blockIdx.x == 0 && tid == 0) *a.count = 0u;
 
     // staging: rows srow + GRP i of each side, pixels 4 quad .. 4 quad + 3
     const int quad = tid % GQ, srow = tid / GQ;
@@ -393,13 +398,20 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = wr + 16 * m + 4 * r + lk, col = wc + 16 * n + li;
-                        const double d2 = (nf[row] + nf[GB + col]) - 2.0 * g[m][n][r];
+                        const double ns = nf[row] + nf[GB + col];
+                        const double d2 = ns - 2.0 * g[m][n][r];
                         const double v = wt * sqrt(a.dA * fmax(d2, 0.0));
                         g[m][n][r] = 0.0;
                         const int k = r0 + row, j = c0 + col;
                         if (k < a.K && j < a.K && k <= j) {
+                            // a d^2 this small against the norms may be
+                            // mostly the expansion's rounding: the partial
+                            // turns negative (no contribution is) and stays
+                            // so, and the pair goes to the direct form
                             double* o = out + (long)k * a.K + j;
-                            *o = f == 0 ? v : *o + v;
+                            const double prev = f == 0 ? 0.0 : *o;
+                            const bool mark = k < j && d2 < a.tau * ns;
+                            *o = (mark || prev < 0.0) ? -1.0 : prev + v;
                         }
                     }
             // nothing of the frame's epilogue stays in flight: the loop's
@@ -427,12 +439,64 @@ __global__ __launch_bounds__(GTHREADS) void dissim_gram_kernel(GramArgs a) {
             }
 }
 
-__global__ __launch_bounds__(256) void dissim_reduce_kernel(const double* part, int ntc, long kk,
-                                                            double* out) {
+// Adds the partial time sums in a fixed order.  A pair with a negative
+// partial (marked by the Gram kernel) is appended to list (k < j, once per
+// pair; the order of the list does not matter, each entry is evaluated on
+// its own) and its entries are left for dissim_pairs_kernel.
+__global__ __launch_bounds__(256) void dissim_reduce_kernel(const double* part, int ntc, int K,
+                                                            double* out, int2* list, unsigned* count) {
+    const long kk = (long)K * K;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < kk; i += (long)gridDim.x * 256) {
         double s = 0.0;
-        for (int c = 0; c < ntc; ++c) s += part[(long)c * kk + i];
-        out[i] = s;
+        bool marked = false;
+        for (int c = 0; c < ntc; ++c) {
+            const double v = part[(long)c * kk + i];
+            marked |= v < 0.0;
+            s += v;
+        }
+        out[i] = marked ? 0.0 : s;
+        if (marked && list) {
+            const int k = (int)(i / K), j = (int)(i - (long)k * K);
+            if (k < j) list[atomicAdd(count, 1u)] = make_int2(k, j);
+        }
+    }
+}
+
+// The marked pairs in the direct form of eq. (16): per frame the sum over
+// pixels of (rho_k - rho_j)^2, the differences of the FP32 values exact in
+// FP64, fused multiply-adds.  A workgroup per pair of the list (a strided
+// loop over the list), pixels strided over its threads, then a butterfly in
+// each wavefront and the four wavefronts in order: the same bits on every
+// run.  Writes d_kj and d_jk.
+__global__ __launch_bounds__(256) void dissim_pairs_kernel(const float* frames, const double* w, double dA,
+                                                           int K, int T, long P, const int2* list,
+                                                           const unsigned* count, double* out) {
+    __shared__ double red[4];
+    const unsigned n = *count;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long TP = (long)T * P;
+    for (unsigned it = blockIdx.x; it < n; it += gridDim.x) {
+        const int2 kj = list[it];
+        const float* fa = frames + (long)kj.x * TP;
+        const float* fb = frames + (long)kj.y * TP;
+        double acc = 0.0;
+        for (int t = 0; t < T; ++t) {
+            double s = 0.0;
+            for (long p = threadIdx.x; p < P; p += 256) {
+                const double e = (double)fa[(long)t * P + p] - (double)fb[(long)t * P + p];
+                s = __builtin_fma(e, e, s);
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+            if (lane == 0) red[wv] = s;
+            __syncthreads();
+            if (threadIdx.x == 0) acc += w[t] * sqrt(dA * (((red[0] + red[1]) + red[2]) + red[3]));
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            out[(long)kj.x * K + kj.y] = acc;
+            out[(long)kj.y * K + kj.x] = acc;
+        }
     }
 }
 
@@ -475,26 +539,43 @@ Plan plan_of(int K, int T) {
     return p;
 }
 
+// Workspace of a call: the partial sums (ntc x K x K doubles), and for FP32
+// frames behind them the count and list of the pairs marked for the direct
+// form (room for every pair k < j).
+constexpr size_t kListHead = 256;
+size_t part_bytes(const Plan& p, int K) { return (size_t)p.ntc * K * K * sizeof(double); }
+size_t list_bytes(int K) { return kListHead + (size_t)K * (K - 1) / 2 * sizeof(int2); }
+size_t need_bytes(int32_t precision, int K, int T) {
+    return precision == TDSE_F32 ? part_bytes(plan_gram(K, T), K) + list_bytes(K)
+                                 : part_bytes(plan_of(K, T), K);
+}
+
 }  // namespace
 
 extern "C" tdse_status tdse_dissimilarity_workspace_size(int32_t K, int32_t T, size_t* bytes) {
     if (!bytes || K < 1 || T < 1) return TDSE_ERR_ARG;
-    // the larger of the two kernels' partial sums (FP64 and FP32 frames)
-    const int ntc = std::max(plan_of(K, T).ntc, plan_gram(K, T).ntc);
-    *bytes = (size_t)ntc * K * K * sizeof(double);
+    // the larger of the two precisions' needs
+    *bytes = std::max(need_bytes(TDSE_F32, K, T), need_bytes(TDSE_F64, K, T));
     return TDSE_OK;
 }
 
 namespace {
 
-// The launches of tdse_dissimilarity with the partial sums at `part`
-// (ntc x K x K doubles of the plan; every entry the reduction reads is
-// written first, so stale contents do no harm).
+// The launches of tdse_dissimilarity with its workspace at `ws` (laid out
+// as need_bytes says; every entry a kernel reads is written first by an
+// earlier one on the stream, so stale contents do no harm).
 tdse_status dissim_launch(int32_t precision, const void* frames, int32_t K, int32_t T, int64_t P,
-                          const double* weights, double dA, double* out, double* part,
-                          hipStream_t st) {
+                          const double* weights, double dA, double* out, void* ws, hipStream_t st) {
     const Plan p = precision == TDSE_F32 ? plan_gram(K, T) : plan_of(K, T);
     const dim3 grid((unsigned)(p.npb * p.ntc));
+    double* part = static_cast<double*>(ws);
+    unsigned* count = nullptr;
+    int2* list = nullptr;
+    if (precision == TDSE_F32) {
+        char* tail = static_cast<char*>(ws) + part_bytes(p, K);
+        count = reinterpret_cast<unsigned*>(tail);
+        list = reinterpret_cast<int2*>(tail + kListHead);
+    }
     if (precision == TDSE_F32) {
         GramArgs g;
         g.frames = static_cast<const float*>(frames);
@@ -506,7 +587,13 @@ tdse_status dissim_launch(int32_t precision, const void* frames, int32_t K, int3
         g.nb = p.nb;
         g.npb = p.npb;
         g.tpc = p.tpc;
+        // The expansion's rounding error in a frame's d^2 is below about
+        // 0.4 P eps64 (|x_k|^2 + |x_j|^2) (sequential sums of P / 8 pixels
+        // per lane for the norms, P / 4 matrix steps for the cross term), so
+        // an unmarked d^2 is good to 0.4 eps64 / 2^-30 = 5e-8 of itself.
+        g.tau = std::ldexp((double)P, -30);
         g.part = part;
+        g.count = count;
         const bool vec = P % 4 == 0 && (reinterpret_cast<uintptr_t>(frames) & 15) == 0;
         if (vec)
             hipLaunchKernelGGL(dissim_gram_kernel<true>, grid, dim3(GTHREADS), 0, st, g);
@@ -530,7 +617,15 @@ tdse_status dissim_launch(int32_t precision, const void* frames, int32_t K, int3
     const long kk = (long)K * K;
     const unsigned g = (unsigned)std::min<long>((kk + 255) / 256, 4096);
     hipLaunchKernelGGL(dissim_reduce_kernel, dim3(g), dim3(256), 0, st,
-                       static_cast<const double*>(part), p.ntc, kk, out);
+                       static_cast<const double*>(part), p.ntc, (int)K, out, list, count);
+    if (hipGetLastError() != hipSuccess) return TDSE_ERR_DEVICE;
+    if (precision == TDSE_F32 && K > 1) {
+        // usually an empty list: every workgroup reads the count and ends
+        const unsigned gp = (unsigned)std::min<long>((long)K * (K - 1) / 2, 1024);
+        hipLaunchKernelGGL(dissim_pairs_kernel, dim3(gp), dim3(256), 0, st,
+                           static_cast<const float*>(frames), weights, dA, (int)K, (int)T, (long)P,
+                           static_cast<const int2*>(list), static_cast<const unsigned*>(count), out);
+    }
     return hipGetLastError() == hipSuccess ? TDSE_OK : TDSE_ERR_DEVICE;
 }
 
@@ -542,7 +637,7 @@ tdse_status dissim_check(int32_t precision, const void* frames, int32_t K, int32
     if (!(dA > 0)) return TDSE_ERR_ARG;
     const Plan p = precision == TDSE_F32 ? plan_gram(K, T) : plan_of(K, T);
     if ((long)p.npb * p.ntc > (1L << 31) - 1) return TDSE_ERR_ARG;
-    *need = (size_t)p.ntc * K * K * sizeof(double);
+    *need = need_bytes(precision, K, T);
     return TDSE_OK;
 }
 
@@ -582,7 +677,7 @@ extern "C" tdse_status tdse_dissimilarity(int32_t precision, const void* frames,
     const tdse_status st = dissim_check(precision, frames, K, T, P, weights, dA, out, &need);
     if (st != TDSE_OK) return st;
     if (!workspace || workspace_bytes < need) return TDSE_ERR_ARG;
-    return dissim_launch(precision, frames, K, T, P, weights, dA, out, static_cast<double*>(workspace),
+    return dissim_launch(precision, frames, K, T, P, weights, dA, out, workspace,
                          static_cast<hipStream_t>(stream));
 }
 

@@ -151,6 +151,57 @@ def test_dissimilarity_keeps_close_pairs_accurate():
     assert err <= 1e-5
 
 
+def test_dissimilarity_of_a_tight_cluster_far_from_trajectory_0():
+    """Trajectories 1e-6 apart at unit distance from trajectory 0 (the shift
+    of the FP32 Gram form): the expansion alone would leave about 1e-4 of
+    relative error in their d^2, so these pairs are evaluated in the direct
+    form, and keep the oracle's accuracy; pairs with trajectory 0 stay on the
+    matrix cores."""
+    K, T, P = 12, 3, 128 * 128
+    rng = np.random.default_rng(24)
+    far = rng.uniform(0.0, 2.0, (1, T, P))
+    centre = rng.uniform(0.0, 2.0, (1, T, P))
+    f = np.concatenate([far, centre + 1e-6 * rng.standard_normal((K - 1, T, P))])
+    f = f.astype(np.float32).astype(np.float64)
+    w = np.full(T, 1.0 / T)
+    ref = oracle.dissimilarity(f, w, 1.0)
+    d = tdse.dissimilarity(torch.from_numpy(f).to("cuda", torch.float32), torch.from_numpy(w),
+                           1.0).cpu().numpy()
+    off = ~np.eye(K, dtype=bool)
+    err = float(np.max(np.abs(d[off] - ref[off]) / ref[off]))
+    say("tight cluster far from trajectory 0: max rel", err, "d within", float(ref[1, 2]),
+        "d to 0", float(ref[0, 1]))
+    assert ref[1, 2] < 1e-4 * ref[0, 1]
+    np.testing.assert_array_equal(d, d.T)
+    assert err <= 1e-6
+
+
+def test_dissimilarity_direct_pairs_across_blocks_are_reproducible():
+    """A cluster of 40 trajectories far from trajectory 0 straddling the
+    edge of two 128-trajectory blocks (its pairs in diagonal and
+    off-diagonal blocks go to the direct form), among random ones: every
+    entry against the oracle, and two calls bitwise equal (the list of such
+    pairs is built in whatever order the reduction appends them)."""
+    K, T, P = 300, 4, 2048
+    rng = np.random.default_rng(25)
+    f = rng.uniform(0.0, 2.0, (K, T, P))
+    centre = rng.uniform(0.0, 2.0, (1, T, P)) + 3.0
+    f[100:140] = centre + 1e-6 * rng.standard_normal((40, T, P))
+    f = f.astype(np.float32).astype(np.float64)
+    w = rng.uniform(0.05, 0.2, T)
+    ref = oracle.dissimilarity(f, w, 0.5)
+    ft = torch.from_numpy(f).to("cuda", torch.float32)
+    wt = torch.from_numpy(w)
+    d1 = tdse.dissimilarity(ft, wt, 0.5).cpu().numpy()
+    d2 = tdse.dissimilarity(ft, wt, 0.5).cpu().numpy()
+    np.testing.assert_array_equal(d1, d2)
+    np.testing.assert_array_equal(d1, d1.T)
+    assert np.all(np.diag(d1) == 0.0)
+    off = ~np.eye(K, dtype=bool)
+    say("cluster across blocks max rel", float(np.max(np.abs(d1[off] - ref[off]) / ref[off])))
+    np.testing.assert_allclose(d1, ref, rtol=1e-6, atol=0)
+
+
 @pytest.mark.parametrize("K,T,P", [(300, 5, 999), (260, 4, 1024), (129, 2, 33), (1, 3, 7), (2, 1, 1)])
 def test_dissimilarity_blocks_and_tails(K, T, P):
     """FP32 frames over several 128-trajectory blocks (off-diagonal and
@@ -194,9 +245,10 @@ def test_dissimilarity_full_size_sampled():
 
 
 def test_dissimilarity_of_repeated_and_shifted_trajectories():
-    """A trajectory repeated under another index is at distance ~0 (to
-    FP64 rounding of the norms, far below the FP32 resolution of the
-    frames), and a common offset of every frame leaves d unchanged."""
+    """A trajectory repeated under another index is at distance exactly 0
+    (its pairs' d^2 are rounding residues of the expansion, so the pair is
+    evaluated from the differences), and a common offset of every frame
+    leaves d unchanged."""
     K, T, P = 40, 3, 4096
     rng = np.random.default_rng(23)
     # values on a 2^-20 grid, so that adding 4 below is exact in FP32
@@ -206,7 +258,7 @@ def test_dissimilarity_of_repeated_and_shifted_trajectories():
     d = tdse.dissimilarity(torch.from_numpy(f).cuda(), torch.from_numpy(w), 1.0).cpu().numpy()
     typical = float(np.median(d[~np.eye(K, dtype=bool)]))
     say("repeated pair", d[5, 17], "typical", typical)
-    assert d[5, 17] <= 1e-6 * typical
+    assert d[5, 17] == 0.0 and d[17, 5] == 0.0 and typical > 0.0
     # the offset is exact in FP32, so the differences are unchanged bit for bit
     g = (f.astype(np.float64) + 4.0).astype(np.float32)
     assert np.array_equal(g.astype(np.float64) - 4.0, f.astype(np.float64))

@@ -40,6 +40,29 @@ def test_noalloc_matches_workspace_entry_point_twice(dtype):
         assert torch.all(got.diagonal() == 0)
 
 
+def test_noalloc_with_pairs_in_the_direct_form_twice():
+    """FP32 frames with a tight cluster far from trajectory 0, whose pairs go
+    through the list of pairs evaluated in the direct form (kept in the same
+    scratch), then a smaller input with fewer such pairs: bitwise the
+    workspace entry point's result both times."""
+    for K, T, P, n, seed in [(260, 6, 1500, 50, 14), (90, 3, 700, 8, 15)]:
+        print(f"no-alloc dissimilarity cluster K={K} T={T} P={P} n={n} seed={seed}", flush=True)
+        fr = frames_of(K, T, P, torch.float64, seed)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed + 100)
+        base = fr[K // 2:K // 2 + 1] + 2.0
+        fr[K // 2 - n // 2:K // 2 - n // 2 + n] = base + 1e-6 * torch.randn(
+            (n, T, P), generator=g, device="cuda", dtype=torch.float64)
+        fr = fr.to(torch.float32).contiguous()
+        w = weights_of(T)
+        ref = tdse.dissimilarity(fr, w, 0.04)
+        got = tdse.dissimilarity_noalloc(fr, w, 0.04)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), (got - ref).abs().max().item()
+        i = K // 2 - n // 2
+        assert 0 < ref[i, i + 1].item() < 1e-4 * ref[0, i].item()
+
+
 def test_noalloc_rejects_partials_beyond_its_scratch():
     lib = tdse.load()
     nb = ctypes.c_size_t()
@@ -53,7 +76,8 @@ def test_noalloc_rejects_partials_beyond_its_scratch():
 
 def test_noalloc_fits_the_paper_sample():
     """FP32 records of 879 trajectories x 77 frames (the paper's sample of
-    section 3.2; 53 MiB of partial sums) fit the fixed scratch; a short
+    section 3.2; 53 MiB of partial sums and 3 MiB of pair list) fit the fixed
+    scratch; a short
     pixel row keeps the run cheap, the plan depends on K and T only."""
     K, T, P = 879, 77, 64
     print(f"no-alloc dissimilarity float32 K={K} T={T} P={P}", flush=True)

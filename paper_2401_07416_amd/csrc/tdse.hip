@@ -2589,7 +2589,9 @@ tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile
     tdse_get_tile(h, &base);
     std::vector<tdse_tile> cands;
     if (want2p) {
-        const int c[4][3] = {{2, 4, 64}, {4, 4, 64}, {2, 4, 16}, {1, 4, 32}};
+        // (one plane per workgroup: small, cache-resident grids, where the
+        // z march's load latency and not the bytes set the time)
+        const int c[5][3] = {{2, 4, 64}, {4, 4, 64}, {2, 4, 16}, {1, 4, 32}, {1, 4, 1}};
         for (const auto& x : c) {
             tdse_tile t = base;
             t.fused = 0;
@@ -2601,7 +2603,8 @@ tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile
         }
     }
     if (want1p && h->R2) {
-        const int c[5][3] = {{3, 64, 256}, {2, 32, 256}, {4, 64, 256}, {2, 8, 128}, {3, 16, 256}};
+        const int c[6][3] = {{3, 64, 256}, {2, 32, 256}, {4, 64, 256}, {2, 8, 128}, {3, 16, 256},
+                             {2, 1, 128}};
         for (const auto& x : c) {
             tdse_tile t = base;
             t.fused = 1;

@@ -37,12 +37,12 @@ def candidates(nz: int):
     keyword dicts."""
     for rows in (1, 2, 4):
         for waves in (1, 2, 4):
-            for zc in (8, 16, 32, 64, 128, 256):
+            for zc in (1, 2, 4, 8, 16, 32, 64, 128, 256):
                 if zc <= nz:
                     yield dict(fused=0, two_step=0, rows=rows, waves=waves, zc=zc)
     for ft in (256, 128, 64):
         for fr in (2, 3, 4):
-            for zc in (4, 8, 16, 32, 64, 128):
+            for zc in (1, 2, 4, 8, 16, 32, 64, 128):
                 if zc <= nz:
                     yield dict(fused=1, two_step=0, fused_rows=fr, fused_zc=zc, fused_prefetch=0,
                                fused_threads=ft)

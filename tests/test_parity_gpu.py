@@ -91,6 +91,8 @@ def test_degenerate_extents(shape, kdet, pp):
 
 
 TILES = [dict(fused=0, two_step=0, rows=1, waves=1, zc=4),
+         dict(fused=0, two_step=0, rows=1, waves=4, zc=1),
+         dict(fused=1, two_step=0, fused_rows=2, fused_zc=1, fused_threads=128, fused_prefetch=1),
          dict(fused=0, two_step=0, rows=2, waves=4, zc=16),
          dict(fused=0, two_step=0, rows=4, waves=2, zc=7),
          dict(fused=0, two_step=0, rows=8, waves=1, zc=128),

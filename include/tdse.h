@@ -389,11 +389,13 @@ tdse_status tdse_batch_bind(tdse_batch b, int32_t i, void* psi_r, void* psi_i, v
 tdse_status tdse_batch_detect(tdse_batch b, int32_t i, tdse_detect_out* out);
 tdse_status tdse_batch_set_tile(tdse_batch b, int32_t fused_rows, int32_t fused_zc,
                                 int32_t prefetch, int32_t threads);
-/* Two-step sweeps for the whole batch (on by default, with tx 64, one row,
- * z chunk 48, prefetch, 1024 threads): when every member
- * fits the sweep's tile (interior width tx, rows per thread, z chunk zc,
- * prefetch and threads per workgroup as for tdse_tile) and the members
- * share the vector width,
+/* Two-step sweeps for the whole batch (on by default, with tx 80, one row,
+ * z chunk 32, prefetch, 1024 threads): when every member
+ * fits the sweep's tile (interior width at most tx, rows per thread, z
+ * chunk zc, prefetch and threads per workgroup as for tdse_tile) and the
+ * members share the vector width; each member takes the interior width
+ * (tx or a multiple of 8 below it) and height that cover its plane with the
+ * fewest tiles, then with the fewest cells swept,
  * tdse_batch_prepare captures intervals of S/2 two-step launches instead of
  * S one-pass launches; otherwise it falls back to the one-pass form.  When
  * S/2 is odd a second graph covers intervals that start from the second

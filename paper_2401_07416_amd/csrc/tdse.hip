@@ -119,7 +119,7 @@ struct tdse_batch_ctx {
     bool pf = false;
     // two-step sweep for the whole batch (when every member fits it)
     bool two = true;
-    int t2x = 64, t2zc = 48, t2m = 1, t2t = 1024;
+    int t2x = 80, t2zc = 32, t2m = 1, t2t = 1024;
     bool t2pf = true;
     bool use2 = false;  // chosen at prepare
     int par = 0;        // state pair holding the members' current level
@@ -1287,6 +1287,34 @@ static hipError_t batch_enqueue_interval2(tdse_batch_ctx* b, int par0) {
 
 // Tables and graphs of the two-step form; false (nothing allocated) if a
 // member does not fit the sweep's tile.
+// A member's tile in the batch sweep: the batch's rows per thread, threads
+// per workgroup and z chunk, vector width W, and an interior width of at
+// most txmax (txmax, then multiples of 8 below it) with the height that
+// covers the plane with the fewest rows of tiles; the tile with the fewest
+// tiles per plane wins (a workgroup takes about the same time whatever its
+// tile), then the one that sweeps the fewest cells (rim included), then the
+// wider.  Grids of uneven sizes then each get a tiling without a mostly
+// empty last row or column of tiles.
+Fused2Dims batch_member_tile(const tdse_ctx* h, int txmax, int m, int zc, int nt, int W) {
+    Fused2Dims best{};
+    best.ok = false;
+    long bt = 0, bc = 0;
+    for (int tx = txmax; tx >= 8; tx = (tx == txmax ? txmax - 1 : tx - 1) / 8 * 8) {
+        const Fused2Dims tall = fused2_dims(h, tx, m, zc, nt, 0);
+        if (!tall.ok || tall.W != W) continue;
+        const long nty = (h->d.ny + tall.ty - 1) / tall.ty;
+        const Fused2Dims f = fused2_dims(h, tx, m, zc, nt, (int)((h->d.ny + nty - 1) / nty));
+        if (!f.ok || f.W != W) continue;
+        const long cells = (long)f.ntx * f.ex * f.nty * f.ey;
+        if (!best.ok || f.ntiles < bt || (f.ntiles == bt && cells < bc)) {
+            best = f;
+            bt = f.ntiles;
+            bc = cells;
+        }
+    }
+    return best;
+}
+
 template <typename T>
 static tdse_status batch_prepare2_t(tdse_batch_ctx* b, bool* used) {
     *used = false;
@@ -1299,10 +1327,10 @@ static tdse_status batch_prepare2_t(tdse_batch_ctx* b, bool* used) {
     for (size_t i = 0; i < n; ++i) {
         tdse_ctx* h = b->members[i];
         const int zc = (int)std::min<int64_t>(b->t2zc, h->d.nz);
-        const Fused2Dims f = fused2_dims(h, b->t2x, b->t2m, zc, b->t2t, 0);
+        // the vector width of the batch's nominal tile on its first member
+        if (W == 0) W = fused2_dims(h, b->t2x, b->t2m, zc, b->t2t, 0).W;
+        const Fused2Dims f = batch_member_tile(h, b->t2x, b->t2m, zc, b->t2t, W);
         if (!f.ok) return TDSE_OK;
-        if (W == 0) W = f.W;
-        if (f.W != W) return TDSE_OK;
         // the member's own tile is kept for its single-grid steps
         const int sx = h->t2x, sm = h->t2m, sz = h->t2zc, st = h->t2t;
         const bool spf = h->t2pf;

@@ -687,7 +687,7 @@ class Batch:
         self._check(self.lib.tdse_batch_set_tile(self.b, int(fused_rows), int(fused_zc),
                                                  int(bool(prefetch)), int(threads)))
 
-    def set_two_step(self, enable=True, tx=64, zc=48, prefetch=True, rows=1, threads=1024):
+    def set_two_step(self, enable=True, tx=80, zc=32, prefetch=True, rows=1, threads=1024):
         """Two-step sweeps for the whole batch where every member fits them."""
         self._check(self.lib.tdse_batch_set_two_step(self.b, int(bool(enable)), int(tx), int(rows),
                                                      int(zc), int(bool(prefetch)), int(threads)))

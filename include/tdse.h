@@ -486,7 +486,8 @@ tdse_status tdse_dissimilarity_noalloc(int32_t precision, const void* frames, in
 /* HBM probe: the practical bandwidth ceiling of this device, measured by
  * streaming kernels that do no part of the method.  kind 0: a copy, bufs[0]
  * -> bufs[1]; kind 1: the one-pass step's mix, three read streams bufs[0..2]
- * and two written streams bufs[3..4] (d = a + b c, e = b - a c, elementwise).
+ * and two written streams bufs[3..4] (d = a + b c, e = b - a c, elementwise);
+ * kind 2: a write-only stream, bufs[0] filled with 1.0f.
  * Each buffer is n floats (n a multiple of 4) of device memory, 16-byte
  * aligned, all distinct, owned by the caller; the written buffers are
  * overwritten.  All accesses carry the non-temporal hint.  grid = workgroups

@@ -1,6 +1,7 @@
 // HBM probe: streaming kernels that give the practical bandwidth ceiling the
-// step kernels are judged against (a plain copy, and the one-pass step's mix
-// of three read and two written streams).  They do no part of the method.
+// step kernels are judged against (a plain copy, the one-pass step's mix of
+// three read and two written streams, and a write-only stream).  They do no
+// part of the method.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -34,13 +35,21 @@ __global__ __launch_bounds__(256) void hbm_mix_kernel(const f4* __restrict__ a, 
     }
 }
 
+// a write-only stream (the ceiling of a kernel that only writes, such as
+// the potential interpolation)
+__global__ __launch_bounds__(256) void hbm_fill_kernel(f4* __restrict__ b, float v, long n4) {
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        __builtin_nontemporal_store(f4{v, v, v, v}, b + i);
+}
+
 }  // namespace
 
 extern "C" tdse_status tdse_hbm_probe(int32_t kind, void* const* bufs, int64_t n, int32_t grid,
                                       int32_t reps, void* stream, double* ms_per_pass) {
     if (!bufs || !ms_per_pass || n <= 0 || n % 4 != 0 || reps < 1 || grid < 0) return TDSE_ERR_ARG;
-    if (kind != 0 && kind != 1) return TDSE_ERR_ARG;
-    const int nb = kind == 0 ? 2 : 5;
+    if (kind != 0 && kind != 1 && kind != 2) return TDSE_ERR_ARG;
+    const int nb = kind == 0 ? 2 : kind == 1 ? 5 : 1;
     for (int i = 0; i < nb; ++i) {
         if (!bufs[i] || reinterpret_cast<uintptr_t>(bufs[i]) % 16 != 0) return TDSE_ERR_ARG;
         for (int j = 0; j < i; ++j)
@@ -54,6 +63,9 @@ extern "C" tdse_status tdse_hbm_probe(int32_t kind, void* const* bufs, int64_t n
         if (kind == 0)
             hipLaunchKernelGGL(hbm_copy_kernel, dim3((unsigned)g), dim3(256), 0, st,
                                static_cast<const f4*>(bufs[0]), static_cast<f4*>(bufs[1]), n4);
+        else if (kind == 2)
+            hipLaunchKernelGGL(hbm_fill_kernel, dim3((unsigned)g), dim3(256), 0, st,
+                               static_cast<f4*>(bufs[0]), 1.0f, n4);
         else
             hipLaunchKernelGGL(hbm_mix_kernel, dim3((unsigned)g), dim3(256), 0, st,
                                static_cast<const f4*>(bufs[0]), static_cast<const f4*>(bufs[1]),

@@ -512,14 +512,15 @@ class Sim:
 
 def hbm_probe(kind: str = "copy", gib: float = 1.0, grid: int = 0, reps: int = 5, device=None):
     """Practical HBM bandwidth of the device in GB/s: 'copy' (one read and
-    one written stream) or 'mix' (the one-pass step's three read and two
-    written streams), over buffers of `gib` GiB each."""
+    one written stream), 'mix' (the one-pass step's three read and two
+    written streams) or 'fill' (one written stream), over buffers of `gib`
+    GiB each."""
     import torch
     lib = load()
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     n = int(gib * (1 << 30)) // 16 * 4
-    k = {"copy": 0, "mix": 1}[kind]
-    bufs = [torch.ones(n, dtype=torch.float32, device=dev) for _ in range(2 if k == 0 else 5)]
+    k = {"copy": 0, "mix": 1, "fill": 2}[kind]
+    bufs = [torch.ones(n, dtype=torch.float32, device=dev) for _ in range((2, 5, 1)[k])]
     ptrs = (ctypes.c_void_p * len(bufs))(*[b.data_ptr() for b in bufs])
     ms = ctypes.c_double()
     stream = torch.cuda.current_stream(dev).cuda_stream

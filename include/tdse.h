@@ -550,7 +550,9 @@ tdse_status tdse_get_tile(tdse_handle h, tdse_tile* out);
 /* Tile autotuner: times a built-in list of candidate tiles on the handle's
  * own grid and state (flags: bit 0 two-pass, bit 1 one-pass, bit 2 two-step
  * sweep; none of the three = all; the one-pass and two-step candidates need
- * tdse_bind_pingpong), each for 2 warm-up and `steps` timed steps with HIP
+ * tdse_bind_pingpong; the two-step list includes, for a few tile widths,
+ * the tile height and z chunk whose workgroups fill one round of the
+ * compute units most fully), each for 2 warm-up and `steps` timed steps with HIP
  * events on the handle's stream, without records; keeps the fastest, sets
  * it and returns it in *out.  The state is spent: afterwards the handle
  * needs tdse_init_gaussian or tdse_set_state before tdse_step

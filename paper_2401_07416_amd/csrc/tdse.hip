@@ -2659,6 +2659,44 @@ tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile
             t.two_step_prefetch = 1;
             cands.push_back(t);
         }
+        // one-round tiles: 1024 threads, a width from the list, and the
+        // height and z chunk whose workgroups fill one round of the CUs
+        // (one workgroup per CU) most fully, at least 90%, then the
+        // shortest (the same tiles with no ragged last row): all
+        // workgroups march the same planes together and the
+        // L2 serves the rims the neighbouring tiles re-read (the fastest
+        // form measured on the benchmark grids)
+        const bool f64 = h->d.precision == TDSE_F64;
+        const int w1[3] = {128, 80, 64}, w2[2] = {64, 32};
+        for (int iw = 0; iw < (f64 ? 2 : 3); ++iw) {
+            const int tx = f64 ? w2[iw] : w1[iw];
+            const Fused2Dims tall = fused2_dims(h, tx, 1, (int)h->d.nz, 1024, 0);
+            if (!tall.ok) continue;
+            int bty = 0, bzc = 0, bwg = 0;
+            for (int ty = tall.ty; ty >= 4; --ty) {
+                for (int nzc = 1; nzc <= 8; ++nzc) {
+                    const int zc = (int)((h->d.nz + nzc - 1) / nzc);
+                    const Fused2Dims f = fused2_dims(h, tx, 1, zc, 1024, ty);
+                    if (!f.ok || f.ty != ty || f.nwg > h->cus || 10L * f.nwg < 9L * h->cus) continue;
+                    if (f.nwg >= bwg) {
+                        bwg = f.nwg;
+                        bty = ty;
+                        bzc = zc;
+                    }
+                }
+            }
+            if (bwg == 0) continue;
+            tdse_tile t = base;
+            t.fused = 1;
+            t.two_step = 1;
+            t.two_step_tx = tx;
+            t.two_step_rows = 1;
+            t.two_step_threads = 1024;
+            t.two_step_zc = bzc;
+            t.two_step_ty = bty;
+            t.two_step_prefetch = 1;
+            cands.push_back(t);
+        }
         // and the cost model's choice for this grid (its z chunk fills the
         // last wave of workgroups)
         const bool two0 = h->two;

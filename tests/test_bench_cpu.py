@@ -13,9 +13,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
-HEADLINE_TILE = {"fused": 1, "two_step": 1, "two_step_tx": 64, "two_step_rows": 1,
-                 "two_step_zc": 128, "two_step_prefetch": 1, "two_step_threads": 1024,
-                 "two_step_ty": 43}
+HEADLINE_TILE = {"fused": 1, "two_step": 1, "two_step_tx": 128, "two_step_rows": 1,
+                 "two_step_zc": 512, "two_step_prefetch": 1, "two_step_threads": 1024,
+                 "two_step_ty": 16}
 
 
 def test_words_per_launch_and_per_cell_step_agree():
@@ -51,7 +51,8 @@ def test_traffic_only_for_the_kernel_and_tile_the_counters_were_taken_with():
     path = os.path.join(ROOT, "profiles", "two_step_surface-512x512x1024_f32_traffic.json")
     with open(path) as f:
         t = json.load(f)
-    got = bench.traffic_from_profiles("surface-512x512x1024", "f32", "two_step", HEADLINE_TILE)
+    tile = t["tile"]   # the tile the counters were taken with
+    got = bench.traffic_from_profiles("surface-512x512x1024", "f32", "two_step", tile)
     if t["kernel_src_sha"] == bench.kernel_src_sha():
         assert got == pytest.approx(t["hbm_bytes_per_launch"])
         # the summary's own arithmetic: scaled counters over the algorithmic bytes
@@ -61,9 +62,9 @@ def test_traffic_only_for_the_kernel_and_tile_the_counters_were_taken_with():
         assert (fb + wb) / t["alg_bytes_per_launch"] == pytest.approx(t["traffic_over_alg"])
     else:
         assert got is None
-    other = dict(HEADLINE_TILE, two_step_zc=64)
+    other = dict(tile, two_step_zc=tile["two_step_zc"] + 8)
     assert bench.traffic_from_profiles("surface-512x512x1024", "f32", "two_step", other) is None
-    assert bench.traffic_from_profiles("surface-512x512x1024", "f32", "fused", HEADLINE_TILE) is None
+    assert bench.traffic_from_profiles("surface-512x512x1024", "f32", "fused", tile) is None
 
 
 def test_more_than_one_gpu_is_refused():

@@ -109,6 +109,8 @@ TILES = [dict(fused=0, two_step=0, rows=1, waves=1, zc=4),
          dict(fused=1, two_step=1, two_step_tx=24, two_step_rows=1, two_step_zc=16,
               two_step_prefetch=1, two_step_threads=1024),
          dict(fused=1, two_step=1, two_step_tx=64, two_step_rows=1, two_step_zc=1024,
+              two_step_prefetch=1, two_step_threads=1024, two_step_ty=16),
+         dict(fused=1, two_step=1, two_step_tx=128, two_step_rows=1, two_step_zc=512,
               two_step_prefetch=1, two_step_threads=1024, two_step_ty=16)]
 
 

@@ -1097,12 +1097,67 @@ double fused2_cost(const tdse_ctx* h, const Fused2Dims& f, int m, int zc) {
     return (double)waves * k * (zc + 6) * (double)f.ex * f.ey;
 }
 
-// The default two-step tile: the lowest modelled time over the built
-// (rows, threads) pairs, a few tile widths and z chunks of 32 .. 256 planes
-// (shorter chunks spend too much on the six-plane start), where the tile
-// fits and its workgroups fill at least three quarters of the CUs' slots.
+// A one-round two-step tile: 1024 threads, one row each, the widest width
+// of the list that divides nx, a height of at least 16 rows and z chunks of
+// at least 32 planes (up to 16 of them) whose workgroups fill 90-100% of one
+// round of the CUs; the fullest round, then the fewest cells swept (rims and
+// chunk starts included).  All workgroups then march the same planes at
+// about the same time and the L2 serves the rims that neighbouring tiles
+// re-read; wide tiles read long contiguous rows.  On the grids measured
+// (512x512x1024 FP32 and FP64, 256x256x512, the 512x512x128 z-slab, the
+// 240x240x520 grid) it is the fastest tile or within 1-2% of it; below
+// 2^24 cells (128x128x256: no faster than the one-pass step) it is not
+// used.  False where no such tile exists (small grids, widths that do not
+// divide nx).
+bool one_round_two_step(tdse_ctx* h) {
+    const tdse_desc& d = h->d;
+    if (d.nx * d.ny * d.nz < (int64_t)1 << 24) return false;
+    const bool f64 = d.precision == TDSE_F64;
+    const int w32[3] = {128, 80, 64}, w64[2] = {64, 32};
+    for (int iw = 0; iw < (f64 ? 2 : 3); ++iw) {
+        const int tx = f64 ? w64[iw] : w32[iw];
+        if (d.nx % tx != 0) continue;
+        const Fused2Dims tall = fused2_dims(h, tx, 1, (int)std::min<int64_t>(d.nz, 32), 1024, 0);
+        if (!tall.ok) continue;
+        long bwg = 0;
+        double bsw = 0.0;
+        int bty = 0, bzc = 0;
+        for (int ty = tall.ty; ty >= 16; --ty) {
+            for (int nzc = 1; nzc <= 16; ++nzc) {
+                const int zc = (int)((d.nz + nzc - 1) / nzc);
+                if (zc < 32 && nzc > 1) break;
+                const Fused2Dims f = fused2_dims(h, tx, 1, zc, 1024, ty);
+                if (!f.ok || f.ty != ty || f.nwg > h->cus || 10L * f.nwg < 9L * h->cus) continue;
+                const double swept = (double)f.ntx * f.ex * f.nty * f.ey * f.nzc * (zc + 6);
+                if (f.nwg > bwg || (f.nwg == bwg && swept < bsw)) {
+                    bwg = f.nwg;
+                    bsw = swept;
+                    bty = ty;
+                    bzc = zc;
+                }
+            }
+        }
+        if (bwg == 0) continue;
+        h->two = true;
+        h->t2x = tx;
+        h->t2m = 1;
+        h->t2t = 1024;
+        h->t2pf = true;
+        h->t2zc = bzc;
+        h->t2ty = bty;
+        return true;
+    }
+    return false;
+}
+
+// The default two-step tile: a one-round tile where the grid has one, else
+// the lowest modelled time over the built (rows, threads) pairs, a few tile
+// widths and z chunks of 32 .. 256 planes (shorter chunks spend too much on
+// the six-plane start), where the tile fits and its workgroups fill at
+// least three quarters of the CUs' slots.
 void default_two_step(tdse_ctx* h) {
     const tdse_desc& d = h->d;
+    if (one_round_two_step(h)) return;
     const bool f64 = d.precision == TDSE_F64;
     struct Cand {
         int tx, m, nt;

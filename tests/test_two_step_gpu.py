@@ -213,3 +213,39 @@ def test_autotuner_cache_round_trip(tmp_path, monkeypatch):
     s4 = tdse.sim_from_workload(w.with_(nx=48), precision="f32", steps=100)
     s4.autotune(steps=4, flags=6)
     assert len(path.read_text().splitlines()) == 2
+
+
+@pytest.mark.parametrize("prec,shape,want", [
+    ("f32", (512, 512, 1024), (128, 16, 512)),
+    ("f64", (512, 512, 1024), (64, 16, 1024)),
+    ("f32", (512, 512, 128), (128, 16, 64)),
+    ("f32", (240, 240, 520), (80, 35, 44)),
+    ("f64", (256, 256, 512), (64, 16, 128)),
+])
+def test_default_tile_on_large_grids_fills_one_round(prec, shape, want):
+    """The library's default two-step tile on grids of 2^24 cells or more:
+    1024 threads, the widest width that divides nx, and the height and z
+    chunk whose workgroups fill one round of the CUs most fully (on the
+    MI355X's 256), the fewest cells swept among those."""
+    props = torch.cuda.get_device_properties(0)
+    if props.multi_processor_count != 256:
+        pytest.skip("the expected tiles are those of a 256-CU device")
+    d = tdse.make_desc(*shape, 0.2, 0.2, 0.2, precision=prec)
+    s = tdse.Sim(d)
+    t = s.get_tile()
+    say("default tile", prec, shape, t.as_dict())
+    assert t.two_step == 1 and t.two_step_threads == 1024 and t.two_step_rows == 1
+    assert (t.two_step_tx, t.two_step_ty, t.two_step_zc) == want
+    s.close()
+
+
+def test_default_tile_on_small_grids_keeps_the_cost_model():
+    """Below 2^24 cells the one-round rule is not used (a 128x128x256 grid
+    stays off the one-round sweep tiles)."""
+    d = tdse.make_desc(128, 128, 256, 0.2, 0.2, 0.2, precision="f64")
+    s = tdse.Sim(d)
+    t = s.get_tile()
+    say("default tile 128x128x256 f64", t.as_dict())
+    assert not (t.two_step == 1 and t.two_step_threads == 1024 and t.two_step_ty == 16
+                and t.two_step_zc == 32)
+    s.close()

@@ -164,12 +164,12 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     // vterm(V) in vtv;
     // IS_R selects eq. (8), else eq. (9).  The result goes to out and, from
     // live threads, to LDS buffer dst (if not null).  A plane outside a zero
-    // z boundary is zero.  The 1024-thread workgroups (one per CU, where
-    // the VALU work is least hidden) also take two uniform shortcuts: no
-    // zero-boundary select without zero x / y boundaries (idle threads'
-    // results are never stored or read), and no CAP factors on planes
-    // without absorption (ca = cb = 1); the bits are the same.
-    const bool sel_xy = NT != 1024 || a.bcx || a.bcy;
+    // z boundary is zero.  Workgroups of 512 and 1024 threads (one or two
+    // per CU, where the VALU work is least hidden) also take two uniform
+    // shortcuts: no zero-boundary select without zero x / y boundaries (idle
+    // threads' results are never stored or read), and no CAP factors on
+    // planes without absorption (ca = cb = 1); the bits are the same.
+    const bool sel_xy = NT < 512 || a.bcx || a.bcy;
     // Phase d (1..4) is exact on extended rows [d, ey - d); with one row per
     // thread, a wavefront none of whose rows lie there skips it (its rows
     // are all discarded rim, and no needed cell of the next phase reads
@@ -236,7 +236,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
         };
         using Yes = std::true_type;
         using No = std::false_type;
-        const bool unit = NT == 1024 && cap == T(1) && cbp == T(1);
+        const bool unit = NT >= 512 && cap == T(1) && cbp == T(1);
         if (sel_xy) {
             if (unit) cells(Yes{}, Yes{});
             else cells(Yes{}, No{});
@@ -248,11 +248,11 @@ __device__ __forceinline__ void fused2_body(const Fused2Args<T>& a, int L, unsig
     using IsR = std::integral_constant<bool, true>;
     using IsI = std::integral_constant<bool, false>;
 
-    // The straight-line iteration (one row per thread, 1024 threads): the
-    // cells of one phase with unit CAP factors from the LDS buffer src,
-    // and the write slot of each buffer (wslot + buffer index x wstep; idle
-    // threads: the slot past the eight buffers, wstep 0).
-    constexpr bool FAST = M == 1 && NT == 1024;
+    // The straight-line iteration (one row per thread, 512 or 1024
+    // threads): the cells of one phase with unit CAP factors from the LDS
+    // buffer src, and the write slot of each buffer (wslot + buffer index x
+    // wstep; idle threads: the slot past the eight buffers, wstep 0).
+    constexpr bool FAST = M == 1 && NT >= 512;
     const bool fast_grid = !sel_xy;
     const bool need4 = M != 1 || wave_needed(4);
     const bool wave_live = wlo < a.rpp;   // some thread of the wavefront owns a row

@@ -1097,15 +1097,19 @@ double fused2_cost(const tdse_ctx* h, const Fused2Dims& f, int m, int zc) {
     return (double)waves * k * (zc + 6) * (double)f.ex * f.ey;
 }
 
-// A one-round two-step tile: 1024 threads, one row each, the widest width
-// of the list that divides nx, a height of at least 16 rows and z chunks of
+// A one-round two-step tile: 1024 threads, one row each, the first width
+// of the list that divides nx (128, 80, 64, the widths measured best, then
+// the other multiples of 8 from 120 down to 72; FP64: 64, 32, then 56, 48,
+// 40), a height of at least 16 rows and z chunks of
 // at least 32 planes (up to 16 of them) whose workgroups fill 90-100% of one
 // round of the CUs; the fullest round, then the fewest cells swept (rims and
 // chunk starts included).  All workgroups then march the same planes at
 // about the same time and the L2 serves the rims that neighbouring tiles
 // re-read; wide tiles read long contiguous rows.  On the grids measured
 // (512x512x1024 FP32 and FP64, 256x256x512, the 512x512x128 z-slab, the
-// 240x240x520 grid) it is the fastest tile or within 1-2% of it; below
+// 240x240x520 grid) it is the fastest tile or within 1-2% of it, and on
+// 208x208x416 and 224x224x448 (104- and 112-wide tiles) 19% and 30% faster
+// than the cost model's tile; below
 // 2^24 cells (128x128x256: no faster than the one-pass step) it is not
 // used.  False where no such tile exists (small grids, widths that do not
 // divide nx).
@@ -1113,8 +1117,8 @@ bool one_round_two_step(tdse_ctx* h) {
     const tdse_desc& d = h->d;
     if (d.nx * d.ny * d.nz < (int64_t)1 << 24) return false;
     const bool f64 = d.precision == TDSE_F64;
-    const int w32[3] = {128, 80, 64}, w64[2] = {64, 32};
-    for (int iw = 0; iw < (f64 ? 2 : 3); ++iw) {
+    const int w32[9] = {128, 80, 64, 120, 112, 104, 96, 88, 72}, w64[5] = {64, 32, 56, 48, 40};
+    for (int iw = 0; iw < (f64 ? 5 : 9); ++iw) {
         const int tx = f64 ? w64[iw] : w32[iw];
         if (d.nx % tx != 0) continue;
         const Fused2Dims tall = fused2_dims(h, tx, 1, (int)std::min<int64_t>(d.nz, 32), 1024, 0);

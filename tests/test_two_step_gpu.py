@@ -221,10 +221,12 @@ def test_autotuner_cache_round_trip(tmp_path, monkeypatch):
     ("f32", (512, 512, 128), (128, 16, 64)),
     ("f32", (240, 240, 520), (80, 35, 44)),
     ("f64", (256, 256, 512), (64, 16, 128)),
+    ("f32", (208, 208, 416), (104, 19, 38)),
+    ("f32", (224, 224, 448), (112, 25, 32)),
 ])
 def test_default_tile_on_large_grids_fills_one_round(prec, shape, want):
     """The library's default two-step tile on grids of 2^24 cells or more:
-    1024 threads, the widest width that divides nx, and the height and z
+    1024 threads, the first width of its list that divides nx, and the height and z
     chunk whose workgroups fill one round of the CUs most fully (on the
     MI355X's 256), the fewest cells swept among those."""
     props = torch.cuda.get_device_properties(0)

@@ -1097,22 +1097,46 @@ double fused2_cost(const tdse_ctx* h, const Fused2Dims& f, int m, int zc) {
     return (double)waves * k * (zc + 6) * (double)f.ex * f.ey;
 }
 
-// A one-round two-step tile: 1024 threads, one row each, the first width
-// of the list that divides nx (128, 80, 64, the widths measured best, then
-// the other multiples of 8 from 120 down to 72; FP64: 64, 32, then 56, 48,
-// 40), a height of at least 16 rows and z chunks of
-// at least 32 planes (up to 16 of them) whose workgroups fill 90-100% of one
-// round of the CUs; the fullest round, then the fewest cells swept (rims and
-// chunk starts included).  All workgroups then march the same planes at
-// about the same time and the L2 serves the rims that neighbouring tiles
-// re-read; wide tiles read long contiguous rows.  On the grids measured
-// (512x512x1024 FP32 and FP64, 256x256x512, the 512x512x128 z-slab, the
-// 240x240x520 grid) it is the fastest tile or within 1-2% of it, and on
-// 208x208x416 and 224x224x448 (104- and 112-wide tiles) 19% and 30% faster
-// than the cost model's tile; below
-// 2^24 cells (128x128x256: no faster than the one-pass step) it is not
-// used.  False where no such tile exists (small grids, widths that do not
-// divide nx).
+// The one-round two-step tile of interior width tx: 1024 threads, one row
+// each, a height of at least 16 rows and z chunks of at least 32 planes (up
+// to 16 of them) whose workgroups fill 90-100% of one round of the CUs; the
+// fullest round, then the fewest cells swept (rims and chunk starts
+// included).  All workgroups then march the same planes at about the same
+// time and the L2 serves the rims that neighbouring tiles re-read; wide
+// tiles read long contiguous rows.  False if no such tile exists.
+bool one_round_tile(tdse_ctx* h, int tx, int* ty_out, int* zc_out) {
+    const tdse_desc& d = h->d;
+    const Fused2Dims tall = fused2_dims(h, tx, 1, (int)std::min<int64_t>(d.nz, 32), 1024, 0);
+    if (!tall.ok) return false;
+    long bwg = 0;
+    double bsw = 0.0;
+    for (int ty = tall.ty; ty >= 16; --ty) {
+        for (int nzc = 1; nzc <= 16; ++nzc) {
+            const int zc = (int)((d.nz + nzc - 1) / nzc);
+            if (zc < 32 && nzc > 1) break;
+            const Fused2Dims f = fused2_dims(h, tx, 1, zc, 1024, ty);
+            if (!f.ok || f.ty != ty || f.nwg > h->cus || 10L * f.nwg < 9L * h->cus) continue;
+            const double swept = (double)f.ntx * f.ex * f.nty * f.ey * f.nzc * (zc + 6);
+            if (f.nwg > bwg || (f.nwg == bwg && swept < bsw)) {
+                bwg = f.nwg;
+                bsw = swept;
+                *ty_out = ty;
+                *zc_out = zc;
+            }
+        }
+    }
+    return bwg > 0;
+}
+
+// The default on grids of 2^24 cells or more: the one-round tile of the
+// first width of the list that divides nx and has one (128, 80, 64, the
+// widths measured best, then the other multiples of 8 from 120 down to 72;
+// FP64: 64, 32, then 56, 48, 40).  On the grids measured (512x512x1024 FP32
+// and FP64, 256x256x512, the 512x512x128 z-slab, the 240x240x520 grid) it
+// is the fastest tile or within 1-2% of it, and on 208x208x416 and
+// 224x224x448 (104- and 112-wide tiles) 19% and 30% faster than the cost
+// model's tile; below 2^24 cells (128x128x256: no faster than the one-pass
+// step) it is not used.  False where no such tile exists.
 bool one_round_two_step(tdse_ctx* h) {
     const tdse_desc& d = h->d;
     if (d.nx * d.ny * d.nz < (int64_t)1 << 24) return false;
@@ -1120,35 +1144,15 @@ bool one_round_two_step(tdse_ctx* h) {
     const int w32[9] = {128, 80, 64, 120, 112, 104, 96, 88, 72}, w64[5] = {64, 32, 56, 48, 40};
     for (int iw = 0; iw < (f64 ? 5 : 9); ++iw) {
         const int tx = f64 ? w64[iw] : w32[iw];
-        if (d.nx % tx != 0) continue;
-        const Fused2Dims tall = fused2_dims(h, tx, 1, (int)std::min<int64_t>(d.nz, 32), 1024, 0);
-        if (!tall.ok) continue;
-        long bwg = 0;
-        double bsw = 0.0;
-        int bty = 0, bzc = 0;
-        for (int ty = tall.ty; ty >= 16; --ty) {
-            for (int nzc = 1; nzc <= 16; ++nzc) {
-                const int zc = (int)((d.nz + nzc - 1) / nzc);
-                if (zc < 32 && nzc > 1) break;
-                const Fused2Dims f = fused2_dims(h, tx, 1, zc, 1024, ty);
-                if (!f.ok || f.ty != ty || f.nwg > h->cus || 10L * f.nwg < 9L * h->cus) continue;
-                const double swept = (double)f.ntx * f.ex * f.nty * f.ey * f.nzc * (zc + 6);
-                if (f.nwg > bwg || (f.nwg == bwg && swept < bsw)) {
-                    bwg = f.nwg;
-                    bsw = swept;
-                    bty = ty;
-                    bzc = zc;
-                }
-            }
-        }
-        if (bwg == 0) continue;
+        int ty = 0, zc = 0;
+        if (d.nx % tx != 0 || !one_round_tile(h, tx, &ty, &zc)) continue;
         h->two = true;
         h->t2x = tx;
         h->t2m = 1;
         h->t2t = 1024;
         h->t2pf = true;
-        h->t2zc = bzc;
-        h->t2ty = bty;
+        h->t2zc = zc;
+        h->t2ty = ty;
         return true;
     }
     return false;
@@ -2718,41 +2722,21 @@ tdse_status tdse_autotune(tdse_handle h, int32_t steps, int32_t flags, tdse_tile
             t.two_step_prefetch = 1;
             cands.push_back(t);
         }
-        // one-round tiles: 1024 threads, a width from the list, and the
-        // height and z chunk whose workgroups fill one round of the CUs
-        // (one workgroup per CU) most fully, at least 90%, then the
-        // shortest (the same tiles with no ragged last row): all
-        // workgroups march the same planes together and the
-        // L2 serves the rims the neighbouring tiles re-read (the fastest
-        // form measured on the benchmark grids)
+        // the one-round tile (one_round_tile) of each of a few widths
         const bool f64 = h->d.precision == TDSE_F64;
         const int w1[3] = {128, 80, 64}, w2[2] = {64, 32};
         for (int iw = 0; iw < (f64 ? 2 : 3); ++iw) {
             const int tx = f64 ? w2[iw] : w1[iw];
-            const Fused2Dims tall = fused2_dims(h, tx, 1, (int)h->d.nz, 1024, 0);
-            if (!tall.ok) continue;
-            int bty = 0, bzc = 0, bwg = 0;
-            for (int ty = tall.ty; ty >= 4; --ty) {
-                for (int nzc = 1; nzc <= 8; ++nzc) {
-                    const int zc = (int)((h->d.nz + nzc - 1) / nzc);
-                    const Fused2Dims f = fused2_dims(h, tx, 1, zc, 1024, ty);
-                    if (!f.ok || f.ty != ty || f.nwg > h->cus || 10L * f.nwg < 9L * h->cus) continue;
-                    if (f.nwg >= bwg) {
-                        bwg = f.nwg;
-                        bty = ty;
-                        bzc = zc;
-                    }
-                }
-            }
-            if (bwg == 0) continue;
+            int ty = 0, zc = 0;
+            if (!one_round_tile(h, tx, &ty, &zc)) continue;
             tdse_tile t = base;
             t.fused = 1;
             t.two_step = 1;
             t.two_step_tx = tx;
             t.two_step_rows = 1;
             t.two_step_threads = 1024;
-            t.two_step_zc = bzc;
-            t.two_step_ty = bty;
+            t.two_step_zc = zc;
+            t.two_step_ty = ty;
             t.two_step_prefetch = 1;
             cands.push_back(t);
         }

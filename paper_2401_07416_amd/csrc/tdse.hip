@@ -1099,27 +1099,29 @@ double fused2_cost(const tdse_ctx* h, const Fused2Dims& f, int m, int zc) {
 
 // The one-round two-step tile of interior width tx: 1024 threads, one row
 // each, a height of at least 16 rows and z chunks of at least 32 planes (up
-// to 16 of them) whose workgroups fill 90-100% of one round of the CUs; the
-// fullest round, then the fewest cells swept (rims and chunk starts
-// included).  All workgroups then march the same planes at about the same
-// time and the L2 serves the rims that neighbouring tiles re-read; wide
-// tiles read long contiguous rows.  False if no such tile exists.
+// to 16 of them) whose workgroups fill 90-100% of one round of the CUs.
+// In one round the time is that of one workgroup, so the tile taken is the
+// one whose workgroup sweeps the fewest cells, (zc + 6) planes of its
+// extended tile (ex x ey), then the one with more workgroups.  All
+// workgroups then march the same planes at about the same time and the L2
+// serves the rims that neighbouring tiles re-read; wide tiles read long
+// contiguous rows.  False if no such tile exists.
 bool one_round_tile(tdse_ctx* h, int tx, int* ty_out, int* zc_out) {
     const tdse_desc& d = h->d;
     const Fused2Dims tall = fused2_dims(h, tx, 1, (int)std::min<int64_t>(d.nz, 32), 1024, 0);
     if (!tall.ok) return false;
     long bwg = 0;
-    double bsw = 0.0;
+    double bper = 0.0;
     for (int ty = tall.ty; ty >= 16; --ty) {
         for (int nzc = 1; nzc <= 16; ++nzc) {
             const int zc = (int)((d.nz + nzc - 1) / nzc);
             if (zc < 32 && nzc > 1) break;
             const Fused2Dims f = fused2_dims(h, tx, 1, zc, 1024, ty);
             if (!f.ok || f.ty != ty || f.nwg > h->cus || 10L * f.nwg < 9L * h->cus) continue;
-            const double swept = (double)f.ntx * f.ex * f.nty * f.ey * f.nzc * (zc + 6);
-            if (f.nwg > bwg || (f.nwg == bwg && swept < bsw)) {
+            const double per = (double)(zc + 6) * f.ex * f.ey;
+            if (bwg == 0 || per < bper || (per == bper && f.nwg > bwg)) {
                 bwg = f.nwg;
-                bsw = swept;
+                bper = per;
                 *ty_out = ty;
                 *zc_out = zc;
             }
@@ -1133,10 +1135,11 @@ bool one_round_tile(tdse_ctx* h, int tx, int* ty_out, int* zc_out) {
 // widths measured best, then the other multiples of 8 from 120 down to 72;
 // FP64: 64, 32, then 56, 48, 40).  On the grids measured (512x512x1024 FP32
 // and FP64, 256x256x512, the 512x512x128 z-slab, the 240x240x520 grid) it
-// is the fastest tile or within 1-2% of it, and on 208x208x416 and
-// 224x224x448 (104- and 112-wide tiles) 19% and 30% faster than the cost
-// model's tile; below 2^24 cells (128x128x256: no faster than the one-pass
-// step) it is not used.  False where no such tile exists.
+// is the fastest tile or within 1-2% of it, and on 208x208x416,
+// 224x224x448, 320x320x640, 384x384x768 and 1024x1024x256 5-30% faster
+// than the cost model's tile; below 2^24 cells (128x128x256: no faster
+// than the one-pass step) it is not used.  False where no such tile
+// exists.
 bool one_round_two_step(tdse_ctx* h) {
     const tdse_desc& d = h->d;
     if (d.nx * d.ny * d.nz < (int64_t)1 << 24) return false;

@@ -223,12 +223,14 @@ def test_autotuner_cache_round_trip(tmp_path, monkeypatch):
     ("f64", (256, 256, 512), (64, 16, 128)),
     ("f32", (208, 208, 416), (104, 19, 38)),
     ("f32", (224, 224, 448), (112, 25, 32)),
+    ("f32", (320, 320, 640), (80, 36, 92)),
 ])
 def test_default_tile_on_large_grids_fills_one_round(prec, shape, want):
     """The library's default two-step tile on grids of 2^24 cells or more:
-    1024 threads, the first width of its list that divides nx, and the height and z
-    chunk whose workgroups fill one round of the CUs most fully (on the
-    MI355X's 256), the fewest cells swept among those."""
+    1024 threads, the first width of its list that divides nx, and, among
+    the heights and z chunks whose workgroups fill 90-100% of one round of
+    the CUs (on the MI355X's 256), the one whose workgroup sweeps the fewest
+    cells."""
     props = torch.cuda.get_device_properties(0)
     if props.multi_processor_count != 256:
         pytest.skip("the expected tiles are those of a 256-CU device")

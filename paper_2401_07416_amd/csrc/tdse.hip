@@ -1136,10 +1136,10 @@ bool one_round_tile(tdse_ctx* h, int tx, int* ty_out, int* zc_out) {
 // FP64: 64, 32, then 56, 48, 40).  On the grids measured (512x512x1024 FP32
 // and FP64, 256x256x512, the 512x512x128 z-slab, the 240x240x520 grid) it
 // is the fastest tile or within 1-2% of it, and on 208x208x416,
-// 224x224x448, 320x320x640, 384x384x768 and 1024x1024x256 5-30% faster
-// than the cost model's tile; below 2^24 cells (128x128x256: no faster
-// than the one-pass step) it is not used.  False where no such tile
-// exists.
+// 224x224x448, 320x320x640 and 384x384x768 4-30% faster than the cost
+// model's tiles; below 2^24 cells (128x128x256: no faster than the
+// one-pass step) it is not used.  False where no such tile exists (e.g.
+// 1024x1024x256, whose planes need more than one round of tiles).
 bool one_round_two_step(tdse_ctx* h) {
     const tdse_desc& d = h->d;
     if (d.nx * d.ny * d.nz < (int64_t)1 << 24) return false;

@@ -454,21 +454,24 @@ __global__ __launch_bounds__(256) void interp_potential_kernel(InterpArgs a, con
 }
 
 // The same with the z blend of the workgroup's mesh plane done once per
-// table sample: Z[b][a] = (1 - tz) T[c0][b][a] + tz T[c1][b][a] staged in LDS
-// (rows of ux + 1 samples, the last a copy of the first, so the upper x
-// sample is always the next one) when it fits.  A cell then costs four LDS
-// reads and the x and y blends (9 FP64 operations instead of 21).  The same
-// trilinear value, blended z first instead of x first: it differs from the
-// x-first order by FP64 rounding only.
+// table sample, Z[b][a] = (1 - tz) T[c0][b][a] + tz T[c1][b][a], and then
+// the y blend of each of its rows once per sample of the row,
+// Y[r][a] = (1 - ty_r) Z[b0_r][a] + ty_r Z[b1_r][a], both staged in LDS
+// when they fit (rows of ux + 1 samples, the last a copy of the first, so
+// the upper x sample is always the next one).  A cell then costs one paired
+// LDS read and the x blend (3 FP64 operations instead of 21).  The same
+// trilinear value, blended z, y, x instead of x, y, z: it differs from that
+// order by FP64 rounding only.
 template <typename T>
 __global__ __launch_bounds__(256) void interp_potential_lds_kernel(InterpArgs a, const AxisW* ax, int nseg,
                                                                    int rows, T* V) {
-    extern __shared__ double zl[];   // [uy][ux + 1]
+    extern __shared__ double zl[];   // Z: [uy][ux + 1], then Y: [rows][ux + 1]
     const int seg = blockIdx.x % nseg;
     const int j0 = (blockIdx.x / nseg) * rows;
     const int k = blockIdx.y;
     const int ux1 = a.ux + 1;
     const int per = a.uy * ux1;
+    const int j1 = min(j0 + rows, a.ny);
     const AxisW wz = ax[a.nx + a.ny + k];
     const long plane = (long)a.uy * a.ux;
     const double* t0 = a.table + (long)wz.a0 * plane;
@@ -479,21 +482,23 @@ __global__ __launch_bounds__(256) void interp_potential_lds_kernel(InterpArgs a,
         zl[t] = (1.0 - wz.t) * t0[src] + wz.t * t1[src];
     }
     __syncthreads();
+    double* yl = zl + per;
+    const int ny1 = (j1 - j0) * ux1;
+    for (int t = threadIdx.x; t < ny1; t += 256) {
+        const int r = t / ux1, q = t - r * ux1;
+        const AxisW wy = ax[a.nx + j0 + r];
+        yl[t] = (1.0 - wy.t) * zl[wy.a0 * ux1 + q] + wy.t * zl[wy.a1 * ux1 + q];
+    }
+    __syncthreads();
     const int i = seg * 256 + threadIdx.x;
-    if (i >= a.nx) return;   // after the only barrier
+    if (i >= a.nx) return;   // after the last barrier
     const AxisW wx = ax[i];
     const double tx = wx.t, sx = 1.0 - tx;
-    const double* zx = zl + wx.a0;
+    const double* yx = yl + wx.a0;
     T* out = V + ((long)k * a.ny) * a.nx + i;
-    const int j1 = min(j0 + rows, a.ny);
     for (int j = j0; j < j1; ++j) {
-        const AxisW wy = ax[a.nx + j];
-        const double ty = wy.t;
-        const double* z0 = zx + wy.a0 * ux1;
-        const double* z1 = zx + wy.a1 * ux1;
-        const double b0 = sx * z0[0] + tx * z0[1];
-        const double b1 = sx * z1[0] + tx * z1[1];
-        __builtin_nontemporal_store((T)((1.0 - ty) * b0 + ty * b1), out + (long)j * a.nx);
+        const double* y = yx + (j - j0) * ux1;
+        __builtin_nontemporal_store((T)(sx * y[0] + tx * y[1]), out + (long)j * a.nx);
     }
 }
 

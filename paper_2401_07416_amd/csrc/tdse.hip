@@ -2034,14 +2034,18 @@ tdse_status tdse_interpolate_potential(tdse_handle h, const double* table, int32
     hipLaunchKernelGGL(interp_axes_kernel, dim3((unsigned)std::min<long>((nax + 255) / 256, 4096)),
                        dim3(256), 0, h->stream, a, ax);
     HIPCHK(h, hipGetLastError());
-    // the z-blended table plane of a mesh plane in LDS when it fits (48
-    // KB); rows of one plane per workgroup: 64 with the staging (it is paid
-    // once per workgroup), 16 without, fewer on small grids
-    const size_t lds = (size_t)uy * (ux + 1) * sizeof(double);
-    const bool staged = lds <= 48 * 1024;
+    // the z-blended table plane of a mesh plane and the y-blended rows of
+    // the workgroup in LDS when they fit (48 KB); rows of one plane per
+    // workgroup: 64 with the staging (it is paid once per workgroup), 16
+    // without, fewer on small grids
     const int nseg = (int)((d.nx + 255) / 256);
-    int rows = staged ? 64 : 16;
+    int rows = 64;
+    const size_t lds_z = (size_t)uy * (ux + 1) * sizeof(double);
+    const bool staged = lds_z + (size_t)rows * (ux + 1) * sizeof(double) <= 48 * 1024;
+    if (!staged) rows = 16;
     while (rows > 1 && (long)nseg * ((d.ny + rows - 1) / rows) * d.nz < 4096) rows /= 2;
+    // the z-blended plane, then the y-blended rows of the workgroup
+    const size_t lds = lds_z + (size_t)rows * (ux + 1) * sizeof(double);
     const long ngx = (long)nseg * ((d.ny + rows - 1) / rows);
     if (ngx >= (1L << 31)) return fail(h, TDSE_ERR_UNSUPPORTED, "grid too large for the interpolation launch");
     const dim3 grid((unsigned)ngx, (unsigned)d.nz);

@@ -293,8 +293,8 @@ void default_tile(tdse_ctx* h) {
     h->zc = (int)std::min<int64_t>(zc, d.nz);
 }
 
-// Default one-pass tile: the largest band that fits the LDS limit, z chunks
-// sized for about 1500 workgroups.
+// Default one-pass tile: the first band shape and z chunk, longest chunks
+// first, whose workgroups keep the CUs busy.
 void default_fused_tile(tdse_ctx* h);
 
 struct TileDims {
@@ -1041,16 +1041,18 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
 void default_fused_tile(tdse_ctx* h) {
     // first (threads per workgroup, rows per thread, z chunk) in order of
     // preference that keeps at least ~8 waves per CU busy; z chunks of 8
-    // only if nothing else does; else the shape with the most threads
+    // only if nothing else does, then chunks of 4 and 2 (on small grids the
+    // z march of each workgroup, not HBM, sets the time, and short chunks
+    // spread it over more workgroups); else the shape with the most threads
     const tdse_desc& d = h->d;
     const long target = 256L * 512;
     long best = -1;
     int bft = 256, bm = 3, bzc = (int)std::min<int64_t>(64, d.nz);
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < 3; ++pass) {
         for (int ft : {256, 128, 64}) {
             for (int m : {3, 4, 2}) {
-                for (int zc0 : {64, 32, 16, 8}) {
-                    if ((pass == 0) != (zc0 >= 16)) continue;
+                for (int zc0 : {64, 32, 16, 8, 4, 2}) {
+                    if (pass != (zc0 >= 16 ? 0 : zc0 == 8 ? 1 : 2)) continue;
                     const int zc = (int)std::min<int64_t>(zc0, d.nz);
                     const FusedDims f = fused_dims(h, m, zc, ft);
                     if (!f.ok) continue;

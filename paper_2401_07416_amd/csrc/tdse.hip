@@ -1049,42 +1049,57 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
 
 void default_fused_tile(tdse_ctx* h) {
     // first (threads per workgroup, rows per thread, z chunk) in order of
-    // preference that keeps at least ~8 waves per CU busy; z chunks of 8
-    // only if nothing else does, then chunks of 4 and 2 (on small grids the
-    // z march of each workgroup, not HBM, sets the time, and short chunks
-    // spread it over more workgroups); else the shape with the most threads
+    // preference that keeps at least ~8 waves per CU busy, z chunks of 8
+    // only if nothing longer does
     const tdse_desc& d = h->d;
     const long target = 256L * 512;
-    long best = -1;
-    int bft = 256, bm = 3, bzc = (int)std::min<int64_t>(64, d.nz);
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
         for (int ft : {256, 128, 64}) {
             for (int m : {3, 4, 2}) {
-                for (int zc0 : {64, 32, 16, 8, 4, 2}) {
-                    if (pass != (zc0 >= 16 ? 0 : zc0 == 8 ? 1 : 2)) continue;
+                for (int zc0 : {64, 32, 16, 8}) {
+                    if ((pass == 0) != (zc0 >= 16)) continue;
                     const int zc = (int)std::min<int64_t>(zc0, d.nz);
                     const FusedDims f = fused_dims(h, m, zc, ft);
-                    if (!f.ok) continue;
-                    const long th = (long)f.nwg * ft;
-                    if (th >= target) {
+                    if (f.ok && (long)f.nwg * ft >= target) {
                         h->ft = ft;
                         h->fm = m;
                         h->fzc = zc;
                         return;
                     }
-                    if (th > best) {
-                        best = th;
-                        bft = ft;
-                        bm = m;
-                        bzc = zc;
-                    }
                 }
             }
         }
     }
-    h->ft = bft;
-    h->fm = bm;
-    h->fzc = bzc;
+    // small grids: the z march of each workgroup, not HBM, sets the time,
+    // so the chunks go to 2 planes, or 1 below two workgroups per CU; the
+    // widest band that fits (narrow bands reload most of their rows as
+    // halo), with the most workgroups when none reaches two per CU
+    h->ft = 256;
+    h->fm = 3;
+    h->fzc = (int)std::min<int64_t>(64, d.nz);
+    for (int ft : {256, 128, 64}) {
+        long most = -1;
+        for (int zc0 : {2, 1}) {
+            for (int m : {3, 4, 2}) {
+                const int zc = (int)std::min<int64_t>(zc0, d.nz);
+                const FusedDims f = fused_dims(h, m, zc, ft);
+                if (!f.ok) continue;
+                if ((long)f.nwg >= 2L * h->cus) {
+                    h->ft = ft;
+                    h->fm = m;
+                    h->fzc = zc;
+                    return;
+                }
+                if (f.nwg > most) {
+                    most = f.nwg;
+                    h->ft = ft;
+                    h->fm = m;
+                    h->fzc = zc;
+                }
+            }
+        }
+        if (most >= 0) return;
+    }
 }
 
 // Workgroups of a two-step tile one CU holds at once: LDS, and the

@@ -258,13 +258,15 @@ def test_default_tile_on_small_grids_keeps_the_cost_model():
 @pytest.mark.gpu
 def test_default_one_pass_chunks_shorten_on_small_grids():
     """Where no chunk of 8 planes or more gives about 8 waves per CU, the
-    one-pass default takes 4- or 2-plane chunks (the z march of each
-    workgroup sets the time on a cache-resident grid); grids that reach the
-    occupancy with long chunks keep them."""
+    one-pass default takes the widest band in 2- or 1-plane chunks (the z
+    march of each workgroup sets the time on a cache-resident grid); grids
+    that reach the occupancy with long chunks keep them."""
     for n, nz, prec, short in ((32, 32, "f64", True), (64, 64, "f32", True), (64, 64, "f64", True),
                                (64, 512, "f32", True), (128, 128, "f64", False), (256, 256, "f32", False)):
         s = tdse.Sim(tdse.make_desc(n, n, nz, 0.2, 0.2, 0.2, precision=prec))
         t = s.get_tile()
         say(f"default one-pass tile {n}x{n}x{nz} {prec}", t.as_dict())
-        assert (t.fused_zc <= 4) == short
+        assert (t.fused_zc <= 2) == short
+        if short:
+            assert t.fused_threads == 256
         s.close()

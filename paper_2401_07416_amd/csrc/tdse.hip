@@ -1047,11 +1047,43 @@ tdse_status run_adjoint(tdse_ctx* h, const T* rho_bar, double* gV64, T* gR0, T* 
 }
 
 
+// Below 2^24 cells: the widest band that fits (256 threads first), two
+// rows per thread (the lowest of 2, 3, 4 whose band is at least 4 rows
+// tall; none: the occupancy rule below), and the longest z
+// chunk of 64 planes down to 1 that gives two workgroups per CU, else
+// 1-plane chunks.  Measured against the occupancy rule below it: 160^3
+// FP32 91 -> 189, 192^3 FP32 151 -> 222, 200^3 FP32 149 -> 229, 128^3 FP64
+// 84 -> 95 Gcell-steps/s; 3 rows per thread at the same chunk was slower
+// on all of these but 160^3 FP64 (6% faster there).
+bool model_fused_tile(tdse_ctx* h) {
+    const tdse_desc& d = h->d;
+    const long want = 2L * h->cus;
+    for (int ft : {256, 128, 64}) {
+        for (int m : {2, 3, 4}) {
+            const FusedDims f1 = fused_dims(h, m, 1, ft);
+            if (!f1.ok || f1.ty < 4) continue;
+            h->ft = ft;
+            h->fm = m;
+            h->fzc = 1;
+            for (int zc0 : {64, 32, 16, 8, 4, 2}) {
+                const int zc = (int)std::min<int64_t>(zc0, d.nz);
+                if ((long)fused_dims(h, m, zc, ft).nwg >= want) {
+                    h->fzc = zc;
+                    break;
+                }
+            }
+            return true;
+        }
+    }
+    return false;
+}
+
 void default_fused_tile(tdse_ctx* h) {
     // first (threads per workgroup, rows per thread, z chunk) in order of
     // preference that keeps at least ~8 waves per CU busy, z chunks of 8
     // only if nothing longer does
     const tdse_desc& d = h->d;
+    if (d.nx * d.ny * d.nz < (int64_t(1) << 24) && model_fused_tile(h)) return;
     const long target = 256L * 512;
     for (int pass = 0; pass < 2; ++pass) {
         for (int ft : {256, 128, 64}) {
